@@ -1,0 +1,106 @@
+"""Closed forms the paper fixes for constant coefficients (test helpers).
+
+* Substitution rules, Sect. 2.1 (Eqs. substE, substp, substm): a discrete time
+  difference becomes -(2i/dt) sin(w dt/2), a spatial one (2i/d_j) sin(k_j d_j/2),
+  the time average cos(w dt/2).
+* Dispersion, Eq. (pwdsip): w = +-(2/dt) arcsin X,
+  X^2 = (m^2 + |P|^2) / (m^2 + (2/dt)^2), with P_j = (2/d_j) sin(k_j d_j/2).
+  Sect. 3 states the same for (2+1)D; its printed denominator is garbled and is
+  read as m^2 + (2/dt)^2 like the 3D one.
+* Eigenkets psi^(1..4) after Eq. (pwdsip): the continuum spinors with E -> E(w),
+  p -> P, m -> m cos(w dt/2).
+* Plane waves on the lattice, Eq. (planeonlattice): every amplitude carries
+  exp(i k.x - i w t) at its own physical position and time sheet.
+
+hbar = c = 1 throughout.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+OFF3 = [(0.0, 0.0, 0.0), (0.5, 0.5, 0.0), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5),
+        (0.0, 0.0, 0.5), (0.5, 0.5, 0.5), (0.5, 0.0, 0.0), (0.0, 0.5, 0.0)]
+OFF2 = [(0.0, 0.0), (0.5, 0.5), (0.5, 0.0), (0.0, 0.5)]
+
+
+def lattice_momentum(k, d=1.0):
+    return 2.0 / d * np.sin(np.asarray(k, np.float64) * d / 2.0)
+
+
+def X_of(P2, m, dt):
+    return np.sqrt((m * m + P2) / (m * m + (2.0 / dt) ** 2))
+
+
+def omega(k, m, dt, d=(1.0, 1.0, 1.0)):
+    """Positive branch of Eq. (pwdsip)."""
+    P = [lattice_momentum(kj, dj) for kj, dj in zip(k, d)]
+    P2 = sum(p * p for p in P)
+    return 2.0 / dt * np.arcsin(X_of(P2, m, dt))
+
+
+def eigenket3(k, m, dt, branch, d=(1.0, 1.0, 1.0)):
+    """(w, [A, B, C, D]) of psi^(branch), branch in 1..4; 1,2 positive energy."""
+    Px, Py, Pz = [lattice_momentum(kj, dj) for kj, dj in zip(k, d)]
+    X = X_of(Px * Px + Py * Py + Pz * Pz, m, dt)
+    E = 2.0 / dt * X                       # |E(w)|
+    mk = m * np.sqrt(1.0 - X * X)          # m(w) = m cos(w dt / 2)
+    den = E + mk
+    w = 2.0 / dt * np.arcsin(X)
+    if branch == 1:
+        return w, [1.0, 0.0, Pz / den, (Px + 1j * Py) / den]
+    if branch == 2:
+        return w, [0.0, 1.0, (Px - 1j * Py) / den, -Pz / den]
+    if branch == 3:
+        return -w, [-Pz / den, -(Px + 1j * Py) / den, 1.0, 0.0]
+    if branch == 4:
+        return -w, [-(Px - 1j * Py) / den, Pz / den, 0.0, 1.0]
+    raise ValueError(branch)
+
+
+def eigenket2(k, m, dt, branch, d=(1.0, 1.0)):
+    """(w, [u, v]); branch 1 positive, 2 negative energy."""
+    Px, Py = [lattice_momentum(kj, dj) for kj, dj in zip(k, d)]
+    X = X_of(Px * Px + Py * Py, m, dt)
+    E = 2.0 / dt * X
+    mk = m * np.sqrt(1.0 - X * X)
+    w = 2.0 / dt * np.arcsin(X)
+    if branch == 1:
+        return w, [1.0, (Px + 1j * Py) / (E + mk)]
+    return -w, [-(Px - 1j * Py) / (E + mk), 1.0]
+
+
+def plane_wave3(shape, k, amps, w, dt, t_shift=0.0):
+    """State arrays (A0..D1) of a lattice plane wave: A,B on sheet -1/2, C,D on 0
+    (shifted by t_shift), cell-unit spacing, shape = (nz, ny, nx)."""
+    nz, ny, nx = shape
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for a in range(8):
+        ox, oy, oz = OFF3[a]
+        t = (-0.5 * dt if a < 4 else 0.0) + t_shift
+        ph = k[0] * (ii + ox) + k[1] * (jj + oy) + k[2] * (kk + oz) - w * t
+        out.append(np.ascontiguousarray(amps[a // 2] * np.exp(1j * ph), dtype=np.complex128))
+    return out
+
+
+def plane_wave2(shape, k, amps, w, dt, t_shift=0.0):
+    ny, nx = shape
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for a in range(4):
+        ox, oy = OFF2[a]
+        t = (-0.5 * dt if a < 2 else 0.0) + t_shift
+        ph = k[0] * (ii + ox) + k[1] * (jj + oy) - w * t
+        out.append(np.ascontiguousarray(amps[a // 2] * np.exp(1j * ph), dtype=np.complex128))
+    return out
+
+
+def growth_factor(X):
+    """|lambda| per step of the growing mode when X > 1: w dt/2 = pi/2 - i acosh X."""
+    return float((X + np.sqrt(X * X - 1.0)) ** 2)
+
+
+def rel_l2(a_list, b_list):
+    num = sum(float(np.sum(np.abs(np.asarray(a) - np.asarray(b)) ** 2)) for a, b in zip(a_list, b_list))
+    den = sum(float(np.sum(np.abs(np.asarray(b)) ** 2)) for b in b_list)
+    return np.sqrt(num / den)

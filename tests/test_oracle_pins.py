@@ -1,0 +1,502 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks.  None of them re-types the oracle's own
+formula: they use the closed-form dispersion and eigenkets, an independently
+assembled dense one-step matrix, proven invariants and inequalities, and
+brute-force finite differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.dense import Dense2, Dense3
+from closed_form import (eigenket2, eigenket3, growth_factor, lattice_momentum, omega,
+                         plane_wave2, plane_wave3, rel_l2)
+
+DT3 = 0.9 / np.sqrt(3.0)
+DT2 = 0.9 / np.sqrt(2.0)
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def rand_state(shape, count, g):
+    return [np.ascontiguousarray(g.standard_normal(shape) + 1j * g.standard_normal(shape)) for _ in range(count)]
+
+
+def rand_theta(shape, count, g, scale=0.4):
+    return [np.ascontiguousarray(scale * g.standard_normal(shape)) for _ in range(count)]
+
+
+# --------------------------------------------------------------------------
+# Plane waves: Eq. (planeonlattice) with eigenkets psi^(1..4) and w from
+# Eq. (pwdsip) evolve as exp(-i w n dt) exactly (Sect. 2.1; Sect. 3 for 2D).
+# k includes k_y != 0 and extended-zone modes (k_x beyond 2*pi: the
+# sublattice-staggered copies of the fcr sublattices).
+# Tolerance: every step rounds each amplitude a handful of times (about four
+# ulps of relative error, coherent for an eigenmode), so the bound is
+# 1e-15 per step: 2e-13 after 200 steps.
+# --------------------------------------------------------------------------
+PW_TOL_PER_STEP = 1e-15
+K3 = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (3, 2, 7), (5, -3, 2), (9, 1, 3), (4, 3, 5), (12, 5, 1)]
+
+
+@pytest.mark.parametrize("branch", [1, 2, 3, 4])
+@pytest.mark.parametrize("m", [0.0, 0.5])
+def test_plane_wave_3d(branch, m):
+    nx, ny, nz = 8, 6, 10
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    th = lat.theta(m)
+    for n in K3:
+        k = (2 * np.pi * n[0] / nx, 2 * np.pi * n[1] / ny, 2 * np.pi * n[2] / nz)
+        w, amps = eigenket3(k, m, DT3, branch)
+        f = plane_wave3(lat.shape, k, amps, w, DT3)
+        g = [a.copy() for a in f]
+        lat.step(g, th, 200)
+        expect = plane_wave3(lat.shape, k, amps, w, DT3, t_shift=200 * DT3)
+        assert rel_l2(g, expect) < 200 * PW_TOL_PER_STEP, (n, branch, m)
+
+
+K2 = [(1, 0), (0, 1), (3, 5), (17, -29), (6, 0), (64, 64), (70, 3), (1, 130)]
+
+
+@pytest.mark.parametrize("branch", [1, 2])
+@pytest.mark.parametrize("m", [0.0, 0.7])
+def test_plane_wave_2d(branch, m):
+    nx = ny = 128
+    lat = oracle.Lattice2(nx, ny, DT2)
+    th = lat.theta(m)
+    for n in K2:
+        k = (2 * np.pi * n[0] / nx, 2 * np.pi * n[1] / ny)
+        w, amps = eigenket2(k, m, DT2, branch)
+        f = plane_wave2(lat.shape, k, amps, w, DT2)
+        g = [a.copy() for a in f]
+        lat.step(g, th, 200)
+        expect = plane_wave2(lat.shape, k, amps, w, DT2, t_shift=200 * DT2)
+        assert rel_l2(g, expect) < 200 * PW_TOL_PER_STEP, (n, branch, m)
+
+
+def test_plane_wave_anisotropic_spacing():
+    """Unequal d_j: P_j = (2/d_j) sin(k_j d_j / 2), r_j = dt/d_j (Eq. substp, Sect. 2.2)."""
+    nx, ny, nz = 6, 8, 4
+    d = (1.0, 0.7, 1.3)
+    dt = 0.8 / np.sqrt(sum(1.0 / dj ** 2 for dj in d))
+    lat = oracle.Lattice3(nx, ny, nz, dt, *d)
+    m = 0.3
+    n = (2, 3, 1)
+    k = tuple(2 * np.pi * n[q] / ((nx, ny, nz)[q] * d[q]) for q in range(3))
+    w, amps = eigenket3(k, m, dt, 1, d)
+    # positions are in cell units; the phase per cell is k_j * d_j
+    kc = tuple(k[q] * d[q] for q in range(3))
+    f = plane_wave3(lat.shape, kc, amps, w, dt)
+    lat.step(f, lat.theta(m), 100)
+    expect = plane_wave3(lat.shape, kc, amps, w, dt, t_shift=100 * dt)
+    assert rel_l2(f, expect) < 100 * PW_TOL_PER_STEP
+
+
+def test_single_cone_in_first_zone():
+    """Sect. 2.1: for m = 0, w(k) vanishes only at k = 0 within (-pi, pi]^3 and is
+    largest at the zone corner; the dispersion is monotonic along each axis."""
+    ks = np.linspace(-np.pi, np.pi, 41)[1:]
+    KX, KY, KZ = np.meshgrid(ks, ks, ks, indexing="ij")
+    w = omega((KX, KY, KZ), 0.0, DT3)
+    zero = np.argwhere(np.abs(w) < 1e-12)
+    assert len(zero) == 1 and np.allclose(ks[zero[0]], 0.0)
+    assert np.isclose(w.max(), omega((np.pi,) * 3, 0.0, DT3))
+    axis = omega((ks[ks >= 0], 0 * ks[ks >= 0], 0 * ks[ks >= 0]), 0.0, DT3)
+    assert np.all(np.diff(axis) > 0)
+
+
+# --------------------------------------------------------------------------
+# Dense matrix assembled independently in numpy (oracle/dense.py).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(2, 2, 4), (3, 2, 2), (4, 4, 4)])
+def test_dense_matches_oracle_3d(shape):
+    nx, ny, nz = shape
+    g = rng(1)
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    D = Dense3(nx, ny, nz, DT3)
+    f = rand_state(lat.shape, 8, g)
+    x = D.pack(f)
+    for _ in range(4):                         # time-dependent theta
+        th = rand_theta(lat.shape, 8, g)
+        lat.step(f, th)
+        x = D.step_matrix(D.pack(th).real) @ x
+    assert rel_l2([D.pack(f)], [x]) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (5, 3), (2, 6)])
+def test_dense_matches_oracle_2d(shape):
+    nx, ny = shape
+    g = rng(2)
+    lat = oracle.Lattice2(nx, ny, DT2)
+    D = Dense2(nx, ny, DT2)
+    f = rand_state(lat.shape, 4, g)
+    x = D.pack(f)
+    for _ in range(4):
+        th = rand_theta(lat.shape, 4, g)
+        lat.step(f, th)
+        x = D.step_matrix(D.pack(th).real) @ x
+    assert rel_l2([D.pack(f)], [x]) < 1e-13
+
+
+def test_reverse_is_inverse_dense():
+    """The reversed step (relations of Eqs. ss3, ss4 then ss1, ss2 solved for the
+    old amplitudes) is the inverse of the dense one-step matrix."""
+    g = rng(3)
+    lat = oracle.Lattice3(2, 3, 4, DT3)
+    D = Dense3(2, 3, 4, DT3)
+    th = rand_theta(lat.shape, 8, g)
+    f = rand_state(lat.shape, 8, g)
+    x = np.linalg.solve(D.step_matrix(D.pack(th).real), D.pack(f))
+    lat.reverse(f, th)
+    assert rel_l2([D.pack(f)], [x]) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gram_invariant_and_energy_form(dim):
+    """Lemmas of Sects. 2 and 3: E_r is conserved for arbitrary real, site- and
+    time-dependent m, V, i.e. M^H G M = G; and the oracle's reduction equals the
+    Hermitian form psi^H G psi (both of its E_r evaluations)."""
+    g = rng(4)
+    if dim == 3:
+        lat, D, cnt = oracle.Lattice3(2, 2, 4, DT3), Dense3(2, 2, 4, DT3), 8
+    else:
+        lat, D, cnt = oracle.Lattice2(4, 3, DT2), Dense2(4, 3, DT2), 4
+    th = rand_theta(lat.shape, cnt, g, 1.0)
+    M = D.step_matrix(D.pack(th).real)
+    G = D.gram()
+    assert np.abs(M.conj().T @ G @ M - G).max() < 1e-13
+    f = rand_state(lat.shape, cnt, g)
+    x = D.pack(f)
+    e_form = float(np.real(np.vdot(x, G @ x)))
+    e = lat.energy(f)
+    assert abs(e[0] - e_form) < 1e-12 * abs(e_form)
+    if dim == 3:
+        assert abs(e[1] - e_form) < 1e-12 * abs(e_form)
+    assert abs(e[-1] - float(np.vdot(x, x).real)) < 1e-12 * e[-1]
+
+
+def _extended_zone_phases(nx, ny, nz, m, dt):
+    """Closed-form eigen-phases w*dt of the one-step map for constant m, V = 0.
+    Distinct plane waves on the fcr sublattices: k_x, k_y in 2*pi*Z/N modulo
+    4*pi and modulo the reciprocal vector (2*pi, 2*pi); k_z in 2*pi*Z/N_z."""
+    out = []
+    for ix in range(2 * nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                k = (2 * np.pi * ix / nx, 2 * np.pi * iy / ny, 2 * np.pi * iz / nz)
+                out.append(omega(k, m, dt) * dt)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("m", [0.0, 0.6])
+def test_spectrum_3d(m):
+    """Eigenvalues of the one-step map are exp(-+i w(k) dt), w from Eq. (pwdsip),
+    each twice (spin) per distinct plane wave."""
+    nx, ny, nz = 2, 2, 4
+    D = Dense3(nx, ny, nz, DT3)
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    th = D.pack(lat.theta(m)).real
+    ev = np.linalg.eigvals(D.step_matrix(th))
+    assert np.allclose(np.abs(ev), 1.0, atol=1e-12)
+    got = np.sort(np.angle(ev))
+    ph = _extended_zone_phases(nx, ny, nz, m, DT3)
+    expect = np.sort(np.concatenate([ph, ph, -ph, -ph]))
+    assert got.shape == expect.shape
+    assert np.abs(got - expect).max() < 1e-10
+
+
+@pytest.mark.parametrize("m", [0.0, 0.4])
+def test_spectrum_2d(m):
+    nx, ny = 4, 6
+    D = Dense2(nx, ny, DT2)
+    lat = oracle.Lattice2(nx, ny, DT2)
+    ev = np.linalg.eigvals(D.step_matrix(D.pack(lat.theta(m)).real))
+    got = np.sort(np.angle(ev))
+    ph = []
+    for ix in range(2 * nx):
+        for iy in range(ny):
+            k = (2 * np.pi * ix / nx, 2 * np.pi * iy / ny)
+            P2 = lattice_momentum(k[0]) ** 2 + lattice_momentum(k[1]) ** 2
+            ph.append(2 * np.arcsin(np.sqrt((m * m + P2) / (m * m + (2 / DT2) ** 2))))
+    ph = np.array(ph)
+    expect = np.sort(np.concatenate([ph, -ph]))
+    assert np.abs(got - expect).max() < 1e-10
+
+
+def test_gram_min_eigenvalue():
+    """Derived from Eq. (EPM): G has eigenvalues 1 +- |rho(k)|/2, rho_j = dt P_j, so its
+    smallest is 1 - sqrt(sum r_j^2), reached at the zone corner (consistent with
+    the reality condition r_x^2 + r_y^2 + r_z^2 <= 1 of Sect. 2.2)."""
+    for dt, (nx, ny, nz) in [(DT3, (2, 2, 2)), (0.3, (4, 2, 2))]:
+        G = Dense3(nx, ny, nz, dt).gram()
+        lo = np.linalg.eigvalsh(G).min()
+        assert abs(lo - (1 - np.sqrt(3) * dt)) < 1e-12
+    G = Dense2(4, 4, DT2).gram()
+    assert abs(np.linalg.eigvalsh(G).min() - (1 - np.sqrt(2) * DT2)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Conservation (Lemmas of Sects. 2, 3) on larger random data with random
+# site- and time-dependent m, V.
+# --------------------------------------------------------------------------
+def test_conservation_3d_time_dependent():
+    g = rng(5)
+    lat = oracle.Lattice3(8, 6, 10, DT3)
+    f = rand_state(lat.shape, 8, g)
+    e0 = lat.energy(f)
+    assert abs(e0[0] - e0[1]) < 1e-13 * abs(e0[0])
+    for _ in range(100):
+        lat.step(f, rand_theta(lat.shape, 8, g, 0.5))
+    e1 = lat.energy(f)
+    assert abs(e1[0] - e0[0]) < 1e-13 * abs(e0[0])
+    assert abs(e1[1] - e1[0]) < 1e-13 * abs(e0[0])
+    assert abs(e1[2] - e0[2]) > 1e-6 * e0[2]     # the plain norm is not conserved
+
+
+def test_conservation_2d_and_printed_sign():
+    """Sect. 3, Eq. (E): the functional the update equations conserve carries
+    delta_+; the printed delta_- form is not conserved once k_y != 0."""
+    g = rng(6)
+    lat = oracle.Lattice2(16, 12, DT2)
+    f = rand_state(lat.shape, 4, g)
+    e0 = lat.energy(f)
+    for _ in range(200):
+        lat.step(f, rand_theta(lat.shape, 4, g, 0.5))
+    e1 = lat.energy(f)
+    assert abs(e1[0] - e0[0]) < 1e-13 * abs(e0[0])
+    assert abs(e1[1] - e0[1]) > 1e-4 * abs(e0[1])
+
+
+def test_energy_plane_wave_closed_form():
+    """E_r of a plane wave psi^(1) with A~ = 1 (from Eq. EPM and the substitution
+    rules): n_A [1 + |P|^2/(E+m k)^2 - (dt^2/2) E |P|^2/(E+m k)], and the plain
+    norm n_A [1 + |P|^2/(E+m k)^2], with n_A the number of A sites."""
+    nx, ny, nz = 8, 6, 10
+    for m in (0.0, 0.5):
+        lat = oracle.Lattice3(nx, ny, nz, DT3)
+        for n in [(1, 2, 3), (3, -1, 4), (9, 2, 1)]:
+            k = (2 * np.pi * n[0] / nx, 2 * np.pi * n[1] / ny, 2 * np.pi * n[2] / nz)
+            w, amps = eigenket3(k, m, DT3, 1)
+            f = plane_wave3(lat.shape, k, amps, w, DT3)
+            P2 = sum(lattice_momentum(kj) ** 2 for kj in k)
+            X = np.sin(w * DT3 / 2)
+            E = 2 / DT3 * X
+            den = E + m * np.sqrt(1 - X * X)
+            nA = 2 * nx * ny * nz
+            e = lat.energy(f)
+            assert abs(e[2] - nA * (1 + P2 / den ** 2)) < 1e-11 * e[2]
+            expect = nA * (1 + P2 / den ** 2 - 0.5 * DT3 ** 2 * E * P2 / den)
+            assert abs(e[0] - expect) < 1e-11 * e[2]
+            assert abs(e[1] - expect) < 1e-11 * e[2]
+    lat2 = oracle.Lattice2(16, 16, DT2)
+    for n in [(1, 3), (5, -2)]:
+        k = (2 * np.pi * n[0] / 16, 2 * np.pi * n[1] / 16)
+        w, amps = eigenket2(k, 0.3, DT2, 1)
+        f = plane_wave2(lat2.shape, k, amps, w, DT2)
+        P2 = sum(lattice_momentum(kj) ** 2 for kj in k)
+        X = np.sin(w * DT2 / 2)
+        E = 2 / DT2 * X
+        den = E + 0.3 * np.sqrt(1 - X * X)
+        nA = 2 * 16 * 16
+        expect = nA * (1 + P2 / den ** 2 - 0.5 * DT2 ** 2 * E * P2 / den)
+        assert abs(lat2.energy(f)[0] - expect) < 1e-11 * expect
+
+
+# --------------------------------------------------------------------------
+# Stability (Sect. 2.2, Props. 2 and 4; Sect. 3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_growth_just_beyond_bound(dim):
+    """At r = 1.01 x bound (m = 0) the zone-corner mode has X = 1.01 > 1 and the
+    plain norm grows by |lambda|^2 = (X + sqrt(X^2 - 1))^4 per step."""
+    g = rng(7)
+    if dim == 3:
+        dt = 1.01 / np.sqrt(3)
+        lat, cnt = oracle.Lattice3(4, 4, 4, dt), 8
+    else:
+        dt = 1.01 / np.sqrt(2)
+        lat, cnt = oracle.Lattice2(4, 4, dt), 4
+    th = lat.theta(0.0)
+    f = rand_state(lat.shape, cnt, g)
+    lat.step(f, th, 40)
+    n0 = lat.energy(f)[-1]
+    lat.step(f, th)
+    n1 = lat.energy(f)[-1]
+    assert abs(n1 / n0 - growth_factor(1.01) ** 2) < 1e-6
+    assert abs(growth_factor(1.01) - 1.32658) < 1e-5
+
+
+def test_bounds_below_threshold():
+    """C2-type bound from the Gram eigenvalues: plain norm <= E_r / (1 - sqrt(sum r^2))
+    at r = 0.99 x bound; Prop. 2 (sum r_j < 1) and Prop. 4 (2D) bounds."""
+    g = rng(8)
+    for dt, bound in [(0.99 / np.sqrt(3), lambda r: 1 - np.sqrt(3) * r), (0.3, lambda r: 1 - 3 * r)]:
+        lat = oracle.Lattice3(4, 4, 4, dt)
+        f = rand_state(lat.shape, 8, g)
+        E0 = lat.energy(f)[0]
+        for _ in range(300):
+            lat.step(f, rand_theta(lat.shape, 8, g, 0.3))
+            assert lat.energy(f)[-1] <= E0 / bound(dt) * (1 + 1e-12)
+    dt = 0.45
+    lat = oracle.Lattice2(6, 6, dt)
+    f = rand_state(lat.shape, 4, g)
+    E0 = lat.energy(f)[0]
+    for _ in range(300):
+        lat.step(f, rand_theta(lat.shape, 4, g, 0.3))
+        assert lat.energy(f)[-1] <= E0 / (1 - 2 * dt) * (1 + 1e-12)
+
+
+def test_prop3_2d_averaged_norm_at_bound():
+    """Sect. 3, last Proposition: at r = 1/sqrt(2) the averaged norms satisfy
+    ||u~||^2 + ||v~||^2 <= 2 E^0 for arbitrary m, V.  ||v~|| uses the same
+    construction on the v sublattices shifted by half a cell in x."""
+    g = rng(9)
+    dt = 1 / np.sqrt(2)
+    lat = oracle.Lattice2(8, 8, dt)
+    f = rand_state(lat.shape, 4, g)
+    E0 = lat.energy(f)[0]
+
+    def avg_norm(p0, p1):
+        # p0 on the integer cells, p1 on the (i+1/2, j+1/2) cells of one fcr sublattice:
+        # sum over both sub-grids of |(p(x+1,y) - i p(x+1/2,y+1/2) + p(x,y) - i p(x+1/2,y-1/2)) / (2 sqrt 2)|^2
+        t0 = (np.roll(p0, -1, 1) - 1j * p1 + p0 - 1j * np.roll(p1, 1, 0)) / (2 * np.sqrt(2))
+        t1 = (np.roll(p1, -1, 1) - 1j * np.roll(p0, (-1, -1), (0, 1)) + p1 - 1j * np.roll(p0, -1, 1)) \
+            / (2 * np.sqrt(2))
+        return float(np.sum(np.abs(t0) ** 2) + np.sum(np.abs(t1) ** 2))
+
+    for _ in range(200):
+        lat.step(f, rand_theta(lat.shape, 4, g, 0.5))
+        u = avg_norm(f[0], f[1])
+        v = avg_norm(f[2], np.roll(f[3], -1, 1))
+        assert u + v <= 2 * E0 * (1 + 1e-12)
+
+
+# --------------------------------------------------------------------------
+# Time reversal and 2D <-> 3D
+# --------------------------------------------------------------------------
+def test_reversibility_3d():
+    g = rng(10)
+    lat = oracle.Lattice3(6, 4, 8, DT3)
+    th = rand_theta(lat.shape, 8, g, 0.5)
+    f0 = rand_state(lat.shape, 8, g)
+    f = [a.copy() for a in f0]
+    lat.step(f, th, 1000)
+    lat.reverse(f, th, 1000)
+    assert rel_l2(f, f0) < 1e-13
+
+
+def test_reversibility_2d():
+    g = rng(11)
+    lat = oracle.Lattice2(12, 10, DT2)
+    th = rand_theta(lat.shape, 4, g, 0.5)
+    f0 = rand_state(lat.shape, 4, g)
+    f = [a.copy() for a in f0]
+    lat.step(f, th, 1000)
+    lat.reverse(f, th, 1000)
+    assert rel_l2(f, f0) < 1e-13
+
+
+def test_2d_is_the_AD_block_of_3d():
+    """With N_z = 1 the z differences vanish: (A, D) evolve as the (2+1)D scheme with
+    (u, v) = (A, D), and (C, B) as the (2+1)D scheme with u = C, v = B, m -> -m."""
+    g = rng(12)
+    nx, ny, dt, m = 7, 5, DT2 * 0.8, 0.35
+    l3 = oracle.Lattice3(nx, ny, 1, dt)
+    l2 = oracle.Lattice2(nx, ny, dt)
+    Vf = lambda x, y, z=None: 0.3 * np.sin(0.9 * x) * np.cos(0.7 * y)
+    th3 = l3.theta(m, lambda x, y, z: Vf(x, y))
+    f3 = rand_state(l3.shape, 8, g)
+    f3[2][:] = 0
+    f3[3][:] = 0
+    f3[4][:] = 0
+    f3[5][:] = 0
+    f2 = [f3[0][0].copy(), f3[1][0].copy(), f3[6][0].copy(), f3[7][0].copy()]
+    l3.step(f3, th3, 50)
+    l2.step(f2, l2.theta(m, Vf), 50)
+    assert rel_l2([f3[0][0], f3[1][0], f3[6][0], f3[7][0]], f2) < 1e-14
+    assert np.abs(l3.energy(f3)[0] - l2.energy(f2)[0]) < 1e-13 * l2.energy(f2)[0]
+    # the B-C block: B is updated first (from C) with the delta_+ stencil, C second
+    # with delta_-, so it is the 2D scheme for u = C, v = B, m -> -m, started from
+    # (u, v) = (C^0, B^{1/2}).  After n 2D steps u = C^n and v = B^{n+1/2}.
+    f3 = rand_state(l3.shape, 8, g)
+    for a in (0, 1, 6, 7):
+        f3[a][:] = 0
+    c0 = [f3[4][0].copy(), f3[5][0].copy()]
+    l3.step(f3, th3, 1)
+    f2 = [c0[0], c0[1], f3[2][0].copy(), f3[3][0].copy()]
+    th2 = l2.theta(-m, Vf)
+    n = 30
+    l3.step(f3, th3, n - 1)
+    c_n = [f3[4][0].copy(), f3[5][0].copy()]
+    l3.step(f3, th3, 1)
+    l2.step(f2, th2, n)
+    assert rel_l2(f2[:2], c_n) < 1e-14
+    assert rel_l2(f2[2:], [f3[2][0], f3[3][0]]) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Adjoint: dot-product test against the dense matrix, and finite differences.
+# --------------------------------------------------------------------------
+def test_adjoint_matches_dense_transpose():
+    g = rng(13)
+    lat = oracle.Lattice3(2, 3, 4, DT3)
+    D = Dense3(2, 3, 4, DT3)
+    th = rand_theta(lat.shape, 8, g)
+    pre = rand_state(lat.shape, 8, g)
+    post = [a.copy() for a in pre]
+    lat.step(post, th)
+    lam = rand_state(lat.shape, 8, g)
+    lam_v = D.pack(lam)
+    gth = [np.zeros(lat.shape) for _ in range(8)]
+    lat.adjoint(pre, post, lam, th, gth)
+    M = D.step_matrix(D.pack(th).real)
+    assert rel_l2([D.pack(lam)], [M.conj().T @ lam_v]) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adjoint_theta_gradient_fd(dim):
+    """dL/dtheta per site from the chain rule vs central differences (h = 1e-6),
+    L = probability in the region z >= z0 (x >= x0 in 2D) after n steps."""
+    g = rng(14 + dim)
+    nsteps = 6
+    if dim == 3:
+        lat, cnt = oracle.Lattice3(3, 2, 6, DT3), 8
+        z0 = 3.0
+
+        def loss(f):
+            return lat.observe(f, z0)[0]
+
+        def seed(f):
+            mask = [lat.positions(a)[2] >= z0 for a in range(8)]
+            return loss(f), [2 * f[a] * mask[a] for a in range(8)]
+        run = oracle.run_with_adjoint3
+    else:
+        lat, cnt = oracle.Lattice2(6, 4, DT2), 4
+        z0 = 3.0
+
+        def loss(f):
+            return lat.observe(f, z0)[0]
+
+        def seed(f):
+            mask = [lat.positions(a)[0] >= z0 for a in range(4)]
+            return loss(f), [2 * f[a] * mask[a] for a in range(4)]
+        run = oracle.run_with_adjoint2
+    th = rand_theta(lat.shape, cnt, g, 0.4)
+    f0 = rand_state(lat.shape, cnt, g)
+    _, _, gth, _ = run(lat, f0, th, nsteps, seed)
+    h = 1e-6
+    for _ in range(12):
+        a = int(g.integers(cnt))
+        idx = tuple(int(g.integers(s)) for s in lat.shape)
+        vals = []
+        for s in (+1, -1):
+            t2 = [x.copy() for x in th]
+            t2[a][idx] += s * h
+            f = [x.copy() for x in f0]
+            lat.step(f, t2, nsteps)
+            vals.append(loss(f))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - gth[a][idx]) < 1e-6 * max(1.0, abs(fd)), (a, idx, fd, gth[a][idx])
