@@ -1,0 +1,264 @@
+/*
+ * dirac.h -- C ABI of the MI355X (gfx950) implementation of the single-cone
+ * staggered leap-frog scheme for the time-dependent Dirac equation
+ * (R. Hammer, W. Poetz, A. Arnold, arXiv:1309.3452).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: hbar = c = 1.  r_j = dt / d_j (Sect. 2.2, "r_j = Delta_o/Delta_j").
+ *
+ * State (Sect. 2, Eq. ABCDgrid; Sect. 3 for 2D).  A (3+1)D state is 8 device
+ * arrays, in this order:
+ *     A0 (i,j,k)        A1 (i+1/2,j+1/2,k)      -- time sheet n-1/2
+ *     B0 (i+1/2,j,k+1/2) B1 (i,j+1/2,k+1/2)     -- time sheet n-1/2
+ *     C0 (i,j,k+1/2)    C1 (i+1/2,j+1/2,k+1/2)  -- time sheet n
+ *     D0 (i+1/2,j,k)    D1 (i,j+1/2,k)          -- time sheet n
+ * where the position is that of the amplitude stored for cell (i,j,k).  A
+ * (2+1)D state is 4 arrays u0 (i,j), u1 (i+1/2,j+1/2) on sheet n-1/2 and
+ * v0 (i+1/2,j), v1 (i,j+1/2) on sheet n.  Each array holds one complex
+ * amplitude per cell, interleaved (re, im), [k][j][i] with i fastest, no
+ * padding: complex64 (DIRAC_C64) or complex128 (DIRAC_C128).  Boundaries are
+ * periodic in every direction.
+ *
+ * Ownership: every device buffer is allocated by the caller and borrowed by
+ * raw pointer; it must stay valid while bound.  The library allocates only its
+ * host-side context; it never frees caller memory.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Launching calls are asynchronous on it unless said otherwise.
+ *
+ * Errors: every int-returning call returns DIRAC_OK (0) or a negative
+ * DIRAC_E_* code.  Arguments are validated before any HIP call; a failed call
+ * leaves the context unchanged.  dirac_last_error() gives a message for the
+ * last failure on a context.  Nothing aborts or throws across the ABI.
+ * A context is not thread-safe; use one per stream.
+ */
+#ifndef DIRAC_H
+#define DIRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dirac_ctx dirac_ctx;
+
+enum dirac_dtype { DIRAC_C64 = 1, DIRAC_C128 = 2 };
+
+enum dirac_status {
+    DIRAC_OK = 0,
+    DIRAC_E_ARG = -1,        /* null pointer, bad enum or value out of range      */
+    DIRAC_E_SHAPE = -2,      /* lattice sizes or buffer sizes do not fit          */
+    DIRAC_E_UNSTABLE = -3,   /* r_x^2 + r_y^2 (+ r_z^2) > 1 without ALLOW_UNSTABLE */
+    DIRAC_E_NONFINITE = -4,  /* a reduction met NaN or Inf                        */
+    DIRAC_E_HIP = -5,        /* a HIP runtime call failed (message has details)   */
+    DIRAC_E_STATE = -6       /* call out of order (e.g. no state bound yet)       */
+};
+
+/* dirac_create flags */
+#define DIRAC_ALLOW_UNSTABLE 1u
+
+/* step kernels (dirac_set_kernel) */
+enum dirac_kernel {
+    DIRAC_KERNEL_AUTO = 0,   /* fused where available                              */
+    DIRAC_KERNEL_SPLIT = 1,  /* one launch per half-step, in place                 */
+    DIRAC_KERNEL_FUSED = 2   /* one launch per step, ping-pong between the buffers */
+};
+
+/* Human-readable name of a status code (static storage). */
+const char *dirac_status_string(int status);
+
+/*
+ * Create a lattice context.
+ *   ndim   2 or 3.  For ndim == 2, nz must be 1 and dz is ignored.
+ *   nx, ny, nz  cells per direction, each >= 1; nx*ny*nz < 2^40.
+ *   dtype  DIRAC_C64 (complex64 storage and FP32 arithmetic, FP64 reductions)
+ *          or DIRAC_C128 (FP64 throughout).
+ *   dt     time step (Delta_o = dt); dx, dy, dz > 0 grid spacings.
+ *   flags  DIRAC_ALLOW_UNSTABLE to accept sum r_j^2 > 1 (the scheme then
+ *          grows, Sect. 2.2 and Sect. 3 "reality condition").
+ * Validates the stability bound sum_j r_j^2 <= 1 of Sect. 2.2 (3D) / Sect. 3
+ * (2D).  The context starts with m = 0, V = 0.  Makes no HIP call.
+ */
+int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                 double dt, double dx, double dy, double dz, unsigned flags);
+
+/* Release the context (and any graph it owns).  Safe on NULL. */
+void dirac_destroy(dirac_ctx *ctx);
+
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char *dirac_last_error(const dirac_ctx *ctx);
+
+/*
+ * Bind the state.  buf0 and buf1 each give 8 (3D) or 4 (2D) device arrays of
+ * nx*ny*nz amplitudes in the layout above.  buf0 holds the initial state;
+ * buf1 is the partner the fused kernel writes into (it may alias nothing the
+ * caller still needs).  The current state flips between them as fused steps
+ * run; dirac_current() says where it is.
+ */
+int dirac_bind_state(dirac_ctx *ctx, void *const buf0[], void *const buf1[]);
+
+/* which = 0 if buf0 holds the current state, 1 if buf1 does. */
+int dirac_current(const dirac_ctx *ctx, int *which);
+
+/* Declare which bound buffer set holds the current state (after the caller
+ * wrote a new state into it). */
+int dirac_set_current(dirac_ctx *ctx, int which);
+
+/*
+ * Scratch for reductions and gradients.  dirac_scratch_bytes reports the size
+ * this context needs; the caller allocates at least that much device memory
+ * (256-byte aligned) and binds it.  Required before norm/observables/adjoint.
+ */
+int dirac_scratch_bytes(const dirac_ctx *ctx, size_t *bytes);
+int dirac_bind_scratch(dirac_ctx *ctx, void *dev, size_t bytes);
+
+/*
+ * Mass and a potential that depends on z only (3D) or is zero (2D), Eqs. ss1-ss4:
+ * theta = (dt/2)(m + V) at A,B sites on sheet n and (dt/2)(-m + V) at C,D
+ * sites on sheet n+1/2, each at the amplitude's own z.
+ *   v_int[k]  = V(z = k)      (used at A and D sites),
+ *   v_half[k] = V(z = k+1/2)  (used at B and C sites),
+ * host arrays of nz doubles, or both NULL for V = 0.  In 2D pass nz = 1 and
+ * NULL arrays (use dirac_theta_from_fields for V(x, y)).  Replaces any
+ * per-site field.  Copies the tables to the device on the next launch.
+ */
+int dirac_set_mass_potential_z(dirac_ctx *ctx, double m, const double *v_int, const double *v_half,
+                               int64_t nz);
+
+/*
+ * Per-site mass and potential.  v_site[a] is a device array (real, float for
+ * DIRAC_C64 and double for DIRAC_C128, one value per cell) holding V at the
+ * sites of state array a, or NULL for V = 0 there.  theta[a] are caller-owned
+ * device arrays of the same type and size that receive
+ * theta = (dt/2)(+-m + V) (+ for A,B / u, - for C,D / v); they stay bound and
+ * are read by every later step until replaced.  Asynchronous on stream.
+ */
+int dirac_theta_from_fields(dirac_ctx *ctx, double m, void *const v_site[], void *const theta[],
+                            void *stream);
+
+/* Bind already computed per-site theta arrays (same type and layout as above). */
+int dirac_set_theta_field(dirac_ctx *ctx, void *const theta[]);
+
+/* Choose the step kernel and its tiling; 0 = library default for a knob.
+ *   tile_y: cells along y per workgroup of the 3D fused kernel: 4 or 8
+ *           (default 4 for complex128, 8 for complex64); the tile is 64 cells in x
+ *   zchunk: planes (3D) or rows (2D) per workgroup along the march of the fused
+ *           kernel (default: enough chunks for ~2048 workgroups)
+ * The reversed step and the adjoint always use the split kernels. */
+int dirac_set_kernel(dirac_ctx *ctx, int kernel, int tile_y, int zchunk);
+
+/*
+ * Advance the bound state by n >= 0 full steps (Sect. 2: A,B from n-1/2 to
+ * n+1/2 by Eqs. ss1, ss2, then C,D from n to n+1 by Eqs. ss3, ss4; Sect. 3:
+ * u then v by Eqs. scheme2Deq-scheme4thline).  Asynchronous on stream.
+ */
+int dirac_step(dirac_ctx *ctx, int64_t n, void *stream);
+
+/*
+ * Undo n full steps exactly (up to rounding): the relations of Eqs. ss3, ss4
+ * solved for the old C,D, then those of ss1, ss2 for the old A,B -- the step
+ * with dt -> -dt in the opposite half-step order.  Asynchronous on stream.
+ */
+int dirac_reverse(dirac_ctx *ctx, int64_t n, void *stream);
+
+/*
+ * Conserved functional of Lemma, Sect. 2, Eq. (EPM) (3D) / Lemma, Sect. 3,
+ * Eq. (E) with the delta_+ sign that the update equations conserve (2D):
+ *   dev_out[0] = sum |X|^2 - Re sum_{A,B sites} conj(X) S_X(C,D)
+ *   dev_out[1] = sum |X|^2 + Re sum_{C,D sites} conj(X) S_X(A,B)   (equal to [0])
+ *   dev_out[2] = sum |X|^2 (the plain norm, conserved only on average)
+ * accumulated in FP64 in a fixed order (run-to-run bitwise reproducible).
+ * dirac_norm_device writes 3 doubles to device memory, asynchronously;
+ * dirac_norm copies them to host `out` and synchronises the stream, and
+ * returns DIRAC_E_NONFINITE if any is NaN/Inf.
+ */
+int dirac_norm_device(dirac_ctx *ctx, void *dev_out, void *stream);
+int dirac_norm(dirac_ctx *ctx, double out[3], void *stream);
+
+/*
+ * Observables of the plain density |X|^2 over all sites, FP64, positions in
+ * cell units (each amplitude at its own site):
+ *   3D: out[0] = sum over sites with z >= z0, out[1..3] = sum x|X|^2, y|X|^2,
+ *       z|X|^2, out[4] = sum |X|^2, out[5..8] = per component A, B, C, D.
+ *   2D: out[0] = sum over sites with x >= z0, out[1..2] = sum x|X|^2, y|X|^2,
+ *       out[3] = sum |X|^2, out[4..5] = per component u, v; out[6..8] = 0.
+ * Synchronous; out has 9 doubles.
+ */
+int dirac_observables(dirac_ctx *ctx, double z0, double out[9], void *stream);
+
+/*
+ * Seed of the adjoint of L = sum_{z_s >= z0} |psi_s|^2 (3D; x_s >= z0 in 2D):
+ * lam[a] = 2 psi on the region, 0 elsewhere, with lam = dL/dRe + i dL/dIm.
+ * lam: device arrays shaped like the state.  Asynchronous.
+ */
+int dirac_seed_region(dirac_ctx *ctx, double z0, void *const lam[], void *stream);
+
+/*
+ * Reverse-mode gradient of a function of the final state with respect to the
+ * z-profile of V (3D, after dirac_set_mass_potential_z).  On entry the bound
+ * state is psi after n steps and lam[] holds dL/dRe + i dL/dIm at that state.
+ * Runs n backward steps, each rebuilding the previous state by the exact
+ * reversed step (no stored trajectory) and carrying lam back by the chain rule
+ * through Eqs. ss3, ss4 then ss1, ss2.  On return the state is the rebuilt
+ * initial state, lam the adjoint at it, and the device FP64 arrays
+ * dLdV_int[nz] (V at z = k: A, D sites) and dLdV_half[nz] (V at z = k+1/2:
+ * B, C sites) hold dL/dV summed over all steps (overwritten, deterministic).
+ * Uses the split kernels.  Asynchronous on stream.
+ */
+int dirac_adjoint_vz(dirac_ctx *ctx, int64_t n, void *const lam[], void *dLdV_int, void *dLdV_half,
+                     void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched (2+1)D lattices: many independent lattices of different size,    */
+/* mass and potential advanced together.                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Create a batch of `count` 2D lattices, lattice b having nx[b] x ny[b] cells
+ * (each >= 1), common dtype and dt (unit spacing), per-site theta supplied by
+ * dirac_batch_bind.  Stability is checked as for dirac_create.  No HIP call.
+ */
+int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype,
+                       double dt, unsigned flags);
+
+/*
+ * Bind the buffers of every lattice: state[4*b + a], partner[4*b + a] and
+ * theta[4*b + a] for array a (u0 u1 v0 v1) of lattice b -- device pointers in
+ * the single-lattice layout; theta real, float for C64 and double for C128,
+ * holding (dt/2)(+-m + V) per site.  Also binds the scratch (see
+ * dirac_scratch_bytes on the batch context).
+ */
+int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[], void *const theta[],
+                     void *scratch, size_t scratch_bytes);
+
+/*
+ * Advance every lattice by n steps.  mode 0: one persistent launch for all n
+ * steps with per-lattice step barriers; mode 1: one launch per step over all
+ * lattices (both replayed from a captured HIP graph when use_graph != 0).
+ * After an odd n the partner buffers hold the state (dirac_current).
+ */
+int dirac_batch_run(dirac_ctx *ctx, int64_t n, int mode, int use_graph, void *stream);
+
+/* E_r, E_r (C,D form), plain norm of every lattice: host out[3*count]. Synchronous. */
+int dirac_batch_norms(dirac_ctx *ctx, double *out, void *stream);
+
+/*
+ * Pick the batched kernel's tile shape (x strip width, y chunk height) for
+ * each mode by timing every candidate for a few steps on the bound lattices.
+ * This advances the bound state by an even number of steps (it stays in the
+ * same buffer set); callers that need the state unchanged save and restore it.
+ * cache_path: JSON file consulted first and updated (NULL = no cache), keyed
+ * by device architecture, dtype and batch shape.  The choice is kept in the
+ * context.  Synchronous.  chosen_out (may be NULL) receives
+ * (candidate for mode 1) | (candidate for mode 0) << 8.
+ */
+int dirac_batch_autotune(dirac_ctx *ctx, const char *cache_path, int *chosen_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIRAC_H */

@@ -1,0 +1,85 @@
+"""Many independent (2+1)D lattices advanced together (dirac_batch_* calls)."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import check, lib, ptr_array
+from .lattice import _dtype_code, _stream_handle
+
+
+class BatchedLattices:
+    """lattices: sequence of dicts with nx, ny, m, v_site (4 real arrays or None)
+    and state (4 complex arrays of shape (ny, nx)).  dt common, unit spacing."""
+
+    def __init__(self, lattices, dtype=torch.complex64, dt=0.5, device="cuda"):
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.real_dtype = torch.float32 if dtype == torch.complex64 else torch.float64
+        self.dt = float(dt)
+        self.count = len(lattices)
+        nx = (ctypes.c_int64 * self.count)(*[int(L["nx"]) for L in lattices])
+        ny = (ctypes.c_int64 * self.count)(*[int(L["ny"]) for L in lattices])
+        self.shapes = [(int(L["ny"]), int(L["nx"])) for L in lattices]
+        ctx = ctypes.c_void_p()
+        check(lib().dirac_batch_create(ctypes.byref(ctx), self.count, nx, ny, _dtype_code(dtype), self.dt, 0))
+        self._ctx = ctx
+        self.bufs = [[], []]
+        self.theta = []
+        half = 0.5 * self.dt
+        for L, shp in zip(lattices, self.shapes):
+            st = [torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous().clone() for a in L["state"]]
+            self.bufs[0].append(st)
+            self.bufs[1].append([torch.zeros(shp, dtype=dtype, device=self.device) for _ in range(4)])
+            m = float(L["m"])
+            vs = L.get("v_site")
+            th = []
+            for a in range(4):
+                v = torch.zeros(shp, dtype=torch.float64, device=self.device) if vs is None else \
+                    torch.as_tensor(vs[a]).to(device=self.device, dtype=torch.float64)
+                sgn = 1.0 if a < 2 else -1.0
+                # theta = (dt/2)(+-m + V) per site (u: +m, v: -m), Eqs. scheme2Deq-scheme4thline
+                th.append((half * (sgn * m + v)).to(self.real_dtype).contiguous())
+            self.theta.append(th)
+        nbytes = ctypes.c_size_t()
+        check(lib().dirac_scratch_bytes(ctx, ctypes.byref(nbytes)), ctx)
+        self.scratch = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.scratch.data_ptr() + 255) & ~255
+        flat = lambda sets: ptr_array([t.data_ptr() for s in sets for t in s])
+        check(lib().dirac_batch_bind(ctx, flat(self.bufs[0]), flat(self.bufs[1]), flat(self.theta),
+                                     ctypes.c_void_p(aligned), int(nbytes.value)), ctx)
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                lib().dirac_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    @property
+    def current(self):
+        w = ctypes.c_int()
+        check(lib().dirac_current(self._ctx, ctypes.byref(w)), self._ctx)
+        return int(w.value)
+
+    def state(self, b):
+        return self.bufs[self.current][b]
+
+    def run(self, n, mode=1, graph=False):
+        """mode 1: one launch per step; mode 0: one persistent launch.  graph: replay a captured HIP graph."""
+        check(lib().dirac_batch_run(self._ctx, int(n), int(mode), 1 if graph else 0, _stream_handle()), self._ctx)
+
+    def norms(self):
+        out = (ctypes.c_double * (3 * self.count))()
+        check(lib().dirac_batch_norms(self._ctx, out, _stream_handle()), self._ctx)
+        return [tuple(out[3 * b:3 * b + 3]) for b in range(self.count)]
+
+    def autotune(self, cache_path=None):
+        ch = ctypes.c_int()
+        check(lib().dirac_batch_autotune(self._ctx, cache_path.encode() if cache_path else None,
+                                         ctypes.byref(ch), _stream_handle()), self._ctx)
+        return int(ch.value) & 0xff, int(ch.value) >> 8

@@ -1,0 +1,556 @@
+// C ABI of the library: context, validation, coefficient tables, dispatch of
+// the single-lattice kernels.  The batched entry points live in batch.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dirac.h"
+#include "ctx.h"
+#include "internal.h"
+
+using namespace dirac;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+int fail(dirac_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(dirac_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((ctx), DIRAC_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                \
+    } while (0)
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// FP64 Cayley coefficients, every operation rounded on its own.
+void cayley64(double th, double out[4]) {
+#pragma clang fp contract(off)
+    double t2 = th * th;
+    double d = 1.0 + t2;
+    out[0] = (1.0 - t2) / d;
+    out[1] = -((2.0 * th) / d);
+    out[2] = 1.0 / d;
+    out[3] = -(th / d);
+}
+
+// FP32 increment-form coefficients gamma = 2 i th / (1 + i th), beta = 1 / (1 + i th).
+// The rounded pair (gamma_re, gamma_im) is chosen among nearby floats to make
+// |1 - gamma|^2 = 1 as closely as FP32 allows (the factor multiplying X- is
+// then unit-modulus to ~1e-10, so the conserved functional does not drift
+// systematically where theta is constant over space).
+void cayley32(double th, float out[4]) {
+#pragma clang fp contract(off)
+    double d = 1.0 + th * th;
+    double gr0 = 2.0 * th * th / d, gi0 = 2.0 * th / d;
+    float best_r = (float)gr0, best_i = (float)gi0;
+    double best = 1e300;
+    float gi = (float)gi0;
+    for (int di = -4; di <= 4; ++di) {
+        float ci = gi;
+        for (int q = 0; q < (di < 0 ? -di : di); ++q) ci = nextafterf(ci, di < 0 ? -INFINITY : INFINITY);
+        double cid = (double)ci;
+        double gr_exact = cid * cid / (1.0 + sqrt(1.0 - cid * cid));
+        float cr = (float)gr_exact;
+        for (int dr = -2; dr <= 2; ++dr) {
+            float c = cr;
+            for (int q = 0; q < (dr < 0 ? -dr : dr); ++q) c = nextafterf(c, dr < 0 ? -INFINITY : INFINITY);
+            double one_m = 1.0 - (double)c;
+            double err = fabs(one_m * one_m + cid * cid - 1.0);
+            // prefer the candidate closest to the exact coefficients among equal errors
+            double dist = fabs((double)c - gr0) + fabs(cid - gi0);
+            if (err < best || (err == best && dist < fabs((double)best_r - gr0) + fabs((double)best_i - gi0))) {
+                best = err;
+                best_r = c;
+                best_i = ci;
+            }
+        }
+    }
+    out[0] = best_r;
+    out[1] = best_i;
+    out[2] = (float)(1.0 / d);
+    out[3] = (float)(-th / d);
+}
+
+// theta of class q (A, B, C, D) at plane k: (dt/2)(+-m + V at the class's z).
+double theta_of(const dirac_ctx *c, int q, int64_t k) {
+    double h = 0.5 * c->dt;
+    double v = 0.0;
+    if (!c->v_int.empty()) v = (q == 0 || q == 3) ? c->v_int[k] : c->v_half[k];
+    double sgn = (q < 2) ? 1.0 : -1.0;
+    return h * (sgn * c->m + v);
+}
+
+template <typename R> size_t tab_bytes(const dirac_ctx *c) { return (size_t)4 * c->nz * 4 * sizeof(R); }
+
+size_t tab_bytes_of(const dirac_ctx *c) {
+    return c->dtype == DIRAC_C64 ? tab_bytes<float>(c) : tab_bytes<double>(c);
+}
+
+// scratch layout
+size_t off_partial(const dirac_ctx *) { return 0; }
+size_t off_result(const dirac_ctx *) { return align256((size_t)kReduceBlocks * kObsVals * sizeof(double)); }
+size_t off_tab(const dirac_ctx *c) { return off_result(c) + 256; }
+size_t off_gpart(const dirac_ctx *c) { return off_tab(c) + 2 * align256(tab_bytes_of(c)); }
+size_t scratch_need(const dirac_ctx *c) {
+    size_t g = 0;
+    if (c->ndim == 3) g = (size_t)adj_tiles3((int)c->nx, (int)c->ny) * c->nz * 2 * sizeof(double);
+    return off_gpart(c) + align256(g);
+}
+
+char *scratch_at(const dirac_ctx *c, size_t off) { return (char *)c->scratch + off; }
+
+int upload_tables(dirac_ctx *c, hipStream_t s) {
+    if (!c->tab_dirty) return DIRAC_OK;
+    if (!c->scratch) return fail(c, DIRAC_E_STATE, "scratch must be bound before stepping");
+    const int64_t nz = c->nz;
+    if (c->dtype == DIRAC_C128) {
+        c->tab_host64.assign((size_t)2 * 4 * nz * 4, 0.0);
+        for (int dir = 0; dir < 2; ++dir)
+            for (int q = 0; q < 4; ++q)
+                for (int64_t k = 0; k < nz; ++k) {
+                    double th = theta_of(c, q, k);
+                    cayley64(dir == 0 ? th : -th, &c->tab_host64[(((size_t)dir * 4 + q) * nz + k) * 4]);
+                }
+        size_t half = tab_bytes<double>(c);
+        HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c)), c->tab_host64.data(), half, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c) + align256(half)), c->tab_host64.data() + 4 * nz * 4,
+                                 half, hipMemcpyHostToDevice, s));
+    } else {
+        c->tab_host32.assign((size_t)2 * 4 * nz * 4, 0.0f);
+        for (int dir = 0; dir < 2; ++dir)
+            for (int q = 0; q < 4; ++q)
+                for (int64_t k = 0; k < nz; ++k) {
+                    double th = theta_of(c, q, k);
+                    cayley32(dir == 0 ? th : -th, &c->tab_host32[(((size_t)dir * 4 + q) * nz + k) * 4]);
+                }
+        size_t half = tab_bytes<float>(c);
+        HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c)), c->tab_host32.data(), half, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c) + align256(half)), c->tab_host32.data() + 4 * nz * 4,
+                                 half, hipMemcpyHostToDevice, s));
+    }
+    // the host staging vectors stay alive in the context until the next upload
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->tab_dirty = false;
+    return DIRAC_OK;
+}
+
+template <typename R> HalfArgs<R> half_args(dirac_ctx *c, bool reverse) {
+    HalfArgs<R> a;
+    memset(&a, 0, sizeof a);
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q) {
+        a.f[q] = c->buf[c->cur][q];
+        a.th[q] = c->site_mode ? (const R *)c->theta[q] : nullptr;
+    }
+    size_t half = align256(tab_bytes<R>(c));
+    a.tab = c->site_mode ? nullptr : (const R *)scratch_at(c, off_tab(c) + (reverse ? half : 0));
+    R sg = reverse ? (R)-1 : (R)1;
+    a.rx = sg * (R)c->rx;
+    a.ry = sg * (R)c->ry;
+    a.rz = sg * (R)c->rz;
+    a.tsgn = sg;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.nz = (int)c->nz;
+    return a;
+}
+
+template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
+    FusedArgs<R> a;
+    memset(&a, 0, sizeof a);
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q) {
+        a.in[q] = c->buf[c->cur][q];
+        a.out[q] = c->buf[1 - c->cur][q];
+        a.th[q] = c->site_mode ? (const R *)c->theta[q] : nullptr;
+    }
+    a.tab = c->site_mode ? nullptr : (const R *)scratch_at(c, off_tab(c));
+    a.rx = (R)c->rx;
+    a.ry = (R)c->ry;
+    a.rz = (R)c->rz;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.nz = (int)c->nz;
+    a.zchunk = c->zchunk;
+    return a;
+}
+
+int kernel_choice(const dirac_ctx *c) {
+    if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
+    if (c->kernel == DIRAC_KERNEL_FUSED) return DIRAC_KERNEL_FUSED;
+    return DIRAC_KERNEL_FUSED;
+}
+
+template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipStream_t s) {
+    int rc = upload_tables(c, s);
+    if (rc) return rc;
+    const bool site = c->site_mode;
+    const bool fused = !reverse && kernel_choice(c) == DIRAC_KERNEL_FUSED;
+    for (int64_t t = 0; t < n; ++t) {
+        if (fused) {
+            FusedArgs<R> a = fused_args<R>(c);
+            if (c->ndim == 3) HIPCHK(c, launch_fused3<R>(a, site, c->tile_y, s));
+            else HIPCHK(c, launch_fused2<R>(a, site, s));
+            c->cur = 1 - c->cur;
+        } else {
+            HalfArgs<R> a = half_args<R>(c, reverse);
+            int first = reverse ? 1 : 0;
+            if (c->ndim == 3) {
+                HIPCHK(c, launch_half3<R>(a, first, site, s));
+                HIPCHK(c, launch_half3<R>(a, 1 - first, site, s));
+            } else {
+                HIPCHK(c, launch_half2<R>(a, first, site, s));
+                HIPCHK(c, launch_half2<R>(a, 1 - first, site, s));
+            }
+        }
+    }
+    return DIRAC_OK;
+}
+
+template <typename R> ReduceArgs<R> reduce_args(dirac_ctx *c, double z0) {
+    ReduceArgs<R> a;
+    memset(&a, 0, sizeof a);
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q) a.f[q] = c->buf[c->cur][q];
+    a.rx = (R)c->rx;
+    a.ry = (R)c->ry;
+    a.rz = (R)c->rz;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.nz = (int)c->nz;
+    a.z0 = z0;
+    a.partial = (double *)scratch_at(c, off_partial(c));
+    return a;
+}
+
+int check_ready(dirac_ctx *c, bool need_scratch) {
+    if (!c) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context: use the dirac_batch_* calls");
+    if (!c->bound) return fail(c, DIRAC_E_STATE, "no state bound (dirac_bind_state)");
+    if (need_scratch && !c->scratch) return fail(c, DIRAC_E_STATE, "no scratch bound (dirac_bind_scratch)");
+    return DIRAC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *dirac_status_string(int status) {
+    switch (status) {
+    case DIRAC_OK: return "ok";
+    case DIRAC_E_ARG: return "invalid argument";
+    case DIRAC_E_SHAPE: return "invalid shape";
+    case DIRAC_E_UNSTABLE: return "step above the stability bound";
+    case DIRAC_E_NONFINITE: return "non-finite value";
+    case DIRAC_E_HIP: return "HIP runtime error";
+    case DIRAC_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, double dt, double dx,
+                 double dy, double dz, unsigned flags) {
+    if (!out) return DIRAC_E_ARG;
+    *out = nullptr;
+    if (ndim != 2 && ndim != 3) return DIRAC_E_ARG;
+    if (dtype != DIRAC_C64 && dtype != DIRAC_C128) return DIRAC_E_ARG;
+    if ((flags & ~DIRAC_ALLOW_UNSTABLE) != 0) return DIRAC_E_ARG;
+    if (nx < 1 || ny < 1 || nz < 1) return DIRAC_E_SHAPE;
+    if (ndim == 2 && nz != 1) return DIRAC_E_SHAPE;
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return DIRAC_E_SHAPE;
+    if ((double)nx * (double)ny * (double)nz >= 1099511627776.0) return DIRAC_E_SHAPE;
+    if (!finite_pos(dt) || !finite_pos(dx) || !finite_pos(dy) || (ndim == 3 && !finite_pos(dz))) return DIRAC_E_ARG;
+    double rx = dt / dx, ry = dt / dy, rz = ndim == 3 ? dt / dz : 0.0;
+    double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 > 1.0 + 1e-12 && !(flags & DIRAC_ALLOW_UNSTABLE)) return DIRAC_E_UNSTABLE;
+    dirac_ctx *c = new (std::nothrow) dirac_ctx();
+    if (!c) return DIRAC_E_ARG;
+    c->ndim = ndim;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->dtype = dtype;
+    c->dt = dt;
+    c->rx = rx;
+    c->ry = ry;
+    c->rz = rz;
+    c->flags = flags;
+    *out = c;
+    return DIRAC_OK;
+}
+
+void dirac_destroy(dirac_ctx *c) {
+    if (!c) return;
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    delete c;
+}
+
+const char *dirac_last_error(const dirac_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int dirac_bind_state(dirac_ctx *c, void *const buf0[], void *const buf1[]) {
+    if (!c || !buf0 || !buf1) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context: use dirac_batch_bind");
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q)
+        if (!buf0[q] || !buf1[q]) return fail(c, DIRAC_E_ARG, "null state array %d", q);
+    for (int q = 0; q < 8; ++q) {
+        c->buf[0][q] = q < narr ? buf0[q] : nullptr;
+        c->buf[1][q] = q < narr ? buf1[q] : nullptr;
+    }
+    c->bound = true;
+    c->cur = 0;
+    return DIRAC_OK;
+}
+
+int dirac_current(const dirac_ctx *c, int *which) {
+    if (!c || !which) return DIRAC_E_ARG;
+    *which = c->cur;
+    return DIRAC_OK;
+}
+
+int dirac_set_current(dirac_ctx *c, int which) {
+    if (!c || (which != 0 && which != 1)) return DIRAC_E_ARG;
+    c->cur = which;
+    return DIRAC_OK;
+}
+
+int dirac_scratch_bytes(const dirac_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return DIRAC_E_ARG;
+    *bytes = c->is_batch ? c->batch_scratch_need : scratch_need(c);
+    return DIRAC_OK;
+}
+
+int dirac_bind_scratch(dirac_ctx *c, void *dev, size_t bytes) {
+    if (!c || !dev) return DIRAC_E_ARG;
+    if (((uintptr_t)dev & 255) != 0) return fail(c, DIRAC_E_ARG, "scratch must be 256-byte aligned");
+    size_t need = c->is_batch ? c->batch_scratch_need : scratch_need(c);
+    if (bytes < need) return fail(c, DIRAC_E_SHAPE, "scratch too small: %zu < %zu bytes", bytes, need);
+    c->scratch = dev;
+    c->scratch_bytes = bytes;
+    c->tab_dirty = true;
+    return DIRAC_OK;
+}
+
+int dirac_set_mass_potential_z(dirac_ctx *c, double m, const double *v_int, const double *v_half, int64_t nz) {
+    if (!c || !isfinite(m)) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    if (nz != c->nz) return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice nz %lld", (long long)nz, (long long)c->nz);
+    if ((v_int == nullptr) != (v_half == nullptr)) return fail(c, DIRAC_E_ARG, "v_int and v_half: both or neither");
+    if (v_int && c->ndim == 2) return fail(c, DIRAC_E_ARG, "2D: use dirac_theta_from_fields for V(x, y)");
+    std::vector<double> vi, vh;
+    if (v_int) {
+        vi.assign(v_int, v_int + nz);
+        vh.assign(v_half, v_half + nz);
+        for (int64_t k = 0; k < nz; ++k)
+            if (!isfinite(vi[k]) || !isfinite(vh[k])) return fail(c, DIRAC_E_NONFINITE, "non-finite V at k=%lld",
+                                                                   (long long)k);
+    }
+    c->m = m;
+    c->v_int.swap(vi);
+    c->v_half.swap(vh);
+    c->site_mode = false;
+    c->tab_dirty = true;
+    return DIRAC_OK;
+}
+
+int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
+    if (!c || !theta) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q)
+        if (!theta[q]) return fail(c, DIRAC_E_ARG, "null theta array %d", q);
+    for (int q = 0; q < 8; ++q) c->theta[q] = q < narr ? theta[q] : nullptr;
+    c->site_mode = true;
+    return DIRAC_OK;
+}
+
+int dirac_theta_from_fields(dirac_ctx *c, double m, void *const v_site[], void *const theta[], void *stream) {
+    if (!c || !theta || !isfinite(m)) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    int narr = c->ndim == 3 ? 8 : 4;
+    for (int q = 0; q < narr; ++q)
+        if (!theta[q]) return fail(c, DIRAC_E_ARG, "null theta array %d", q);
+    void *th8[8] = {0}, *v8[8] = {0};
+    for (int q = 0; q < narr; ++q) {
+        th8[q] = theta[q];
+        v8[q] = v_site ? v_site[q] : nullptr;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int64_t ncell = c->nx * c->ny * c->nz;
+    if (c->dtype == DIRAC_C64) HIPCHK(c, launch_theta_fields<float>(th8, v8, narr, ncell, 0.5 * c->dt, m, s));
+    else HIPCHK(c, launch_theta_fields<double>(th8, v8, narr, ncell, 0.5 * c->dt, m, s));
+    c->m = m;
+    return dirac_set_theta_field(c, theta);
+}
+
+int dirac_set_kernel(dirac_ctx *c, int kernel, int tile_y, int zchunk) {
+    if (!c) return DIRAC_E_ARG;
+    if (kernel < DIRAC_KERNEL_AUTO || kernel > DIRAC_KERNEL_FUSED) return fail(c, DIRAC_E_ARG, "bad kernel %d", kernel);
+    if (tile_y != 0 && tile_y != 4 && tile_y != 8) return fail(c, DIRAC_E_ARG, "tile_y must be 0, 4 or 8");
+    if (zchunk < 0) return fail(c, DIRAC_E_ARG, "zchunk must be >= 0");
+    c->kernel = kernel;
+    c->tile_y = tile_y;
+    c->zchunk = zchunk;
+    return DIRAC_OK;
+}
+
+int dirac_step(dirac_ctx *c, int64_t n, void *stream) {
+    int rc = check_ready(c, !c || !c->site_mode);
+    if (rc) return rc;
+    if (n < 0) return fail(c, DIRAC_E_ARG, "n must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    return c->dtype == DIRAC_C64 ? run_steps<float>(c, n, false, s) : run_steps<double>(c, n, false, s);
+}
+
+int dirac_reverse(dirac_ctx *c, int64_t n, void *stream) {
+    int rc = check_ready(c, !c || !c->site_mode);
+    if (rc) return rc;
+    if (n < 0) return fail(c, DIRAC_E_ARG, "n must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    return c->dtype == DIRAC_C64 ? run_steps<float>(c, n, true, s) : run_steps<double>(c, n, true, s);
+}
+
+int dirac_norm_device(dirac_ctx *c, void *dev_out, void *stream) {
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    if (!dev_out) return fail(c, DIRAC_E_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    double *part = (double *)scratch_at(c, off_partial(c));
+    if (c->dtype == DIRAC_C64) {
+        ReduceArgs<float> a = reduce_args<float>(c, 0.0);
+        HIPCHK(c, c->ndim == 3 ? launch_norm3<float>(a, s) : launch_norm2<float>(a, s));
+    } else {
+        ReduceArgs<double> a = reduce_args<double>(c, 0.0);
+        HIPCHK(c, c->ndim == 3 ? launch_norm3<double>(a, s) : launch_norm2<double>(a, s));
+    }
+    HIPCHK(c, launch_final_sum(part, kReduceBlocks, kNormVals, (double *)dev_out, s));
+    return DIRAC_OK;
+}
+
+int dirac_norm(dirac_ctx *c, double out[3], void *stream) {
+    if (!out) return c ? fail(c, DIRAC_E_ARG, "null output") : DIRAC_E_ARG;
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    double *res = (double *)scratch_at(c, off_result(c));
+    rc = dirac_norm_device(c, res, stream);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int q = 0; q < 3; ++q)
+        if (!isfinite(out[q])) return fail(c, DIRAC_E_NONFINITE, "norm value %d is not finite", q);
+    return DIRAC_OK;
+}
+
+int dirac_observables(dirac_ctx *c, double z0, double out[9], void *stream) {
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    if (!out || !isfinite(z0)) return fail(c, DIRAC_E_ARG, "bad output or z0");
+    hipStream_t s = (hipStream_t)stream;
+    double *part = (double *)scratch_at(c, off_partial(c));
+    double *res = (double *)scratch_at(c, off_result(c));
+    if (c->dtype == DIRAC_C64) {
+        ReduceArgs<float> a = reduce_args<float>(c, z0);
+        HIPCHK(c, c->ndim == 3 ? launch_obs3<float>(a, s) : launch_obs2<float>(a, s));
+    } else {
+        ReduceArgs<double> a = reduce_args<double>(c, z0);
+        HIPCHK(c, c->ndim == 3 ? launch_obs3<double>(a, s) : launch_obs2<double>(a, s));
+    }
+    HIPCHK(c, launch_final_sum(part, kReduceBlocks, kObsVals, res, s));
+    HIPCHK(c, hipMemcpyAsync(out, res, kObsVals * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int q = 0; q < kObsVals; ++q)
+        if (!isfinite(out[q])) return fail(c, DIRAC_E_NONFINITE, "observable %d is not finite", q);
+    return DIRAC_OK;
+}
+
+int dirac_seed_region(dirac_ctx *c, double z0, void *const lam[], void *stream) {
+    int rc = check_ready(c, false);
+    if (rc) return rc;
+    if (!lam || !isfinite(z0)) return fail(c, DIRAC_E_ARG, "bad lam or z0");
+    int narr = c->ndim == 3 ? 8 : 4;
+    void *l8[8] = {0};
+    for (int q = 0; q < narr; ++q) {
+        if (!lam[q]) return fail(c, DIRAC_E_ARG, "null lam array %d", q);
+        l8[q] = lam[q];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (c->dtype == DIRAC_C64) {
+        ReduceArgs<float> a = reduce_args<float>(c, z0);
+        HIPCHK(c, c->ndim == 3 ? launch_seed3<float>(a, l8, s) : launch_seed2<float>(a, l8, s));
+    } else {
+        ReduceArgs<double> a = reduce_args<double>(c, z0);
+        HIPCHK(c, c->ndim == 3 ? launch_seed3<double>(a, l8, s) : launch_seed2<double>(a, l8, s));
+    }
+    return DIRAC_OK;
+}
+
+int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int, void *dLdV_half, void *stream) {
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    if (c->ndim != 3) return fail(c, DIRAC_E_STATE, "the V(z) gradient is defined for 3D lattices");
+    if (c->site_mode) return fail(c, DIRAC_E_STATE, "needs a V(z) profile (dirac_set_mass_potential_z)");
+    if (n < 0 || !lam || !dLdV_int || !dLdV_half) return fail(c, DIRAC_E_ARG, "bad arguments");
+    for (int q = 0; q < 8; ++q)
+        if (!lam[q]) return fail(c, DIRAC_E_ARG, "null lam array %d", q);
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload_tables(c, s);
+    if (rc) return rc;
+    const int ntiles = adj_tiles3((int)c->nx, (int)c->ny);
+    double *gpart = (double *)scratch_at(c, off_gpart(c));
+    HIPCHK(c, launch_zero(gpart, (int64_t)ntiles * c->nz * 2, s));
+    auto run = [&](auto zero) -> int {
+        using R = decltype(zero);
+        AdjArgs<R> a;
+        memset(&a, 0, sizeof a);
+        for (int q = 0; q < 8; ++q) {
+            a.f[q] = c->buf[c->cur][q];
+            a.lam[q] = lam[q];
+        }
+        size_t half = align256(tab_bytes<R>(c));
+        a.tab_f = (const R *)scratch_at(c, off_tab(c));
+        a.tab_r = (const R *)scratch_at(c, off_tab(c) + half);
+        a.rx = (R)c->rx;
+        a.ry = (R)c->ry;
+        a.rz = (R)c->rz;
+        a.nx = (int)c->nx;
+        a.ny = (int)c->ny;
+        a.nz = (int)c->nz;
+        a.gpart = gpart;
+        for (int64_t t = 0; t < n; ++t)
+            for (int sw = 0; sw < 3; ++sw) HIPCHK(c, launch_adj3<R>(a, sw, s));
+        return DIRAC_OK;
+    };
+    rc = c->dtype == DIRAC_C64 ? run(0.0f) : run(0.0);
+    if (rc) return rc;
+    HIPCHK(c, launch_adj_finish(gpart, ntiles, (int)c->nz, 0.5 * c->dt, (double *)dLdV_int, (double *)dLdV_half, s));
+    return DIRAC_OK;
+}
+
+}  // extern "C"

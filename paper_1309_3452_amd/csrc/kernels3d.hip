@@ -1,0 +1,308 @@
+// (3+1)D kernels: split half-steps (in place), conserved-functional and
+// observable reductions, adjoint seed and per-site theta fields.
+//
+// Stencils (cell (i,j,k), periodic; the position of each array's amplitude is
+// A0 (i,j,k), A1 (i+1/2,j+1/2,k), B0 (i+1/2,j,k+1/2), B1 (i,j+1/2,k+1/2),
+// C0 (i,j,k+1/2), C1 (i+1/2,j+1/2,k+1/2), D0 (i+1/2,j,k), D1 (i,j+1/2,k)).
+// Written out from Eqs. ss1-ss4 (centred differences over one cell):
+//   S_A0 =  rz(C0 - C0[k-1]) + rx(D0 - D0[i-1]) - i ry(D1 - D1[j-1])
+//   S_A1 =  rz(C1 - C1[k-1]) + rx(D1[i+1] - D1) - i ry(D0[j+1] - D0)
+//   S_B0 = -rz(D0[k+1] - D0) + rx(C0[i+1] - C0) + i ry(C1 - C1[j-1])
+//   S_B1 = -rz(D1[k+1] - D1) + rx(C1 - C1[i-1]) + i ry(C0[j+1] - C0)
+//   S_C0 =  rz(A0[k+1] - A0) + rx(B0 - B0[i-1]) - i ry(B1 - B1[j-1])
+//   S_C1 =  rz(A1[k+1] - A1) + rx(B1[i+1] - B1) - i ry(B0[j+1] - B0)
+//   S_D0 = -rz(B0 - B0[k-1]) + rx(A0[i+1] - A0) + i ry(A1 - A1[j-1])
+//   S_D1 = -rz(B1 - B1[k-1]) + rx(A1 - A1[i-1]) + i ry(A0[j+1] - A0)
+#include "device.h"
+#include "internal.h"
+#include "stencil3.h"
+
+namespace dirac {
+
+namespace {
+
+constexpr int kTX = 64, kTY = 4;
+
+template <typename R> __device__ __forceinline__ Coef<R> tab_coef(const R *tab, int q, int nz, int k) {
+    const R *e = tab + ((size_t)q * nz + k) * 4;
+    Coef<R> c;
+    c.c1 = mk2(e[0], e[1]);
+    c.c2 = mk2(e[2], e[3]);
+    return c;
+}
+
+template <typename R, bool SITE>
+__device__ __forceinline__ Coef<R> coef_at(const HalfArgs<R> &a, int arr, int q, int k, size_t c) {
+    if constexpr (SITE) {
+        return coef_theta((R)(a.tsgn * a.th[arr][c]));
+    } else {
+        return tab_coef(a.tab, q, a.nz, k);
+    }
+}
+
+// which == 0: A,B from C,D (Eqs. ss1, ss2); which == 1: C,D from A,B (ss3, ss4).
+template <typename R, bool SITE, int WHICH>
+__global__ __launch_bounds__(256) void k3_half(HalfArgs<R> a) {
+    using C = cx<R>;
+    const int nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int k = b / nby;
+    const int i = bx * kTX + (threadIdx.x & (kTX - 1));
+    const int j = by * kTY + (threadIdx.x / kTX);
+    if (i >= a.nx || j >= a.ny) return;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t row = (size_t)j * a.nx;
+    const size_t kk = (size_t)k * plane;
+    const int im = wrap_dec(i, a.nx), ip = wrap_inc(i, a.nx);
+    const int jm = wrap_dec(j, a.ny), jp = wrap_inc(j, a.ny);
+    const int km = wrap_dec(k, a.nz), kp = wrap_inc(k, a.nz);
+    const size_t c = kk + row + i;
+    const size_t xm = kk + row + im, xp = kk + row + ip;
+    const size_t ym = kk + (size_t)jm * a.nx + i, yp = kk + (size_t)jp * a.nx + i;
+    const size_t zm = (size_t)km * plane + row + i, zp = (size_t)kp * plane + row + i;
+    C *f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = (C *)a.f[q];
+    if constexpr (WHICH == 0) {
+        St3<C> s = stencil_ab<C, R>(a.rx, a.ry, a.rz,
+                                     f[4][c], f[4][zm], f[4][xp], f[4][yp],
+                                     f[5][c], f[5][zm], f[5][ym], f[5][xm],
+                                     f[6][c], f[6][xm], f[6][yp], f[6][zp],
+                                     f[7][c], f[7][ym], f[7][xp], f[7][zp]);
+        f[0][c] = update(f[0][c], s.s0, coef_at<R, SITE>(a, 0, 0, k, c));
+        f[1][c] = update(f[1][c], s.s1, coef_at<R, SITE>(a, 1, 0, k, c));
+        f[2][c] = update(f[2][c], s.s2, coef_at<R, SITE>(a, 2, 1, k, c));
+        f[3][c] = update(f[3][c], s.s3, coef_at<R, SITE>(a, 3, 1, k, c));
+    } else {
+        St3<C> s = stencil_cd<C, R>(a.rx, a.ry, a.rz,
+                                     f[0][c], f[0][zp], f[0][xp], f[0][yp],
+                                     f[1][c], f[1][zp], f[1][xm], f[1][ym],
+                                     f[2][c], f[2][zm], f[2][xm], f[2][yp],
+                                     f[3][c], f[3][zm], f[3][xp], f[3][ym]);
+        f[4][c] = update(f[4][c], s.s0, coef_at<R, SITE>(a, 4, 2, k, c));
+        f[5][c] = update(f[5][c], s.s1, coef_at<R, SITE>(a, 5, 2, k, c));
+        f[6][c] = update(f[6][c], s.s2, coef_at<R, SITE>(a, 6, 3, k, c));
+        f[7][c] = update(f[7][c], s.s3, coef_at<R, SITE>(a, 7, 3, k, c));
+    }
+}
+
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ double re_conj_mul(double2 x, double2 s) { return x.x * s.x + x.y * s.y; }
+__device__ __forceinline__ double abs2(double2 x) { return x.x * x.x + x.y * x.y; }
+
+// Cell (i,j,k) of a flattened index.
+__device__ __forceinline__ void cell_of(int64_t t, int nx, int ny, int &i, int &j, int &k) {
+    int64_t q = t / nx;
+    i = (int)(t - q * nx);
+    k = (int)(q / ny);
+    j = (int)(q - (int64_t)k * ny);
+}
+
+// Per-block partial sums of (E_r terms, C,D-side terms, plain norm), FP64.
+template <typename R>
+__global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
+    using C = cx<R>;
+    __shared__ double lds[kNormVals * 16];
+    const C *f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = (const C *)a.f[q];
+    const double rx = a.rx, ry = a.ry, rz = a.rz;
+    double v[kNormVals] = {0.0, 0.0, 0.0};
+    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
+    const size_t plane = (size_t)a.nx * a.ny;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_of(t, a.nx, a.ny, i, j, k);
+        const size_t row = (size_t)j * a.nx, kk = (size_t)k * plane;
+        const size_t c = kk + row + i;
+        const size_t xm = kk + row + wrap_dec(i, a.nx), xp = kk + row + wrap_inc(i, a.nx);
+        const size_t ym = kk + (size_t)wrap_dec(j, a.ny) * a.nx + i, yp = kk + (size_t)wrap_inc(j, a.ny) * a.nx + i;
+        const size_t zm = (size_t)wrap_dec(k, a.nz) * plane + row + i, zp = (size_t)wrap_inc(k, a.nz) * plane + row + i;
+        double2 x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = to_d(f[q][c]);
+        St3<double2> sab = stencil_ab<double2, double>(rx, ry, rz,
+            x[4], to_d(f[4][zm]), to_d(f[4][xp]), to_d(f[4][yp]),
+            x[5], to_d(f[5][zm]), to_d(f[5][ym]), to_d(f[5][xm]),
+            x[6], to_d(f[6][xm]), to_d(f[6][yp]), to_d(f[6][zp]),
+            x[7], to_d(f[7][ym]), to_d(f[7][xp]), to_d(f[7][zp]));
+        St3<double2> scd = stencil_cd<double2, double>(rx, ry, rz,
+            x[0], to_d(f[0][zp]), to_d(f[0][xp]), to_d(f[0][yp]),
+            x[1], to_d(f[1][zp]), to_d(f[1][xm]), to_d(f[1][ym]),
+            x[2], to_d(f[2][zm]), to_d(f[2][xm]), to_d(f[2][yp]),
+            x[3], to_d(f[3][zm]), to_d(f[3][xp]), to_d(f[3][ym]));
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) p += abs2(x[q]);
+        v[0] -= re_conj_mul(x[0], sab.s0) + re_conj_mul(x[1], sab.s1) + re_conj_mul(x[2], sab.s2) +
+                re_conj_mul(x[3], sab.s3);
+        v[1] += re_conj_mul(x[4], scd.s0) + re_conj_mul(x[5], scd.s1) + re_conj_mul(x[6], scd.s2) +
+                re_conj_mul(x[7], scd.s3);
+        v[0] += p;
+        v[1] += p;
+        v[2] += p;
+    }
+    block_sum<kNormVals>(v, lds);
+    if (threadIdx.x == 0) {
+        double *o = a.partial + (size_t)blockIdx.x * kNormVals;
+        o[0] = v[0];
+        o[1] = v[1];
+        o[2] = v[2];
+    }
+}
+
+__constant__ float kOff3[8][3] = {{0.f, 0.f, 0.f}, {.5f, .5f, 0.f}, {.5f, 0.f, .5f}, {0.f, .5f, .5f},
+                                  {0.f, 0.f, .5f}, {.5f, .5f, .5f}, {.5f, 0.f, 0.f}, {0.f, .5f, 0.f}};
+
+template <typename R>
+__global__ __launch_bounds__(kReduceThreads) void k3_obs(ReduceArgs<R> a) {
+    using C = cx<R>;
+    __shared__ double lds[kObsVals * 16];
+    double v[kObsVals];
+#pragma unroll
+    for (int q = 0; q < kObsVals; ++q) v[q] = 0.0;
+    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_of(t, a.nx, a.ny, i, j, k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double p = abs2(to_d(((const C *)a.f[q])[t]));
+            double x = (double)i + (double)kOff3[q][0];
+            double y = (double)j + (double)kOff3[q][1];
+            double z = (double)k + (double)kOff3[q][2];
+            if (z >= a.z0) v[0] += p;
+            v[1] += x * p;
+            v[2] += y * p;
+            v[3] += z * p;
+            v[4] += p;
+            v[5 + q / 2] += p;
+        }
+    }
+    block_sum<kObsVals>(v, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kObsVals; ++q) a.partial[(size_t)blockIdx.x * kObsVals + q] = v[q];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k3_seed(ReduceArgs<R> a, CPtr8 lam) {
+    using C = cx<R>;
+    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_of(t, a.nx, a.ny, i, j, k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double z = (double)k + (double)kOff3[q][2];
+            C x = ((const C *)a.f[q])[t];
+            R w = (z >= a.z0) ? (R)2 : (R)0;
+            ((C *)lam.p[q])[t] = mk2(w * x.x, w * x.y);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_theta_fields(CPtr8 th, CPtr8 v, int narr, int64_t ncell, double half_dt,
+                                                       double m) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        for (int q = 0; q < narr; ++q) {
+            // + for the first sheet's arrays (A,B / u), - for the second (C,D / v)
+            double sgn = (q < narr / 2) ? 1.0 : -1.0;
+            double vv = v.p[q] ? (double)((const R *)v.p[q])[t] : 0.0;
+            ((R *)th.p[q])[t] = (R)(half_dt * (sgn * m + vv));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_final_sum(const double *partial, int nblocks, int nv, double *out) {
+    __shared__ double lds[16 * 16];
+    // one value at a time, fixed order: thread t sums blocks t, t+256, ...
+    for (int q = 0; q < nv; ++q) {
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v[0] += partial[(size_t)b * nv + q];
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) out[q] = v[0];
+        __syncthreads();
+    }
+}
+
+inline int grid_for(int64_t n, int threads, int cap) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_half3(const HalfArgs<R> &a, int which, bool site, hipStream_t s) {
+    const int64_t nblk = (int64_t)((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY) * a.nz;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 g((unsigned)nblk), b(kTX * kTY);
+    if (which == 0) {
+        if (site) hipLaunchKernelGGL((k3_half<R, true, 0>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k3_half<R, false, 0>), g, b, 0, s, a);
+    } else {
+        if (site) hipLaunchKernelGGL((k3_half<R, true, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k3_half<R, false, 1>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename R> hipError_t launch_norm3(const ReduceArgs<R> &a, hipStream_t s) {
+    hipLaunchKernelGGL((k3_norm<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R> hipError_t launch_obs3(const ReduceArgs<R> &a, hipStream_t s) {
+    hipLaunchKernelGGL((k3_obs<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R> hipError_t launch_seed3(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s) {
+    CPtr8 l;
+    for (int q = 0; q < 8; ++q) l.p[q] = lam[q];
+    const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+    hipLaunchKernelGGL((k3_seed<R>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, a, l);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_theta_fields(void *const th[8], void *const v[8], int narr, int64_t ncell, double half_dt,
+                               double m, hipStream_t s) {
+    CPtr8 t, vv;
+    for (int q = 0; q < 8; ++q) {
+        t.p[q] = q < narr ? th[q] : nullptr;
+        vv.p[q] = (q < narr && v) ? v[q] : nullptr;
+    }
+    hipLaunchKernelGGL((k_theta_fields<R>), dim3(grid_for(ncell, 256, 8192)), dim3(256), 0, s, t, vv, narr, ncell,
+                       half_dt, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_sum(const double *partial, int nblocks, int nv, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, partial, nblocks, nv, out);
+    return hipGetLastError();
+}
+
+#define INST(R)                                                                                             \
+    template hipError_t launch_half3<R>(const HalfArgs<R> &, int, bool, hipStream_t);                       \
+    template hipError_t launch_norm3<R>(const ReduceArgs<R> &, hipStream_t);                                \
+    template hipError_t launch_obs3<R>(const ReduceArgs<R> &, hipStream_t);                                 \
+    template hipError_t launch_seed3<R>(const ReduceArgs<R> &, void *const[8], hipStream_t);               \
+    template hipError_t launch_theta_fields<R>(void *const[8], void *const[8], int, int64_t, double, double, \
+                                               hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace dirac

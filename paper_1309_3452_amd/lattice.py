@@ -1,0 +1,181 @@
+"""Single lattices on the GPU: torch owns the device memory and the stream,
+libdirac.so does every step of the computation (argument marshalling only here).
+
+Array convention (Sect. 2, Eq. ABCDgrid; Sect. 3): a (3+1)D state is 8 complex
+tensors of shape (nz, ny, nx) -- A0, A1, B0, B1 on time sheet n-1/2 and C0, C1,
+D0, D1 on sheet n; a (2+1)D state is 4 tensors of shape (ny, nx): u0, u1
+(sheet n-1/2), v0, v1 (sheet n).  Site positions are in include/dirac.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _abi
+from ._abi import check, lib, ptr_array
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(dtype):
+    if dtype == torch.complex64:
+        return _abi.DIRAC_C64
+    if dtype == torch.complex128:
+        return _abi.DIRAC_C128
+    raise ValueError("dtype must be torch.complex64 or torch.complex128")
+
+
+class Lattice:
+    """A periodic (2+1)D or (3+1)D lattice of the staggered leap-frog scheme.
+
+    shape: (nx, ny) or (nx, ny, nz) cells; dt: time step; d: grid spacings.
+    """
+
+    def __init__(self, shape: Sequence[int], dtype=torch.complex128, dt: float = 0.5, d=None,
+                 allow_unstable: bool = False, device="cuda"):
+        if len(shape) not in (2, 3):
+            raise ValueError("shape must have 2 or 3 entries")
+        self.ndim = len(shape)
+        self.nx, self.ny = int(shape[0]), int(shape[1])
+        self.nz = int(shape[2]) if self.ndim == 3 else 1
+        self.dtype = dtype
+        self.real_dtype = torch.float32 if dtype == torch.complex64 else torch.float64
+        self.dt = float(dt)
+        d = tuple(d) if d is not None else (1.0,) * self.ndim
+        self.device = torch.device(device)
+        self.narr = 8 if self.ndim == 3 else 4
+        self.tshape = (self.nz, self.ny, self.nx) if self.ndim == 3 else (self.ny, self.nx)
+        ctx = ctypes.c_void_p()
+        dz = d[2] if self.ndim == 3 else 1.0
+        flags = _abi.DIRAC_ALLOW_UNSTABLE if allow_unstable else 0
+        check(lib().dirac_create(ctypes.byref(ctx), self.ndim, self.nx, self.ny, self.nz, _dtype_code(dtype),
+                                 self.dt, float(d[0]), float(d[1]), float(dz), flags))
+        self._ctx = ctx
+        self.bufs = [[torch.zeros(self.tshape, dtype=dtype, device=self.device) for _ in range(self.narr)]
+                     for _ in range(2)]
+        check(lib().dirac_bind_state(ctx, ptr_array([t.data_ptr() for t in self.bufs[0]]),
+                                     ptr_array([t.data_ptr() for t in self.bufs[1]])), ctx)
+        nbytes = ctypes.c_size_t()
+        check(lib().dirac_scratch_bytes(ctx, ctypes.byref(nbytes)), ctx)
+        self.scratch = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.scratch.data_ptr()
+        aligned = (base + 255) & ~255
+        check(lib().dirac_bind_scratch(ctx, ctypes.c_void_p(aligned), int(nbytes.value)), ctx)
+        self.theta = None
+        self._norm_out = torch.zeros(3, dtype=torch.float64, device=self.device)
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                lib().dirac_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    # -- state ---------------------------------------------------------------
+    @property
+    def current(self) -> int:
+        w = ctypes.c_int()
+        check(lib().dirac_current(self._ctx, ctypes.byref(w)), self._ctx)
+        return int(w.value)
+
+    def state(self):
+        """The tensors currently holding the state (views, not copies)."""
+        return self.bufs[self.current]
+
+    def load(self, arrays):
+        """Copy a state (sequence of narr arrays/tensors) into the current buffers."""
+        if len(arrays) != self.narr:
+            raise ValueError("expected %d arrays" % self.narr)
+        cur = self.state()
+        for t, a in zip(cur, arrays):
+            src = torch.as_tensor(a)
+            if tuple(src.shape) != self.tshape:
+                raise ValueError("array shape %s != %s" % (tuple(src.shape), self.tshape))
+            t.copy_(src.to(device=self.device, dtype=self.dtype))
+
+    # -- coefficients --------------------------------------------------------
+    def set_potential_z(self, m: float, v_int=None, v_half=None):
+        """Mass m and V(z) sampled at integer (v_int) and half-integer (v_half) z."""
+        if v_int is None:
+            check(lib().dirac_set_mass_potential_z(self._ctx, float(m), None, None, self.nz), self._ctx)
+            return
+        import numpy as np
+        vi = np.ascontiguousarray(v_int, dtype=np.float64)
+        vh = np.ascontiguousarray(v_half, dtype=np.float64)
+        if vi.shape != (self.nz,) or vh.shape != (self.nz,):
+            raise ValueError("v_int and v_half need nz entries")
+        check(lib().dirac_set_mass_potential_z(self._ctx, float(m), vi.ctypes.data_as(ctypes.c_void_p),
+                                               vh.ctypes.data_as(ctypes.c_void_p), self.nz), self._ctx)
+        self._pin = (vi, vh)
+
+    def set_fields(self, m: float, v_site=None):
+        """Per-site potential: v_site[a] holds V at the sites of state array a."""
+        self.theta = [torch.empty(self.tshape, dtype=self.real_dtype, device=self.device)
+                      for _ in range(self.narr)]
+        vs = None
+        if v_site is not None:
+            vs = [torch.as_tensor(v).to(device=self.device, dtype=self.real_dtype).contiguous() for v in v_site]
+            self._vsite = vs
+        check(lib().dirac_theta_from_fields(
+            self._ctx, float(m), ptr_array([v.data_ptr() for v in vs]) if vs is not None else None,
+            ptr_array([t.data_ptr() for t in self.theta]), _stream_handle()), self._ctx)
+
+    def set_kernel(self, kind: str = "auto", tile_y: int = 0, zchunk: int = 0):
+        code = {"auto": _abi.DIRAC_KERNEL_AUTO, "split": _abi.DIRAC_KERNEL_SPLIT,
+                "fused": _abi.DIRAC_KERNEL_FUSED}[kind]
+        check(lib().dirac_set_kernel(self._ctx, code, int(tile_y), int(zchunk)), self._ctx)
+
+    # -- time stepping -------------------------------------------------------
+    def step(self, n: int = 1):
+        check(lib().dirac_step(self._ctx, int(n), _stream_handle()), self._ctx)
+
+    def reverse(self, n: int = 1):
+        check(lib().dirac_reverse(self._ctx, int(n), _stream_handle()), self._ctx)
+
+    # -- reductions ----------------------------------------------------------
+    def norm(self):
+        """(E_r, E_r summed on the C,D / v sites, plain norm) in FP64; synchronous."""
+        out = (ctypes.c_double * 3)()
+        check(lib().dirac_norm(self._ctx, out, _stream_handle()), self._ctx)
+        return tuple(out)
+
+    def norm_device(self, out: torch.Tensor = None) -> torch.Tensor:
+        """Asynchronous: the same three FP64 values written into a device tensor."""
+        out = self._norm_out if out is None else out
+        check(lib().dirac_norm_device(self._ctx, ctypes.c_void_p(out.data_ptr()), _stream_handle()), self._ctx)
+        return out
+
+    def observables(self, z0: float):
+        out = (ctypes.c_double * 9)()
+        check(lib().dirac_observables(self._ctx, float(z0), out, _stream_handle()), self._ctx)
+        return tuple(out)
+
+    # -- adjoint -------------------------------------------------------------
+    def seed_region(self, z0: float):
+        lam = [torch.empty(self.tshape, dtype=self.dtype, device=self.device) for _ in range(self.narr)]
+        check(lib().dirac_seed_region(self._ctx, float(z0), ptr_array([t.data_ptr() for t in lam]),
+                                      _stream_handle()), self._ctx)
+        return lam
+
+    def adjoint_vz(self, n: int, lam):
+        """Backward through n steps from the current (final) state; see dirac_adjoint_vz."""
+        dvi = torch.zeros(self.nz, dtype=torch.float64, device=self.device)
+        dvh = torch.zeros(self.nz, dtype=torch.float64, device=self.device)
+        check(lib().dirac_adjoint_vz(self._ctx, int(n), ptr_array([t.data_ptr() for t in lam]),
+                                     ctypes.c_void_p(dvi.data_ptr()), ctypes.c_void_p(dvh.data_ptr()),
+                                     _stream_handle()), self._ctx)
+        return dvi, dvh
+
+
+def Lattice3D(nx, ny, nz, **kw):
+    return Lattice((nx, ny, nz), **kw)
+
+
+def Lattice2D(nx, ny, **kw):
+    return Lattice((nx, ny), **kw)

@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/dirac.h declares, and validates arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1309_3452_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1309_3452_amd import build
+        build.build()
+    return _abi.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dirac.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dirac_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_1309_3452_amd import _abi
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_abi.EXPORTS) == names
+
+
+def _create(L, ndim=3, n=(8, 8, 8), dtype=2, dt=0.5, d=(1.0, 1.0, 1.0), flags=0):
+    c = ctypes.c_void_p()
+    rc = L.dirac_create(ctypes.byref(c), ndim, n[0], n[1], n[2], dtype, dt, d[0], d[1], d[2], flags)
+    return rc, c
+
+
+def test_create_validation(L):
+    import math
+    rc, c = _create(L)
+    assert rc == 0 and c.value
+    L.dirac_destroy(c)
+    # stability bound sum r_j^2 <= 1 (Sect. 2.2): r = 1/sqrt(3) passes, slightly above fails
+    assert _create(L, dt=1 / math.sqrt(3))[0] == 0
+    assert _create(L, dt=1.001 / math.sqrt(3))[0] == -3
+    assert _create(L, dt=1.001 / math.sqrt(3), flags=1)[0] == 0
+    assert _create(L, ndim=2, n=(8, 8, 1), dt=1 / math.sqrt(2))[0] == 0
+    assert _create(L, ndim=2, n=(8, 8, 1), dt=0.75)[0] == -3
+    # anisotropic spacing enters through r_j = dt / d_j
+    assert _create(L, dt=0.5, d=(1.0, 1.0, 0.5))[0] == -3
+    assert _create(L, ndim=4)[0] == -1
+    assert _create(L, dtype=3)[0] == -1
+    assert _create(L, n=(0, 8, 8))[0] == -2
+    assert _create(L, ndim=2, n=(8, 8, 2))[0] == -2
+    assert _create(L, dt=float("nan"))[0] == -1
+    assert _create(L, dt=-0.1)[0] == -1
+    assert _create(L, flags=8)[0] == -1
+
+
+def test_calls_out_of_order_are_rejected(L):
+    rc, c = _create(L)
+    assert rc == 0
+    out = (ctypes.c_double * 3)()
+    assert L.dirac_step(c, 1, None) == -6          # no state bound
+    assert b"no state bound" in L.dirac_last_error(c)
+    assert L.dirac_norm(c, out, None) == -6
+    nb = ctypes.c_size_t()
+    assert L.dirac_scratch_bytes(c, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.dirac_bind_scratch(c, ctypes.c_void_p(256), 16) == -2      # too small (checked before use)
+    assert L.dirac_bind_scratch(c, ctypes.c_void_p(255), nb.value) == -1   # misaligned
+    assert L.dirac_set_kernel(c, 7, 0, 0) == -1
+    assert L.dirac_set_kernel(c, 2, 5, 0) == -1
+    assert L.dirac_set_mass_potential_z(c, 0.5, None, None, 7) == -2   # nz mismatch
+    L.dirac_destroy(c)
+    L.dirac_destroy(None)
+
+
+def test_batch_create_validation(L):
+    c = ctypes.c_void_p()
+    nx = (ctypes.c_int64 * 2)(64, 96)
+    ny = (ctypes.c_int64 * 2)(32, 1)
+    assert L.dirac_batch_create(ctypes.byref(c), 2, nx, ny, 1, 0.6, 0) == 0
+    nb = ctypes.c_size_t()
+    assert L.dirac_scratch_bytes(c, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.dirac_batch_run(c, 1, 0, 0, None) == -6
+    L.dirac_destroy(c)
+    assert L.dirac_batch_create(ctypes.byref(c), 2, nx, ny, 1, 0.75, 0) == -3
+    bad = (ctypes.c_int64 * 2)(64, 0)
+    assert L.dirac_batch_create(ctypes.byref(c), 2, nx, bad, 1, 0.6, 0) == -2
+    assert L.dirac_batch_create(ctypes.byref(c), 0, nx, ny, 1, 0.6, 0) == -1
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.dirac_status_string(code)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_1309_3452_amd import _abi
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_abi, "_lib", None)
+    with pytest.raises(ImportError):
+        _abi.lib()

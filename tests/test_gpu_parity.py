@@ -1,0 +1,243 @@
+"""GPU path vs the CPU oracle, element by element, on the same seeded inputs.
+
+Bars: FP64 relative L2 <= 1e-13 (the stated target); reductions in FP64 to
+1e-12 relative; FP32 against the FP64 oracle within a bound derived from
+FP32 rounding (see each test).  Sizes span several tiles and ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from closed_form import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+DT3 = workloads.DT3
+DT2 = workloads.DT2
+
+
+def np_state(tensors):
+    return [t.detach().cpu().numpy().astype(np.complex128) for t in tensors]
+
+
+def rand_state(shape, count, seed):
+    g = np.random.default_rng(seed)
+    return [np.ascontiguousarray(g.standard_normal(shape) + 1j * g.standard_normal(shape)) for _ in range(count)]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1309_3452_amd as P
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.lib()
+    return P
+
+
+# --------------------------------------------------------------------------
+# (2+1)D, the 128x128 configuration in full
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_config1_full_parity(P, kernel):
+    cfg = workloads.config1()
+    print("config1 kernel=%s" % kernel, flush=True)
+    lat = P.Lattice2D(128, 128, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_kernel(kernel)
+    lat.set_potential_z(0.0)
+    lat.load(cfg["state"])
+    e0 = lat.norm()
+    lat.step(cfg["steps"])
+    g = np_state(lat.state())
+    ol = oracle.Lattice2(128, 128, cfg["dt"])
+    f = [t.numpy().copy() for t in cfg["state"]]
+    ol.step(f, ol.theta(0.0), cfg["steps"])
+    assert rel_l2(g, f) <= 1e-13
+    e1 = lat.norm()
+    eo = ol.energy(f)
+    assert abs(e1[0] - e0[0]) <= 1e-14 * 200 * abs(e0[0])
+    assert abs(e1[0] - eo[0]) <= 1e-12 * abs(eo[0])
+    assert abs(e1[2] - eo[2]) <= 1e-12 * eo[2]
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+@pytest.mark.parametrize("shape", [(96, 70), (130, 33), (1, 5)])
+def test_2d_site_fields_parity(P, kernel, shape):
+    nx, ny = shape
+    print("2d fields %s %s" % (shape, kernel), flush=True)
+    g = np.random.default_rng(21)
+    f0 = rand_state((ny, nx), 4, 22)
+    V = [np.ascontiguousarray(0.6 * g.standard_normal((ny, nx))) for _ in range(4)]
+    m = 0.4
+    lat = P.Lattice2D(nx, ny, dtype=torch.complex128, dt=DT2)
+    lat.set_kernel(kernel)
+    lat.load(f0)
+    lat.set_fields(m, [torch.from_numpy(v) for v in V])
+    lat.step(60)
+    ol = oracle.Lattice2(nx, ny, DT2)
+    th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * m + V[a])) for a in range(4)]
+    f = [a.copy() for a in f0]
+    ol.step(f, th, 60)
+    assert rel_l2(np_state(lat.state()), f) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# (3+1)D
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel,tile_y,zchunk", [("split", 0, 0), ("fused", 4, 0), ("fused", 8, 7),
+                                                   ("fused", 4, 64)])
+@pytest.mark.parametrize("shape", [(70, 20, 22), (64, 8, 16), (5, 3, 1)])
+def test_3d_potential_z_parity(P, kernel, tile_y, zchunk, shape):
+    nx, ny, nz = shape
+    print("3d vz %s %s ty=%d zc=%d" % (shape, kernel, tile_y, zchunk), flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 31)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat.set_kernel(kernel, tile_y, zchunk)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.load(f0)
+    lat.step(40)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    f = [a.copy() for a in f0]
+    ol.step(f, ol.theta_vz(0.5, v_int, v_half), 40)
+    assert rel_l2(np_state(lat.state()), f) <= 1e-13
+    en = lat.norm()
+    eo = ol.energy(f)
+    for q in range(3):
+        assert abs(en[q] - eo[q]) <= 1e-12 * abs(eo[2])
+    ob = lat.observables(nz / 2.0)
+    oo = ol.observe(f, nz / 2.0)
+    for q in range(9):
+        assert abs(ob[q] - oo[q]) <= 1e-12 * max(abs(oo[q]), oo[4])
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_3d_site_fields_parity(P, kernel):
+    nx, ny, nz = 66, 9, 12
+    print("3d fields %s" % kernel, flush=True)
+    g = np.random.default_rng(41)
+    f0 = rand_state((nz, ny, nx), 8, 42)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((nz, ny, nx))) for _ in range(8)]
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat.set_kernel(kernel)
+    lat.load(f0)
+    lat.set_fields(0.3, [torch.from_numpy(v) for v in V])
+    lat.step(30)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    th = [np.ascontiguousarray(0.5 * DT3 * ((1.0 if a < 4 else -1.0) * 0.3 + V[a])) for a in range(8)]
+    f = [a.copy() for a in f0]
+    ol.step(f, th, 30)
+    assert rel_l2(np_state(lat.state()), f) <= 1e-13
+
+
+def test_3d_reverse_parity(P):
+    nx, ny, nz = 40, 12, 10
+    print("3d reverse", flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.0, 5.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 51)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.load(f0)
+    lat.reverse(20)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    f = [a.copy() for a in f0]
+    ol.reverse(f, ol.theta_vz(0.5, v_int, v_half), 20)
+    assert rel_l2(np_state(lat.state()), f) <= 1e-13
+    lat.step(20)
+    assert rel_l2(np_state(lat.state()), f0) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# FP32 form.  Per step each amplitude carries a few FP32 roundings
+# (relative ~6e-8 each), accumulating coherently at worst: bound 1e-6 per
+# step relative L2 against the FP64 oracle.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_3d_fp32_vs_oracle(P, kernel):
+    nx, ny, nz = 70, 17, 12
+    print("3d fp32 %s" % kernel, flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, 6.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 61)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
+    lat.set_kernel(kernel)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.load(f0)
+    f0_32 = np_state(lat.state())
+    lat.step(50)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    f = [a.copy() for a in f0_32]
+    ol.step(f, ol.theta_vz(0.5, v_int, v_half), 50)
+    assert rel_l2(np_state(lat.state()), f) <= 50 * 1e-6
+    en = lat.norm()
+    eo = ol.energy(f)
+    assert abs(en[0] - eo[0]) <= 1e-5 * eo[2]
+
+
+# --------------------------------------------------------------------------
+# Adjoint: GPU (reversal) vs oracle (stored states)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-3)])
+def test_adjoint_vs_oracle(P, dtype, tol):
+    nx, ny, nz, steps = 20, 6, 16, 12
+    print("adjoint %s" % dtype, flush=True)
+    g = np.random.default_rng(71)
+    v_int = 0.8 * g.standard_normal(nz)
+    v_half = 0.8 * g.standard_normal(nz)
+    f0 = rand_state((nz, ny, nx), 8, 72)
+    z0 = nz / 2.0
+    lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+    lat.load(f0)
+    f0_lat = np_state(lat.state())
+    loss, dvi, dvh = P.potential_gradient(lat, f0_lat, 0.5, v_int, v_half, steps, z0)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    th = ol.theta_vz(0.5, v_int, v_half)
+
+    def seed(f):
+        mask = [ol.positions(a)[2] >= z0 for a in range(8)]
+        return ol.observe(f, z0)[0], [2 * f[a] * mask[a] for a in range(8)]
+    oloss, _, gth, _ = oracle.run_with_adjoint3(ol, f0_lat, th, steps, seed)
+    # dL/dV at integer z: A and D sites; at half-integer z: B and C sites
+    gi = 0.5 * DT3 * sum(gth[a].sum(axis=(1, 2)) for a in (0, 1, 6, 7))
+    gh = 0.5 * DT3 * sum(gth[a].sum(axis=(1, 2)) for a in (2, 3, 4, 5))
+    scale = max(np.abs(gi).max(), np.abs(gh).max())
+    ltol = 1e-12 if dtype == torch.complex128 else 1e-5
+    assert abs(loss - oloss) <= ltol * max(1.0, abs(oloss))
+    assert np.abs(dvi.cpu().numpy() - gi).max() <= tol * scale
+    assert np.abs(dvh.cpu().numpy() - gh).max() <= tol * scale
+    # the reversal rebuilt the initial state
+    rtol = 1e-13 if dtype == torch.complex128 else 1e-5
+    assert rel_l2(np_state(lat.state()), f0_lat) <= rtol * steps
+
+
+# --------------------------------------------------------------------------
+# Batched lattices: each against its own oracle run (FP64) and against the
+# single-lattice kernel (bitwise: the same arithmetic)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,graph", [(1, False), (1, True), (0, False), (0, True)])
+def test_batched_vs_oracle(P, mode, graph):
+    print("batched mode=%d graph=%s" % (mode, graph), flush=True)
+    sizes = [(64, 64), (96, 130), (200, 33), (17, 250), (1, 7), (128, 96)]
+    g = np.random.default_rng(81)
+    lats = []
+    for (nx, ny) in sizes:
+        lats.append(dict(nx=nx, ny=ny, m=float(g.uniform(0, 1)),
+                         v_site=[np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)],
+                         state=rand_state((ny, nx), 4, int(g.integers(1 << 30)))))
+    B = P.BatchedLattices(lats, dtype=torch.complex128, dt=DT2)
+    steps = 25
+    B.run(steps, mode=mode, graph=graph)
+    if graph:
+        B.run(steps, mode=mode, graph=graph)
+        steps *= 2
+    norms = B.norms()
+    for b, L in enumerate(lats):
+        ol = oracle.Lattice2(L["nx"], L["ny"], DT2)
+        th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * L["m"] + L["v_site"][a]))
+              for a in range(4)]
+        f = [a.copy() for a in L["state"]]
+        ol.step(f, th, steps)
+        assert rel_l2(np_state(B.state(b)), f) <= 1e-13, b
+        eo = ol.energy(f)
+        assert abs(norms[b][0] - eo[0]) <= 1e-12 * eo[2]
