@@ -10,8 +10,8 @@
 // of plane p-1 (Eqs. ss3, ss4) from LDS and registers.  The halo ring is
 // recomputed from the old state rather than exchanged, so workgroups never
 // read each other's results: the state ping-pongs between two buffers.
-// Per cell the old C(p-1), D(p), D(p-1) and new B(p-1), B(p-2) ride along the
-// march in registers.  A chunk [z0, z1) runs planes z0-1 .. z1 so that its
+// The old C,D planes are staged in LDS by coalesced row loads (one plane ahead,
+// software-prefetched into registers), so the ring needs no extra global reads.  A chunk [z0, z1) runs planes z0-1 .. z1 so that its
 // first and last C,D planes have their A,B neighbours; periodic wrap in z is
 // a modulo on the plane index.
 //
@@ -51,76 +51,141 @@ __device__ __forceinline__ Coef<R> fcoef(const FusedArgs<R> &a, int arr, int cls
     }
 }
 
-// New value of A,B array Q (0: A0, 1: A1, 2: B0, 3: B1) at cell (gi, gj) of
-// plane pk, everything loaded from the old state (halo cells).
-template <typename R, bool SITE, int Q>
-__device__ __forceinline__ cx<R> h1_at(const FusedArgs<R> &a, int gi, int gj, int pk) {
-    using C = cx<R>;
-    const size_t plane = (size_t)a.nx * a.ny;
-    const size_t P = (size_t)pk * plane;
-    const size_t row = (size_t)gj * a.nx;
-    const size_t c = P + row + gi;
-    const C *in[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) in[q] = (const C *)a.in[q];
-    const R rx = a.rx, ry = a.ry, rz = a.rz;
-    C s;
-    if constexpr (Q == 0) {      // S_A0 = rz(C0 - C0[k-1]) + rx(D0 - D0[i-1]) - i ry(D1 - D1[j-1])
-        const size_t zm = (size_t)wrap_dec(pk, a.nz) * plane + row + gi;
-        const size_t xm = P + row + wrap_dec(gi, a.nx), ym = P + (size_t)wrap_dec(gj, a.ny) * a.nx + gi;
-        s = cadd(cadd(cscale(rz, csub(in[4][c], in[4][zm])), cscale(rx, csub(in[6][c], in[6][xm]))),
-                 ciscale(-ry, csub(in[7][c], in[7][ym])));
-    } else if constexpr (Q == 1) {   // S_A1 = rz(C1 - C1[k-1]) + rx(D1[i+1] - D1) - i ry(D0[j+1] - D0)
-        const size_t zm = (size_t)wrap_dec(pk, a.nz) * plane + row + gi;
-        const size_t xp = P + row + wrap_inc(gi, a.nx), yp = P + (size_t)wrap_inc(gj, a.ny) * a.nx + gi;
-        s = cadd(cadd(cscale(rz, csub(in[5][c], in[5][zm])), cscale(rx, csub(in[7][xp], in[7][c]))),
-                 ciscale(-ry, csub(in[6][yp], in[6][c])));
-    } else if constexpr (Q == 2) {   // S_B0 = -rz(D0[k+1] - D0) + rx(C0[i+1] - C0) + i ry(C1 - C1[j-1])
-        const size_t zp = (size_t)wrap_inc(pk, a.nz) * plane + row + gi;
-        const size_t xp = P + row + wrap_inc(gi, a.nx), ym = P + (size_t)wrap_dec(gj, a.ny) * a.nx + gi;
-        s = cadd(cadd(cscale(-rz, csub(in[6][zp], in[6][c])), cscale(rx, csub(in[4][xp], in[4][c]))),
-                 ciscale(ry, csub(in[5][c], in[5][ym])));
-    } else {                         // S_B1 = -rz(D1[k+1] - D1) + rx(C1 - C1[i-1]) + i ry(C0[j+1] - C0)
-        const size_t zp = (size_t)wrap_inc(pk, a.nz) * plane + row + gi;
-        const size_t xm = P + row + wrap_dec(gi, a.nx), yp = P + (size_t)wrap_inc(gj, a.ny) * a.nx + gi;
-        s = cadd(cadd(cscale(-rz, csub(in[7][zp], in[7][c])), cscale(rx, csub(in[5][c], in[5][xm]))),
-                 ciscale(ry, csub(in[4][yp], in[4][c])));
-    }
-    return update(in[Q][c], s, fcoef<R, SITE>(a, Q, Q / 2, pk, c));
+// Load/store through a wave-uniform base pointer and a 32-bit per-lane byte
+// offset (scalar-base addressing: one VGPR per offset instead of a 64-bit
+// address per load).
+template <typename C> __device__ __forceinline__ C ldo(const C *base, uint32_t boff) {
+    return *(const C *)((const char *)base + boff);
+}
+template <typename C> __device__ __forceinline__ void sto(C *base, uint32_t boff, C v) {
+    *(C *)((char *)base + boff) = v;
 }
 
-template <typename R, bool SITE, int TY>
-__global__ __launch_bounds__(kTX *TY) void k3_fused(FusedArgs<R> a) {
+// CPT consecutive cells along x moved as one access (two complex64 = 16 bytes).
+template <typename C, int CPT> struct Cells {
+    C v[CPT];
+};
+template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> ldv(const C *base, uint32_t boff) {
+    Cells<C, CPT> r;
+    if constexpr (CPT == 1) {
+        r.v[0] = ldo(base, boff);
+    } else {
+        const float4 q = *(const float4 *)((const char *)base + boff);
+        r.v[0] = mk2(q.x, q.y);
+        r.v[1] = mk2(q.z, q.w);
+    }
+    return r;
+}
+template <typename C, int CPT> __device__ __forceinline__ void stv(C *base, uint32_t boff, const Cells<C, CPT> &c) {
+    if constexpr (CPT == 1) {
+        sto(base, boff, c.v[0]);
+    } else {
+        *(float4 *)((char *)base + boff) = make_float4(c.v[0].x, c.v[0].y, c.v[1].x, c.v[1].y);
+    }
+}
+template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> lds_v(const C *p) {
+    Cells<C, CPT> r;
+    if constexpr (CPT == 1) {
+        r.v[0] = p[0];
+    } else {
+        const float4 q = *(const float4 *)p;
+        r.v[0] = mk2(q.x, q.y);
+        r.v[1] = mk2(q.z, q.w);
+    }
+    return r;
+}
+template <typename C, int CPT> __device__ __forceinline__ void lds_st(C *p, const Cells<C, CPT> &c) {
+    if constexpr (CPT == 1) {
+        p[0] = c.v[0];
+    } else {
+        *(float4 *)p = make_float4(c.v[0].x, c.v[0].y, c.v[1].x, c.v[1].y);
+    }
+}
+
+// Asynchronous global -> LDS copy of LB bytes per lane: lane l's bytes land at
+// lds_wave_base + l * LB (lds_wave_base must be the same for the whole wave).
+// Completion is tracked by the vector-memory counter (wait vmcnt(0), then a
+// barrier, before the LDS is read).
+template <int LB> __device__ __forceinline__ void g2lds(const void *gsrc, void *lds_wave_base) {
+    static_assert(LB == 16 || LB == 4, "copy width");
+    if constexpr (LB == 16)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)gsrc,
+                                         (__attribute__((address_space(3))) void *)lds_wave_base, 16, 0, 0);
+    else
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)gsrc,
+                                         (__attribute__((address_space(3))) void *)lds_wave_base, 4, 0, 0);
+}
+
+// Plane-by-plane schedule of one workgroup (tile (64 CPT) x TY cells, chunk
+// [z0, z1) of planes; lane l of row y owns the CPT cells x = l CPT + c):
+//   iteration p:  (the old C(p) and D(p+1) regions -- tile plus a one-cell
+//                 ring, corners included -- are already in LDS)
+//                 start the global->LDS copies of C(p+1), D(p+2) and register
+//                 loads of the next A,B; new A,B(p) for the tile and for the
+//                 ring cells the C,D stencils need (Eqs. ss1, ss2); new
+//                 C,D(p-1) for the tile from the new A,B(p-1) in LDS and
+//                 registers (Eqs. ss3, ss4); barrier; new A,B(p) into LDS;
+//                 wait for the copies; barrier.
+// Ring cells (the new A,B the tile's C,D stencils read outside it): left
+// column x = -1: A1, B0; right column x = w: A0, B1; bottom row y = -1: A1,
+// B1; top row y = h: A0, B0.  LDS holds C of 2 planes (2 arrays each), D of
+// 3 planes (2 arrays each) and the new A,B(p-1) (4 arrays), each a
+// (64 CPT + 4) x (TY + 2) region with x stored at index x + 2.  The interior
+// rows of the regions are copied global -> LDS without passing through
+// registers; the two halo columns go through registers.  Registers carry each
+// cell's old C(p-1), D(p-1) and new B(p-1), B(p-2) along the march.
+template <typename R, bool SITE, int TY, int CPT>
+__global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fused(FusedArgs<R> a) {
     using C = cx<R>;
-    constexpr int LW = kTX + 2, LN = LW * (TY + 2);
-    __shared__ C ab[2][4][LN];
+    using V = Cells<C, CPT>;
+    constexpr int NT = kTX * TY, TXC = kTX * CPT;
+    constexpr int LW = TXC + 4, LN = LW * (TY + 2);
+    constexpr int LB = sizeof(C) * CPT >= 16 ? 16 : 4;         // bytes per lane per copy
+    constexpr int NI = (TXC * (int)sizeof(C)) / (kTX * LB);     // copies per region row
+    constexpr int NROW = 4 * (TY + 2);                          // C0, C1, D0, D1 rows
+    static_assert(2 * (TY + 2) <= NT, "halo slots");
+    __shared__ __align__(16) C sC[2][2][LN];
+    __shared__ __align__(16) C sD[3][2][LN];
+    __shared__ __align__(16) C sAB[4][LN];
 
     int L = logical_block();
     const int tx = L % a.ntx;
     L /= a.ntx;
     const int ty = L % a.nty;
     const int zc = L / a.nty;
-    const int x0 = tx * kTX, y0 = ty * TY;
-    const int w = min(kTX, a.nx - x0), h = min(TY, a.ny - y0);
+    const int x0 = tx * TXC, y0 = ty * TY;
+    const int w = min(TXC, a.nx - x0), h = min(TY, a.ny - y0);
     const int z0 = zc * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
-    const int x = threadIdx.x & (kTX - 1), y = threadIdx.x / kTX;
-    const bool own = x < w && y < h;
-    const int i = x0 + (own ? x : 0), j = y0 + (own ? y : 0);
-    const size_t plane = (size_t)a.nx * a.ny;
-    const size_t rc = (size_t)j * a.nx + i;
-    const size_t rxm = (size_t)j * a.nx + wrap_dec(i, a.nx), rxp = (size_t)j * a.nx + wrap_inc(i, a.nx);
-    const size_t rym = (size_t)wrap_dec(j, a.ny) * a.nx + i, ryp = (size_t)wrap_inc(j, a.ny) * a.nx + i;
-    const int li = (y + 1) * LW + (x + 1);
-
-    // halo item of this thread (t < 2(w + h)); kind 0: left, 1: right, 2: bottom, 3: top
     const int t = threadIdx.x;
-    int hk = -1, hx = 0, hy = 0;
-    if (t < h) { hk = 0; hx = -1; hy = t; }
-    else if (t < 2 * h) { hk = 1; hx = w; hy = t - h; }
-    else if (t < 2 * h + w) { hk = 2; hx = t - 2 * h; hy = -1; }
-    else if (t < 2 * h + 2 * w) { hk = 3; hx = t - 2 * h - w; hy = h; }
-    const int hgi = wrapn(x0 + hx, a.nx), hgj = wrapn(y0 + hy, a.ny);
-    const int hli = (hy + 1) * LW + (hx + 1);
+    const int lane = t & (kTX - 1), y = t / kTX;
+    const int xl = lane * CPT;                       // first cell of this lane
+    const bool own = xl < w && y < h;                // w is a multiple of CPT
+    const size_t plane = (size_t)a.nx * a.ny;
+    constexpr uint32_t CS = sizeof(C);
+    const uint32_t nxu = (uint32_t)a.nx;
+    const uint32_t rc = ((uint32_t)(y0 + (own ? y : 0)) * nxu + (uint32_t)(x0 + (own ? xl : 0))) * CS;
+    const int li = (y + 1) * LW + xl + 2;
+
+    // region halo-column slots (x = -1 and x = w of rows -1..h), through registers
+    const bool sv = t < 2 * (TY + 2) && (t / 2 - 1) <= h;
+    const int sx = (t & 1) ? w : -1, sy = t / 2 - 1;
+    const int sl = sv ? (sy + 1) * LW + sx + 2 : 0;
+    const uint32_t so = ((uint32_t)wrapn(y0 + sy, a.ny) * nxu + (uint32_t)wrapn(x0 + sx, a.nx)) * CS;
+
+    // ring unit of this thread: columns (one cell) then rows (CPT cells)
+    //   kind 0 left (A1, B0), 1 right (A0, B1), 2 bottom (A1, B1), 3 top (A0, B0)
+    int rk = -1, rxc = 0, ryc = 0;
+    if (t < h) { rk = 0; rxc = -1; ryc = t; }
+    else if (t < 2 * h) { rk = 1; rxc = w; ryc = t - h; }
+    else if (t < 2 * h + w / CPT) { rk = 2; rxc = (t - 2 * h) * CPT; ryc = -1; }
+    else if (t < 2 * h + 2 * (w / CPT)) { rk = 3; rxc = (t - 2 * h - w / CPT) * CPT; ryc = h; }
+    const bool ring = rk >= 0;
+    const int rnc = rk >= 2 ? CPT : 1;               // cells in this unit
+    const bool qa0 = rk == 1 || rk == 3, qb2 = rk == 0 || rk == 3;
+    const int hli = (ryc + 1) * LW + rxc + 2;
+    const uint32_t ho = ((uint32_t)wrapn(y0 + ryc, a.ny) * nxu + (uint32_t)wrapn(x0 + rxc, a.nx)) * CS;
+    C *ringA_lds = qa0 ? sAB[0] : sAB[1];
+    C *ringB_lds = qb2 ? sAB[2] : sAB[3];
 
     const C *in[8];
     C *out[8];
@@ -130,92 +195,214 @@ __global__ __launch_bounds__(kTX *TY) void k3_fused(FusedArgs<R> a) {
         out[q] = (C *)a.out[q];
     }
     const R rx = a.rx, ry = a.ry, rz = a.rz;
+    const C zero = mk2((R)0, (R)0);
+    V vz;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) vz.v[c] = zero;
 
-    // register windows of the march (own cell)
-    C cm0 = mk2((R)0, (R)0), cm1 = cm0;   // old C(p-1)
-    C dc0 = cm0, dc1 = cm0;               // old D(p)
-    C dm0 = cm0, dm1 = cm0;               // old D(p-1)
-    C bm0 = cm0, bm1 = cm0;               // new B(p-1)
-    C bmm0 = cm0, bmm1 = cm0;             // new B(p-2)
-    if (own) {
-        const size_t Pc = (size_t)wrapn(z0 - 2, a.nz) * plane, Pd = (size_t)wrapn(z0 - 1, a.nz) * plane;
-        cm0 = in[4][Pc + rc];
-        cm1 = in[5][Pc + rc];
-        dc0 = in[6][Pd + rc];
-        dc1 = in[7][Pd + rc];
+    // Global -> LDS copies of the interior rows of C(pl) (slot pl & 1) and
+    // D(pl+1) (slot (pl+1) mod 3); wave y takes rows y, y + TY, ...
+    auto copy_rows = [&](int pl) {
+        const size_t Pc = (size_t)wrapn(pl, a.nz) * plane, Pd = (size_t)wrapn(pl + 1, a.nz) * plane;
+        const int cs = pl & 1, ds = wrapn(pl + 1, 3);
+        for (int item = y; item < NROW; item += TY) {
+            const int arr = item / (TY + 2), ry0 = item % (TY + 2) - 1;
+            if (ry0 > h) continue;
+            const C *src = arr == 0 ? in[4] + Pc : arr == 1 ? in[5] + Pc : arr == 2 ? in[6] + Pd : in[7] + Pd;
+            C *dst = (arr < 2 ? sC[cs][arr] : sD[ds][arr - 2]) + (ry0 + 1) * LW + 2;
+            const char *row = (const char *)(src + (size_t)wrapn(y0 + ry0, a.ny) * a.nx + x0);
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                const int b = (j * kTX + lane) * LB;             // byte within the row
+                if (b < w * (int)CS) g2lds<LB>(row + b, (char *)dst + j * kTX * LB);
+            }
+        }
+    };
+    C psc[2] = {zero, zero}, psd[2] = {zero, zero};
+    V pa[4] = {vz, vz, vz, vz}, pra = vz, prb = vz;
+    auto ring_load = [&](const C *base, uint32_t off) -> V {
+        if (rnc == CPT) return ldv<C, CPT>(base, off);
+        V r = vz;
+        r.v[0] = ldo(base, off);
+        return r;
+    };
+    // register loads for plane pl: halo columns of C(pl), D(pl+1); own and ring A,B(pl)
+    auto load_regs = [&](int pl) {
+        const size_t P = (size_t)wrapn(pl, a.nz) * plane, Pp = (size_t)wrapn(pl + 1, a.nz) * plane;
+        if (sv) {
+            psc[0] = ldo(in[4] + P, so);
+            psc[1] = ldo(in[5] + P, so);
+            psd[0] = ldo(in[6] + Pp, so);
+            psd[1] = ldo(in[7] + Pp, so);
+        }
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pa[q] = ldv<C, CPT>(in[q] + P, rc);
+        }
+        if (ring) {
+            pra = qa0 ? ring_load(in[0] + P, ho) : ring_load(in[1] + P, ho);
+            prb = qb2 ? ring_load(in[2] + P, ho) : ring_load(in[3] + P, ho);
+        }
+    };
+    auto store_halo = [&](int pl) {
+        if (sv) {
+            sC[pl & 1][0][sl] = psc[0];
+            sC[pl & 1][1][sl] = psc[1];
+            sD[wrapn(pl + 1, 3)][0][sl] = psd[0];
+            sD[wrapn(pl + 1, 3)][1][sl] = psd[1];
+        }
+    };
+
+    // march windows
+    V cm0 = vz, cm1 = vz, dm0 = vz, dm1 = vz, bm0 = vz, bm1 = vz, bmm0 = vz, bmm1 = vz;
+    V rcm = vz;   // old C(p-1) at the ring cells (C0 for A0 ring cells, C1 for A1)
+    {
+        // D(z0-1) region (slot (z0-1) mod 3), C(z0-2) at the own and ring cells
+        const int dsl = wrapn(z0 - 1, 3);
+        const size_t Pd = (size_t)wrapn(z0 - 1, a.nz) * plane, Pc = (size_t)wrapn(z0 - 2, a.nz) * plane;
+        for (int item = y; item < 2 * (TY + 2); item += TY) {
+            const int arr = item / (TY + 2), ry0 = item % (TY + 2) - 1;
+            if (ry0 > h) continue;
+            C *dst = sD[dsl][arr] + (ry0 + 1) * LW + 2;
+            const char *row = (const char *)((arr == 0 ? in[6] : in[7]) + Pd + (size_t)wrapn(y0 + ry0, a.ny) * a.nx + x0);
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                const int b = (j * kTX + lane) * LB;
+                if (b < w * (int)CS) g2lds<LB>(row + b, (char *)dst + j * kTX * LB);
+            }
+        }
+        if (sv) {
+            sD[dsl][0][sl] = ldo(in[6] + Pd, so);
+            sD[dsl][1][sl] = ldo(in[7] + Pd, so);
+        }
+        if (own) {
+            cm0 = ldv<C, CPT>(in[4] + Pc, rc);
+            cm1 = ldv<C, CPT>(in[5] + Pc, rc);
+        }
+        if (ring) rcm = qa0 ? ring_load(in[4] + Pc, ho) : ring_load(in[5] + Pc, ho);
+        copy_rows(z0 - 1);
+        load_regs(z0 - 1);
+        store_halo(z0 - 1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
 
     for (int p = z0 - 1; p <= z1; ++p) {
+        const int cs = p & 1;
+        const int ds = wrapn(p, 3), dsn = wrapn(p + 1, 3);
         const int pk = wrapn(p, a.nz);
-        const size_t P = (size_t)pk * plane, Pp = (size_t)wrap_inc(pk, a.nz) * plane;
-        const int buf = p & 1;
-        C nA0 = cm0, nA1 = cm0, nB0 = cm0, nB1 = cm0, c0 = cm0, c1 = cm0, dn0 = cm0, dn1 = cm0;
+        const size_t P = (size_t)pk * plane;
+        const V a0 = pa[0], a1 = pa[1], b0 = pa[2], b1 = pa[3], ra = pra, rb = prb;
+        if (p < z1) {
+            copy_rows(p + 1);
+            load_regs(p + 1);
+        }
+
+        const C *C0 = sC[cs][0], *C1 = sC[cs][1];
+        const C *D0 = sD[ds][0], *D1 = sD[ds][1], *D0n = sD[dsn][0], *D1n = sD[dsn][1];
+        V nA0 = vz, nA1 = vz, nB0 = vz, nB1 = vz, c0v = vz, c1v = vz, d0v = vz, d1v = vz;
         if (own) {
-            c0 = in[4][P + rc];
-            c1 = in[5][P + rc];
-            dn0 = in[6][Pp + rc];
-            dn1 = in[7][Pp + rc];
-            const C a0 = in[0][P + rc], a1 = in[1][P + rc], b0 = in[2][P + rc], b1 = in[3][P + rc];
-            St3<C> s = stencil_ab<C, R>(rx, ry, rz,
-                                        c0, cm0, in[4][P + rxp], in[4][P + ryp],
-                                        c1, cm1, in[5][P + rym], in[5][P + rxm],
-                                        dc0, in[6][P + rxm], in[6][P + ryp], dn0,
-                                        dc1, in[7][P + rym], in[7][P + rxp], dn1);
-            nA0 = update(a0, s.s0, fcoef<R, SITE>(a, 0, 0, pk, P + rc));
-            nA1 = update(a1, s.s1, fcoef<R, SITE>(a, 1, 0, pk, P + rc));
-            nB0 = update(b0, s.s2, fcoef<R, SITE>(a, 2, 1, pk, P + rc));
-            nB1 = update(b1, s.s3, fcoef<R, SITE>(a, 3, 1, pk, P + rc));
-            ab[buf][0][li] = nA0;
-            ab[buf][1][li] = nA1;
-            ab[buf][2][li] = nB0;
-            ab[buf][3][li] = nB1;
-            if (p >= z0 && p < z1) {
-                out[0][P + rc] = nA0;
-                out[1][P + rc] = nA1;
-                out[2][P + rc] = nB0;
-                out[3][P + rc] = nB1;
+            c0v = lds_v<C, CPT>(&C0[li]);
+            c1v = lds_v<C, CPT>(&C1[li]);
+            d0v = lds_v<C, CPT>(&D0[li]);
+            d1v = lds_v<C, CPT>(&D1[li]);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int e = li + c;
+                St3<C> s = stencil_ab<C, R>(rx, ry, rz,
+                                            c0v.v[c], cm0.v[c], C0[e + 1], C0[e + LW],
+                                            c1v.v[c], cm1.v[c], C1[e - LW], C1[e - 1],
+                                            d0v.v[c], D0[e - 1], D0[e + LW], D0n[e],
+                                            d1v.v[c], D1[e - LW], D1[e + 1], D1n[e]);
+                const size_t g = P + rc / CS + c;
+                nA0.v[c] = update(a0.v[c], s.s0, fcoef<R, SITE>(a, 0, 0, pk, g));
+                nA1.v[c] = update(a1.v[c], s.s1, fcoef<R, SITE>(a, 1, 0, pk, g));
+                nB0.v[c] = update(b0.v[c], s.s2, fcoef<R, SITE>(a, 2, 1, pk, g));
+                nB1.v[c] = update(b1.v[c], s.s3, fcoef<R, SITE>(a, 3, 1, pk, g));
             }
         }
-        if (hk == 0) {
-            ab[buf][1][hli] = h1_at<R, SITE, 1>(a, hgi, hgj, pk);
-            ab[buf][2][hli] = h1_at<R, SITE, 2>(a, hgi, hgj, pk);
-        } else if (hk == 1) {
-            ab[buf][0][hli] = h1_at<R, SITE, 0>(a, hgi, hgj, pk);
-            ab[buf][3][hli] = h1_at<R, SITE, 3>(a, hgi, hgj, pk);
-        } else if (hk == 2) {
-            ab[buf][1][hli] = h1_at<R, SITE, 1>(a, hgi, hgj, pk);
-            ab[buf][3][hli] = h1_at<R, SITE, 3>(a, hgi, hgj, pk);
-        } else if (hk == 3) {
-            ab[buf][0][hli] = h1_at<R, SITE, 0>(a, hgi, hgj, pk);
-            ab[buf][2][hli] = h1_at<R, SITE, 2>(a, hgi, hgj, pk);
+        V ringA = vz, ringB = vz;
+        if (ring) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (c >= rnc) break;
+                const int e = hli + c;
+                C sa, sb;
+                if (qa0)   // S_A0 = rz(C0 - C0[k-1]) + rx(D0 - D0[i-1]) - i ry(D1 - D1[j-1])
+                    sa = cadd(cadd(cscale(rz, csub(C0[e], rcm.v[c])), cscale(rx, csub(D0[e], D0[e - 1]))),
+                              ciscale(-ry, csub(D1[e], D1[e - LW])));
+                else       // S_A1 = rz(C1 - C1[k-1]) + rx(D1[i+1] - D1) - i ry(D0[j+1] - D0)
+                    sa = cadd(cadd(cscale(rz, csub(C1[e], rcm.v[c])), cscale(rx, csub(D1[e + 1], D1[e]))),
+                              ciscale(-ry, csub(D0[e + LW], D0[e])));
+                if (qb2)   // S_B0 = -rz(D0[k+1] - D0) + rx(C0[i+1] - C0) + i ry(C1 - C1[j-1])
+                    sb = cadd(cadd(cscale(-rz, csub(D0n[e], D0[e])), cscale(rx, csub(C0[e + 1], C0[e]))),
+                              ciscale(ry, csub(C1[e], C1[e - LW])));
+                else       // S_B1 = -rz(D1[k+1] - D1) + rx(C1 - C1[i-1]) + i ry(C0[j+1] - C0)
+                    sb = cadd(cadd(cscale(-rz, csub(D1n[e], D1[e])), cscale(rx, csub(C1[e], C1[e - 1]))),
+                              ciscale(ry, csub(C0[e + LW], C0[e])));
+                const size_t g = P + ho / CS + c;
+                ringA.v[c] = update(ra.v[c], sa, qa0 ? fcoef<R, SITE>(a, 0, 0, pk, g) : fcoef<R, SITE>(a, 1, 0, pk, g));
+                ringB.v[c] = update(rb.v[c], sb, qb2 ? fcoef<R, SITE>(a, 2, 1, pk, g) : fcoef<R, SITE>(a, 3, 1, pk, g));
+                rcm.v[c] = qa0 ? C0[e] : C1[e];
+            }
         }
-        __syncthreads();
         if (own && p >= z0 + 1) {
-            // C,D of plane k = p-1 from the new A,B of planes p-1 (LDS) and p, p-2 (registers)
+            // C,D of plane k = p-1 from the new A,B of planes p-1 (LDS), p and p-2 (registers)
             const int kq = wrapn(p - 1, a.nz);
             const size_t Pm = (size_t)kq * plane;
-            const C *A0 = ab[buf ^ 1][0], *A1 = ab[buf ^ 1][1], *B0 = ab[buf ^ 1][2], *B1 = ab[buf ^ 1][3];
-            St3<C> s = stencil_cd<C, R>(rx, ry, rz,
-                                        A0[li], nA0, A0[li + 1], A0[li + LW],
-                                        A1[li], nA1, A1[li - 1], A1[li - LW],
-                                        B0[li], bmm0, B0[li - 1], B0[li + LW],
-                                        B1[li], bmm1, B1[li + 1], B1[li - LW]);
-            out[4][Pm + rc] = update(cm0, s.s0, fcoef<R, SITE>(a, 4, 2, kq, Pm + rc));
-            out[5][Pm + rc] = update(cm1, s.s1, fcoef<R, SITE>(a, 5, 2, kq, Pm + rc));
-            out[6][Pm + rc] = update(dm0, s.s2, fcoef<R, SITE>(a, 6, 3, kq, Pm + rc));
-            out[7][Pm + rc] = update(dm1, s.s3, fcoef<R, SITE>(a, 7, 3, kq, Pm + rc));
+            const C *A0 = sAB[0], *A1 = sAB[1], *B0 = sAB[2], *B1 = sAB[3];
+            V o4, o5, o6, o7;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int e = li + c;
+                St3<C> s = stencil_cd<C, R>(rx, ry, rz,
+                                            A0[e], nA0.v[c], A0[e + 1], A0[e + LW],
+                                            A1[e], nA1.v[c], A1[e - 1], A1[e - LW],
+                                            B0[e], bmm0.v[c], B0[e - 1], B0[e + LW],
+                                            B1[e], bmm1.v[c], B1[e + 1], B1[e - LW]);
+                const size_t g = Pm + rc / CS + c;
+                o4.v[c] = update(cm0.v[c], s.s0, fcoef<R, SITE>(a, 4, 2, kq, g));
+                o5.v[c] = update(cm1.v[c], s.s1, fcoef<R, SITE>(a, 5, 2, kq, g));
+                o6.v[c] = update(dm0.v[c], s.s2, fcoef<R, SITE>(a, 6, 3, kq, g));
+                o7.v[c] = update(dm1.v[c], s.s3, fcoef<R, SITE>(a, 7, 3, kq, g));
+            }
+            stv<C, CPT>(out[4] + Pm, rc, o4);
+            stv<C, CPT>(out[5] + Pm, rc, o5);
+            stv<C, CPT>(out[6] + Pm, rc, o6);
+            stv<C, CPT>(out[7] + Pm, rc, o7);
+        }
+        if (own && p >= z0 && p < z1) {
+            stv<C, CPT>(out[0] + P, rc, nA0);
+            stv<C, CPT>(out[1] + P, rc, nA1);
+            stv<C, CPT>(out[2] + P, rc, nB0);
+            stv<C, CPT>(out[3] + P, rc, nB1);
         }
         __syncthreads();
-        cm0 = c0;
-        cm1 = c1;
-        dm0 = dc0;
-        dm1 = dc1;
-        dc0 = dn0;
-        dc1 = dn1;
+        if (own) {
+            lds_st<C, CPT>(&sAB[0][li], nA0);
+            lds_st<C, CPT>(&sAB[1][li], nA1);
+            lds_st<C, CPT>(&sAB[2][li], nB0);
+            lds_st<C, CPT>(&sAB[3][li], nB1);
+        }
+        if (ring) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (c >= rnc) break;
+                ringA_lds[hli + c] = ringA.v[c];
+                ringB_lds[hli + c] = ringB.v[c];
+            }
+        }
+        if (p < z1) store_halo(p + 1);
+        cm0 = c0v;
+        cm1 = c1v;
+        dm0 = d0v;
+        dm1 = d1v;
         bmm0 = bm0;
         bmm1 = bm1;
         bm0 = nB0;
         bm1 = nB1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
 }
 
@@ -237,25 +424,30 @@ int default_chunks(int64_t tiles, int n_along, int target_blocks) {
 
 template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStream_t s) {
     FusedArgs<R> a = a0;
-    const int TY = tile_y > 0 ? tile_y : (sizeof(R) == 8 ? 4 : 8);
+    const int TY = tile_y > 0 ? tile_y : 8;
     if (TY != 4 && TY != 8) return hipErrorInvalidValue;
-    a.ntx = (a.nx + kTX - 1) / kTX;
+    // complex64 with an even row length: two cells per lane (16-byte accesses)
+    const int CPT = (sizeof(R) == 4 && (a.nx % 2) == 0) ? 2 : 1;
+    a.ntx = (a.nx + kTX * CPT - 1) / (kTX * CPT);
     a.nty = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)a.ntx * a.nty;
     if (a.zchunk <= 0) {
-        const int nzc = default_chunks(tiles, a.nz, 2048);
+        const int nzc = default_chunks(tiles, a.nz, 1024);
         a.zchunk = (a.nz + nzc - 1) / nzc;
     }
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
     const int64_t nblk = tiles * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     dim3 g((unsigned)nblk), b(kTX * TY);
-#define L3(T)                                                                 \
-    if (TY == T) {                                                            \
-        if (site) hipLaunchKernelGGL((k3_fused<R, true, T>), g, b, 0, s, a);  \
-        else hipLaunchKernelGGL((k3_fused<R, false, T>), g, b, 0, s, a);      \
+#define L3(T, P)                                                                  \
+    if (TY == T && CPT == P) {                                                    \
+        if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P>), g, b, 0, s, a);   \
+        else hipLaunchKernelGGL((k3_fused<R, false, T, P>), g, b, 0, s, a);       \
     }
-    L3(4) L3(8)
+    L3(4, 1) L3(8, 1)
+    if constexpr (sizeof(R) == 4) {
+        L3(4, 2) L3(8, 2)
+    }
 #undef L3
     return hipGetLastError();
 }

@@ -155,13 +155,14 @@ def test_3d_reverse_parity(P):
 # step relative L2 against the FP64 oracle.
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("kernel", ["split", "fused"])
-def test_3d_fp32_vs_oracle(P, kernel):
-    nx, ny, nz = 70, 17, 12
-    print("3d fp32 %s" % kernel, flush=True)
+@pytest.mark.parametrize("nx,tile_y", [(70, 8), (71, 8), (262, 4)])
+def test_3d_fp32_vs_oracle(P, kernel, nx, tile_y):
+    ny, nz = 17, 12
+    print("3d fp32 %s nx=%d ty=%d" % (kernel, nx, tile_y), flush=True)
     v_int, v_half = workloads.step_potential(nz, 1.5, 6.0, 2.0)
     f0 = rand_state((nz, ny, nx), 8, 61)
     lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
-    lat.set_kernel(kernel)
+    lat.set_kernel(kernel, tile_y if kernel == "fused" else 0)
     lat.set_potential_z(0.5, v_int, v_half)
     lat.load(f0)
     f0_32 = np_state(lat.state())
