@@ -179,6 +179,16 @@ int dirac_norm_device(dirac_ctx *ctx, void *dev_out, void *stream);
 int dirac_norm(dirac_ctx *ctx, double out[3], void *stream);
 
 /*
+ * n >= 1 steps (as dirac_step) whose last step also evaluates, on the state it
+ * produces, the conserved functional in its C,D-summed form (dev_out[0], equal
+ * to dirac_norm's values) and the plain norm (dev_out[1]); two FP64 values
+ * written to device memory, asynchronously, in a fixed order.  With the fused
+ * (3+1)D kernel the functional is accumulated inside the step at no extra
+ * pass over memory; otherwise a step is followed by the reduction.
+ */
+int dirac_step_norm(dirac_ctx *ctx, int64_t n, void *dev_out, void *stream);
+
+/*
  * Observables of the plain density |X|^2 over all sites, FP64, positions in
  * cell units (each amplitude at its own site):
  *   3D: out[0] = sum over sites with z >= z0, out[1..3] = sum x|X|^2, y|X|^2,

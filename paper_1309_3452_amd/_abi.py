@@ -24,7 +24,7 @@ EXPORTS = (
     "dirac_status_string", "dirac_create", "dirac_destroy", "dirac_last_error", "dirac_bind_state",
     "dirac_current", "dirac_set_current", "dirac_scratch_bytes", "dirac_bind_scratch",
     "dirac_set_mass_potential_z", "dirac_theta_from_fields", "dirac_set_theta_field", "dirac_set_kernel",
-    "dirac_step", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
+    "dirac_step", "dirac_step_norm", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
     "dirac_batch_norms", "dirac_batch_autotune",
 )
@@ -65,6 +65,7 @@ def lib():
         "dirac_set_kernel": ([P, I, I, I], I),
         "dirac_step": ([P, I64, P], I),
         "dirac_reverse": ([P, I64, P], I),
+        "dirac_step_norm": ([P, I64, P, P], I),
         "dirac_norm_device": ([P, P, P], I),
         "dirac_norm": ([P, ctypes.POINTER(D), P], I),
         "dirac_observables": ([P, D, ctypes.POINTER(D), P], I),

@@ -15,6 +15,9 @@ SOURCES = ["dirac_api.hip", "kernels3d.hip", "kernels2d.hip", "fused.hip", "adjo
 ARCH = os.environ.get("DIRAC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+         # IEEE operation order as written: a halo value recomputed by a
+         # neighbouring workgroup is then bitwise the value its owner stores
+         "-ffp-contract=off",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]

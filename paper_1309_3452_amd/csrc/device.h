@@ -37,13 +37,19 @@ template <typename R> struct Coef {
     cx<R> c1, c2;
 };
 
+// Fused multiply-adds are written out explicitly (the library is built
+// without automatic contraction), so every code path that evaluates the same
+// expression produces the same bits.
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ double2 update(double2 xm, double2 s, const Coef<double> &k) {
-    return mk2(k.c1.x * xm.x - k.c1.y * xm.y - (k.c2.x * s.x - k.c2.y * s.y),
-               k.c1.x * xm.y + k.c1.y * xm.x - (k.c2.x * s.y + k.c2.y * s.x));
+    return mk2(fmx(k.c1.x, xm.x, fmx(-k.c1.y, xm.y, fmx(-k.c2.x, s.x, k.c2.y * s.y))),
+               fmx(k.c1.x, xm.y, fmx(k.c1.y, xm.x, fmx(-k.c2.x, s.y, -(k.c2.y * s.x)))));
 }
 __device__ __forceinline__ float2 update(float2 xm, float2 s, const Coef<float> &k) {
-    float re = k.c1.x * xm.x - k.c1.y * xm.y + (k.c2.x * s.x - k.c2.y * s.y);
-    float im = k.c1.x * xm.y + k.c1.y * xm.x + (k.c2.x * s.y + k.c2.y * s.x);
+    const float re = fmx(k.c1.x, xm.x, fmx(-k.c1.y, xm.y, fmx(k.c2.x, s.x, -(k.c2.y * s.y))));
+    const float im = fmx(k.c1.x, xm.y, fmx(k.c1.y, xm.x, fmx(k.c2.x, s.y, k.c2.y * s.x)));
     return mk2(xm.x - re, xm.y - im);
 }
 

@@ -65,6 +65,22 @@ template <typename C> __device__ __forceinline__ void sto(C *base, uint32_t boff
 template <typename C, int CPT> struct Cells {
     C v[CPT];
 };
+// Streaming (nontemporal) accesses for data touched once per step: the own
+// cells' A,B and every output.  Halo-shared C,D rows keep the normal policy.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void nt_store(float2 *p, float2 v) { __builtin_nontemporal_store(nt_f2{v.x, v.y}, (nt_f2 *)p); }
+__device__ __forceinline__ void nt_store(double2 *p, double2 v) { __builtin_nontemporal_store(nt_d2{v.x, v.y}, (nt_d2 *)p); }
+__device__ __forceinline__ float2 nt_load(const float2 *p) {
+    nt_f2 t = __builtin_nontemporal_load((const nt_f2 *)p);
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double2 nt_load(const double2 *p) {
+    nt_d2 t = __builtin_nontemporal_load((const nt_d2 *)p);
+    return make_double2(t.x, t.y);
+}
+
 template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> ldv(const C *base, uint32_t boff) {
     Cells<C, CPT> r;
     if constexpr (CPT == 1) {
@@ -76,11 +92,23 @@ template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> ldv(cons
     }
     return r;
 }
+// streaming load of the own cells
+template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> ldv_nt(const C *base, uint32_t boff) {
+    Cells<C, CPT> r;
+    if constexpr (CPT == 1) {
+        r.v[0] = nt_load((const C *)((const char *)base + boff));
+    } else {
+        const nt_f4 q = __builtin_nontemporal_load((const nt_f4 *)((const char *)base + boff));
+        r.v[0] = mk2(q.x, q.y);
+        r.v[1] = mk2(q.z, q.w);
+    }
+    return r;
+}
 template <typename C, int CPT> __device__ __forceinline__ void stv(C *base, uint32_t boff, const Cells<C, CPT> &c) {
     if constexpr (CPT == 1) {
-        sto(base, boff, c.v[0]);
+        nt_store((C *)((char *)base + boff), c.v[0]);
     } else {
-        *(float4 *)((char *)base + boff) = make_float4(c.v[0].x, c.v[0].y, c.v[1].x, c.v[1].y);
+        __builtin_nontemporal_store(nt_f4{c.v[0].x, c.v[0].y, c.v[1].x, c.v[1].y}, (nt_f4 *)((char *)base + boff));
     }
 }
 template <typename C, int CPT> __device__ __forceinline__ Cells<C, CPT> lds_v(const C *p) {
@@ -134,7 +162,11 @@ template <int LB> __device__ __forceinline__ void g2lds(const void *gsrc, void *
 // rows of the regions are copied global -> LDS without passing through
 // registers; the two halo columns go through registers.  Registers carry each
 // cell's old C(p-1), D(p-1) and new B(p-1), B(p-2) along the march.
-template <typename R, bool SITE, int TY, int CPT>
+// NORM: also accumulate, per workgroup, the conserved functional of the new
+// state in its C,D-summed form E_r = sum |X|^2 + Re sum_{C,D} conj(Y) S_Y(A,B)
+// (Lemma of Sect. 2 after summation by parts; S_Y(A,B) is exactly the stencil
+// the C,D update evaluates) and the plain norm, into a.npart.
+template <typename R, bool SITE, int TY, int CPT, bool NORM>
 __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fused(FusedArgs<R> a) {
     using C = cx<R>;
     using V = Cells<C, CPT>;
@@ -199,6 +231,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
     V vz;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) vz.v[c] = zero;
+    double nrm[2] = {0.0, 0.0};
 
     // Global -> LDS copies of the interior rows of C(pl) (slot pl & 1) and
     // D(pl+1) (slot (pl+1) mod 3); wave y takes rows y, y + TY, ...
@@ -237,7 +270,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
         }
         if (own) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pa[q] = ldv<C, CPT>(in[q] + P, rc);
+            for (int q = 0; q < 4; ++q) pa[q] = ldv_nt<C, CPT>(in[q] + P, rc);
         }
         if (ring) {
             pra = qa0 ? ring_load(in[0] + P, ho) : ring_load(in[1] + P, ho);
@@ -328,18 +361,15 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
                 if (c >= rnc) break;
                 const int e = hli + c;
                 C sa, sb;
+                // the same expressions as the owners' (stencil_ab), hence the same bits
                 if (qa0)   // S_A0 = rz(C0 - C0[k-1]) + rx(D0 - D0[i-1]) - i ry(D1 - D1[j-1])
-                    sa = cadd(cadd(cscale(rz, csub(C0[e], rcm.v[c])), cscale(rx, csub(D0[e], D0[e - 1]))),
-                              ciscale(-ry, csub(D1[e], D1[e - LW])));
+                    sa = sterm3(rz, csub(C0[e], rcm.v[c]), rx, csub(D0[e], D0[e - 1]), -ry, csub(D1[e], D1[e - LW]));
                 else       // S_A1 = rz(C1 - C1[k-1]) + rx(D1[i+1] - D1) - i ry(D0[j+1] - D0)
-                    sa = cadd(cadd(cscale(rz, csub(C1[e], rcm.v[c])), cscale(rx, csub(D1[e + 1], D1[e]))),
-                              ciscale(-ry, csub(D0[e + LW], D0[e])));
+                    sa = sterm3(rz, csub(C1[e], rcm.v[c]), rx, csub(D1[e + 1], D1[e]), -ry, csub(D0[e + LW], D0[e]));
                 if (qb2)   // S_B0 = -rz(D0[k+1] - D0) + rx(C0[i+1] - C0) + i ry(C1 - C1[j-1])
-                    sb = cadd(cadd(cscale(-rz, csub(D0n[e], D0[e])), cscale(rx, csub(C0[e + 1], C0[e]))),
-                              ciscale(ry, csub(C1[e], C1[e - LW])));
+                    sb = sterm3(-rz, csub(D0n[e], D0[e]), rx, csub(C0[e + 1], C0[e]), ry, csub(C1[e], C1[e - LW]));
                 else       // S_B1 = -rz(D1[k+1] - D1) + rx(C1 - C1[i-1]) + i ry(C0[j+1] - C0)
-                    sb = cadd(cadd(cscale(-rz, csub(D1n[e], D1[e])), cscale(rx, csub(C1[e], C1[e - 1]))),
-                              ciscale(ry, csub(C0[e + LW], C0[e])));
+                    sb = sterm3(-rz, csub(D1n[e], D1[e]), rx, csub(C1[e], C1[e - 1]), ry, csub(C0[e + LW], C0[e]));
                 const size_t g = P + ho / CS + c;
                 ringA.v[c] = update(ra.v[c], sa, qa0 ? fcoef<R, SITE>(a, 0, 0, pk, g) : fcoef<R, SITE>(a, 1, 0, pk, g));
                 ringB.v[c] = update(rb.v[c], sb, qb2 ? fcoef<R, SITE>(a, 2, 1, pk, g) : fcoef<R, SITE>(a, 3, 1, pk, g));
@@ -352,6 +382,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
             const size_t Pm = (size_t)kq * plane;
             const C *A0 = sAB[0], *A1 = sAB[1], *B0 = sAB[2], *B1 = sAB[3];
             V o4, o5, o6, o7;
+            St3<C> sv[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const int e = li + c;
@@ -365,17 +396,44 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
                 o5.v[c] = update(cm1.v[c], s.s1, fcoef<R, SITE>(a, 5, 2, kq, g));
                 o6.v[c] = update(dm0.v[c], s.s2, fcoef<R, SITE>(a, 6, 3, kq, g));
                 o7.v[c] = update(dm1.v[c], s.s3, fcoef<R, SITE>(a, 7, 3, kq, g));
+                if constexpr (NORM) sv[c] = s;
             }
             stv<C, CPT>(out[4] + Pm, rc, o4);
             stv<C, CPT>(out[5] + Pm, rc, o5);
             stv<C, CPT>(out[6] + Pm, rc, o6);
             stv<C, CPT>(out[7] + Pm, rc, o7);
+            if constexpr (NORM) {
+                // conj(Y) S_Y(A,B) with the S the update used (FP64 in the
+                // complex128 form; FP32-evaluated in complex64), summed in FP64
+                auto D2 = [](C v) { return make_double2((double)v.x, (double)v.y); };
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const double2 y4 = D2(o4.v[c]), y5 = D2(o5.v[c]), y6 = D2(o6.v[c]), y7 = D2(o7.v[c]);
+                    const double2 s4 = D2(sv[c].s0), s5 = D2(sv[c].s1), s6 = D2(sv[c].s2), s7 = D2(sv[c].s3);
+                    const double pp = y4.x * y4.x + y4.y * y4.y + y5.x * y5.x + y5.y * y5.y + y6.x * y6.x +
+                                      y6.y * y6.y + y7.x * y7.x + y7.y * y7.y;
+                    nrm[0] += pp + (y4.x * s4.x + y4.y * s4.y) + (y5.x * s5.x + y5.y * s5.y) +
+                              (y6.x * s6.x + y6.y * s6.y) + (y7.x * s7.x + y7.y * s7.y);
+                    nrm[1] += pp;
+                }
+            }
         }
         if (own && p >= z0 && p < z1) {
             stv<C, CPT>(out[0] + P, rc, nA0);
             stv<C, CPT>(out[1] + P, rc, nA1);
             stv<C, CPT>(out[2] + P, rc, nB0);
             stv<C, CPT>(out[3] + P, rc, nB1);
+            if constexpr (NORM) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    double pp = 0.0;
+                    const C q4[4] = {nA0.v[c], nA1.v[c], nB0.v[c], nB1.v[c]};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pp += (double)q4[u].x * (double)q4[u].x + (double)q4[u].y * (double)q4[u].y;
+                    nrm[0] += pp;
+                    nrm[1] += pp;
+                }
+            }
         }
         __syncthreads();
         if (own) {
@@ -404,6 +462,29 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
+    if constexpr (NORM) {
+        // reuse the C region of LDS for the block reduction (all reads are done)
+        double *red = (double *)&sC[0][0][0];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm[q] += __shfl_xor(nrm[q], off, 64);
+        }
+        if (lane == 0) {
+            red[2 * y] = nrm[0];
+            red[2 * y + 1] = nrm[1];
+        }
+        __syncthreads();
+        if (t == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < TY; ++q) {
+                s0 += red[2 * q];
+                s1 += red[2 * q + 1];
+            }
+            a.npart[2 * blockIdx.x] = s0;
+            a.npart[2 * blockIdx.x + 1] = s1;
+        }
+    }
 }
 
 template <typename R, bool SITE, int TXB>
@@ -422,7 +503,8 @@ int default_chunks(int64_t tiles, int n_along, int target_blocks) {
 
 }  // namespace
 
-template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStream_t s) {
+template <typename R>
+hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStream_t s, int *nblocks_out) {
     FusedArgs<R> a = a0;
     const int TY = tile_y > 0 ? tile_y : 8;
     if (TY != 4 && TY != 8) return hipErrorInvalidValue;
@@ -438,11 +520,19 @@ template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a0, bool site
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
     const int64_t nblk = tiles * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    if (nblocks_out) *nblocks_out = (int)nblk;
+    const bool norm = a.npart != nullptr;
+    if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;   // caller falls back
     dim3 g((unsigned)nblk), b(kTX * TY);
-#define L3(T, P)                                                                  \
-    if (TY == T && CPT == P) {                                                    \
-        if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P>), g, b, 0, s, a);   \
-        else hipLaunchKernelGGL((k3_fused<R, false, T, P>), g, b, 0, s, a);       \
+#define L3(T, P)                                                                          \
+    if (TY == T && CPT == P) {                                                            \
+        if (norm) {                                                                       \
+            if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P, true>), g, b, 0, s, a);  \
+            else hipLaunchKernelGGL((k3_fused<R, false, T, P, true>), g, b, 0, s, a);      \
+        } else {                                                                          \
+            if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P, false>), g, b, 0, s, a); \
+            else hipLaunchKernelGGL((k3_fused<R, false, T, P, false>), g, b, 0, s, a);     \
+        }                                                                                 \
     }
     L3(4, 1) L3(8, 1)
     if constexpr (sizeof(R) == 4) {
@@ -470,8 +560,8 @@ template <typename R> hipError_t launch_fused2(const FusedArgs<R> &a0, bool site
     return hipGetLastError();
 }
 
-template hipError_t launch_fused3<float>(const FusedArgs<float> &, bool, int, hipStream_t);
-template hipError_t launch_fused3<double>(const FusedArgs<double> &, bool, int, hipStream_t);
+template hipError_t launch_fused3<float>(const FusedArgs<float> &, bool, int, hipStream_t, int *);
+template hipError_t launch_fused3<double>(const FusedArgs<double> &, bool, int, hipStream_t, int *);
 template hipError_t launch_fused2<float>(const FusedArgs<float> &, bool, hipStream_t);
 template hipError_t launch_fused2<double>(const FusedArgs<double> &, bool, hipStream_t);
 

@@ -33,6 +33,8 @@ template <typename R> struct FusedArgs {
     int zchunk;           // planes per workgroup along the march
     int nzc;              // number of chunks = ceil(nz / zchunk)
     int ntx, nty;         // tiles in x, y
+    double *npart;        // if set: per-workgroup (E_r, plain norm) of the new state, FP64
+    int npart_cap;        // capacity of npart in workgroups
 };
 
 // Reduction launch over a single lattice.
@@ -63,7 +65,8 @@ constexpr int kObsVals = 9;
 // 3D split kernels (kernels3d.hip)
 template <typename R> hipError_t launch_half3(const HalfArgs<R> &a, int which /*0: A,B  1: C,D*/, bool site,
                                               hipStream_t s);
-template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a, bool site, int tile_y, hipStream_t s);
+template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a, bool site, int tile_y, hipStream_t s,
+                                               int *nblocks_out = nullptr);
 template <typename R> hipError_t launch_norm3(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_obs3(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_seed3(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);

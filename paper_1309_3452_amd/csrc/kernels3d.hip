@@ -102,7 +102,30 @@ __device__ __forceinline__ void cell_of(int64_t t, int nx, int ny, int &i, int &
     j = (int)(q - (int64_t)k * ny);
 }
 
-// Per-block partial sums of (E_r terms, C,D-side terms, plain norm), FP64.
+// Reductions march along z like the step: work items are (64 x 4 column tile,
+// z chunk), taken round-robin by the kReduceBlocks workgroups, so the partial
+// sums have a fixed count and a fixed order.  Own-column z neighbours ride in
+// registers; x-y neighbours come through the caches.
+struct MarchMap {
+    int ntx, nty, nzc, zchunk, items;
+};
+__host__ __device__ inline MarchMap march_map(int nx, int ny, int nz) {
+    MarchMap m;
+    m.ntx = (nx + kTX - 1) / kTX;
+    m.nty = (ny + kTY - 1) / kTY;
+    const int tiles = m.ntx * m.nty;
+    int nzc = (kReduceBlocks + tiles - 1) / tiles;
+    if (nzc > nz) nzc = nz;
+    if (nzc < 1) nzc = 1;
+    m.zchunk = (nz + nzc - 1) / nzc;
+    m.nzc = (nz + m.zchunk - 1) / m.zchunk;
+    m.items = tiles * m.nzc;
+    return m;
+}
+
+// Per-workgroup partial sums of (E_r, E_r summed on the C,D sites, plain norm), FP64:
+//   E_r   = sum |X|^2 - Re sum_{A,B} conj(X) S_X(C,D)
+//   E_r'  = sum |X|^2 + Re sum_{C,D} conj(X) S_X(A,B)
 template <typename R>
 __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
     using C = cx<R>;
@@ -112,40 +135,57 @@ __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
     for (int q = 0; q < 8; ++q) f[q] = (const C *)a.f[q];
     const double rx = a.rx, ry = a.ry, rz = a.rz;
     double v[kNormVals] = {0.0, 0.0, 0.0};
-    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
+    const MarchMap mm = march_map(a.nx, a.ny, a.nz);
     const size_t plane = (size_t)a.nx * a.ny;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_of(t, a.nx, a.ny, i, j, k);
-        const size_t row = (size_t)j * a.nx, kk = (size_t)k * plane;
-        const size_t c = kk + row + i;
-        const size_t xm = kk + row + wrap_dec(i, a.nx), xp = kk + row + wrap_inc(i, a.nx);
-        const size_t ym = kk + (size_t)wrap_dec(j, a.ny) * a.nx + i, yp = kk + (size_t)wrap_inc(j, a.ny) * a.nx + i;
-        const size_t zm = (size_t)wrap_dec(k, a.nz) * plane + row + i, zp = (size_t)wrap_inc(k, a.nz) * plane + row + i;
-        double2 x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = to_d(f[q][c]);
-        St3<double2> sab = stencil_ab<double2, double>(rx, ry, rz,
-            x[4], to_d(f[4][zm]), to_d(f[4][xp]), to_d(f[4][yp]),
-            x[5], to_d(f[5][zm]), to_d(f[5][ym]), to_d(f[5][xm]),
-            x[6], to_d(f[6][xm]), to_d(f[6][yp]), to_d(f[6][zp]),
-            x[7], to_d(f[7][ym]), to_d(f[7][xp]), to_d(f[7][zp]));
-        St3<double2> scd = stencil_cd<double2, double>(rx, ry, rz,
-            x[0], to_d(f[0][zp]), to_d(f[0][xp]), to_d(f[0][yp]),
-            x[1], to_d(f[1][zp]), to_d(f[1][xm]), to_d(f[1][ym]),
-            x[2], to_d(f[2][zm]), to_d(f[2][xm]), to_d(f[2][yp]),
-            x[3], to_d(f[3][zm]), to_d(f[3][xp]), to_d(f[3][ym]));
-        double p = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) p += abs2(x[q]);
-        v[0] -= re_conj_mul(x[0], sab.s0) + re_conj_mul(x[1], sab.s1) + re_conj_mul(x[2], sab.s2) +
-                re_conj_mul(x[3], sab.s3);
-        v[1] += re_conj_mul(x[4], scd.s0) + re_conj_mul(x[5], scd.s1) + re_conj_mul(x[6], scd.s2) +
-                re_conj_mul(x[7], scd.s3);
-        v[0] += p;
-        v[1] += p;
-        v[2] += p;
+    const int x = threadIdx.x & (kTX - 1), y = threadIdx.x / kTX;
+    for (int item = blockIdx.x; item < mm.items; item += gridDim.x) {
+        int r = item;
+        const int tx = r % mm.ntx;
+        r /= mm.ntx;
+        const int ty = r % mm.nty;
+        const int zc = r / mm.nty;
+        const int i = tx * kTX + x, j = ty * kTY + y;
+        if (i >= a.nx || j >= a.ny) continue;
+        const int z0 = zc * mm.zchunk, z1 = min(a.nz, z0 + mm.zchunk);
+        const uint32_t c = (uint32_t)j * a.nx + i;
+        const uint32_t xm = (uint32_t)j * a.nx + wrap_dec(i, a.nx), xp = (uint32_t)j * a.nx + wrap_inc(i, a.nx);
+        const uint32_t ym = (uint32_t)wrap_dec(j, a.ny) * a.nx + i, yp = (uint32_t)wrap_inc(j, a.ny) * a.nx + i;
+        const size_t Pb = (size_t)wrap_dec(z0, a.nz) * plane, P0 = (size_t)z0 * plane;
+        double2 cm0 = to_d(f[4][Pb + c]), cm1 = to_d(f[5][Pb + c]);      // C(k-1)
+        double2 bm0 = to_d(f[2][Pb + c]), bm1 = to_d(f[3][Pb + c]);      // B(k-1)
+        double2 a0 = to_d(f[0][P0 + c]), a1 = to_d(f[1][P0 + c]), d0 = to_d(f[6][P0 + c]), d1 = to_d(f[7][P0 + c]);
+        for (int k = z0; k < z1; ++k) {
+            const size_t Pk = (size_t)k * plane;
+            const size_t Pn = (size_t)wrap_inc(k, a.nz) * plane;
+            const double2 an0 = to_d(f[0][Pn + c]), an1 = to_d(f[1][Pn + c]);
+            const double2 dn0 = to_d(f[6][Pn + c]), dn1 = to_d(f[7][Pn + c]);
+            const double2 b0 = to_d(f[2][Pk + c]), b1 = to_d(f[3][Pk + c]);
+            const double2 c0 = to_d(f[4][Pk + c]), c1 = to_d(f[5][Pk + c]);
+            St3<double2> sab = stencil_ab<double2, double>(rx, ry, rz,
+                c0, cm0, to_d(f[4][Pk + xp]), to_d(f[4][Pk + yp]),
+                c1, cm1, to_d(f[5][Pk + ym]), to_d(f[5][Pk + xm]),
+                d0, to_d(f[6][Pk + xm]), to_d(f[6][Pk + yp]), dn0,
+                d1, to_d(f[7][Pk + ym]), to_d(f[7][Pk + xp]), dn1);
+            St3<double2> scd = stencil_cd<double2, double>(rx, ry, rz,
+                a0, an0, to_d(f[0][Pk + xp]), to_d(f[0][Pk + yp]),
+                a1, an1, to_d(f[1][Pk + xm]), to_d(f[1][Pk + ym]),
+                b0, bm0, to_d(f[2][Pk + xm]), to_d(f[2][Pk + yp]),
+                b1, bm1, to_d(f[3][Pk + xp]), to_d(f[3][Pk + ym]));
+            const double p = abs2(a0) + abs2(a1) + abs2(b0) + abs2(b1) + abs2(c0) + abs2(c1) + abs2(d0) + abs2(d1);
+            v[0] += p - (re_conj_mul(a0, sab.s0) + re_conj_mul(a1, sab.s1) + re_conj_mul(b0, sab.s2) +
+                         re_conj_mul(b1, sab.s3));
+            v[1] += p + (re_conj_mul(c0, scd.s0) + re_conj_mul(c1, scd.s1) + re_conj_mul(d0, scd.s2) +
+                         re_conj_mul(d1, scd.s3));
+            v[2] += p;
+            cm0 = c0;
+            cm1 = c1;
+            bm0 = b0;
+            bm1 = b1;
+            a0 = an0;
+            a1 = an1;
+            d0 = dn0;
+            d1 = dn1;
+        }
     }
     block_sum<kNormVals>(v, lds);
     if (threadIdx.x == 0) {
@@ -166,23 +206,34 @@ __global__ __launch_bounds__(kReduceThreads) void k3_obs(ReduceArgs<R> a) {
     double v[kObsVals];
 #pragma unroll
     for (int q = 0; q < kObsVals; ++q) v[q] = 0.0;
-    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_of(t, a.nx, a.ny, i, j, k);
+    const MarchMap mm = march_map(a.nx, a.ny, a.nz);
+    const size_t plane = (size_t)a.nx * a.ny;
+    const int x = threadIdx.x & (kTX - 1), y = threadIdx.x / kTX;
+    for (int item = blockIdx.x; item < mm.items; item += gridDim.x) {
+        int r = item;
+        const int tx = r % mm.ntx;
+        r /= mm.ntx;
+        const int ty = r % mm.nty;
+        const int zc = r / mm.nty;
+        const int i = tx * kTX + x, j = ty * kTY + y;
+        if (i >= a.nx || j >= a.ny) continue;
+        const int z0 = zc * mm.zchunk, z1 = min(a.nz, z0 + mm.zchunk);
+        const uint32_t c = (uint32_t)j * a.nx + i;
+        for (int k = z0; k < z1; ++k) {
+            const size_t e = (size_t)k * plane + c;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            double p = abs2(to_d(((const C *)a.f[q])[t]));
-            double x = (double)i + (double)kOff3[q][0];
-            double y = (double)j + (double)kOff3[q][1];
-            double z = (double)k + (double)kOff3[q][2];
-            if (z >= a.z0) v[0] += p;
-            v[1] += x * p;
-            v[2] += y * p;
-            v[3] += z * p;
-            v[4] += p;
-            v[5 + q / 2] += p;
+            for (int q = 0; q < 8; ++q) {
+                const double p = abs2(to_d(((const C *)a.f[q])[e]));
+                const double px = (double)i + (double)kOff3[q][0];
+                const double py = (double)j + (double)kOff3[q][1];
+                const double pz = (double)k + (double)kOff3[q][2];
+                if (pz >= a.z0) v[0] += p;
+                v[1] += px * p;
+                v[2] += py * p;
+                v[3] += pz * p;
+                v[4] += p;
+                v[5 + q / 2] += p;
+            }
         }
     }
     block_sum<kObsVals>(v, lds);

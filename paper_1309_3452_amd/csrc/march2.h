@@ -83,14 +83,14 @@ __device__ __forceinline__ void march2(const FusedArgs<R> &a, int tx, int zc, cx
         if (threadIdx.x == 0) {
             // u1 at the left halo column: S_u1 = rx(v1[i+1] - v1) - i ry(v0[j+1] - v0)
             const int g = hgl;
-            C s = cadd(cscale(rx, csub(in[3][Rw + wrap_inc(g, a.nx)], in[3][Rw + g])),
-                       ciscale(-ry, csub(in[2][Rp + g], in[2][Rw + g])));
+            C s = sterm2(rx, csub(in[3][Rw + wrap_inc(g, a.nx)], in[3][Rw + g]), -ry,
+                         csub(in[2][Rp + g], in[2][Rw + g]));
             uu[buf][1][0] = update(in[1][Rw + g], s, fcoef2<R, SITE>(a, 1, Rw + g));
         } else if (threadIdx.x == 1) {
             // u0 at the right halo column: S_u0 = rx(v0 - v0[i-1]) - i ry(v1 - v1[j-1])
             const int g = hgr;
-            C s = cadd(cscale(rx, csub(in[2][Rw + g], in[2][Rw + wrap_dec(g, a.nx)])),
-                       ciscale(-ry, csub(in[3][Rw + g], in[3][Rm + g])));
+            C s = sterm2(rx, csub(in[2][Rw + g], in[2][Rw + wrap_dec(g, a.nx)]), -ry,
+                         csub(in[3][Rw + g], in[3][Rm + g]));
             uu[buf][0][w + 1] = update(in[0][Rw + g], s, fcoef2<R, SITE>(a, 0, Rw + g));
         }
         __syncthreads();

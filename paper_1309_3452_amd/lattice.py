@@ -135,6 +135,14 @@ class Lattice:
     def step(self, n: int = 1):
         check(lib().dirac_step(self._ctx, int(n), _stream_handle()), self._ctx)
 
+    def step_norm(self, n: int = 1, out: torch.Tensor = None) -> torch.Tensor:
+        """n steps; the last also writes (E_r, plain norm) of the new state, FP64, into
+        a device tensor (asynchronous)."""
+        out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
+        check(lib().dirac_step_norm(self._ctx, int(n), ctypes.c_void_p(out.data_ptr()), _stream_handle()),
+              self._ctx)
+        return out
+
     def reverse(self, n: int = 1):
         check(lib().dirac_reverse(self._ctx, int(n), _stream_handle()), self._ctx)
 

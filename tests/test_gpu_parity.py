@@ -242,3 +242,39 @@ def test_batched_vs_oracle(P, mode, graph):
         assert rel_l2(np_state(B.state(b)), f) <= 1e-13, b
         eo = ol.energy(f)
         assert abs(norms[b][0] - eo[0]) <= 1e-12 * eo[2]
+
+
+# --------------------------------------------------------------------------
+# In-step conserved functional (fused kernel) against the standalone reduction
+# and the oracle: the same FP64 sums in another order.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("shape", [(70, 20, 22), (130, 9, 5)])
+def test_step_norm_matches_reduction(P, dtype, shape):
+    nx, ny, nz = shape
+    print("step_norm %s %s" % (shape, dtype), flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 91)
+    lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+    lat.set_kernel("fused")
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.load(f0)
+    out = lat.step_norm(3).cpu().numpy()
+    ref = lat.norm()
+    # complex128: the same FP64 sums in another order.  complex64: the in-step
+    # sum uses the FP32-evaluated stencil (a few ulps, 2^-24 each, of each
+    # cross term, random over the ~1e5 sites), the reduction an FP64 one.
+    tol = 1e-12 if dtype == torch.complex128 else 2e-9
+    assert abs(out[0] - ref[1]) <= tol * ref[2]
+    assert abs(out[0] - ref[0]) <= tol * ref[2]
+    assert abs(out[1] - ref[2]) <= 1e-12 * ref[2]
+    if dtype == torch.complex128:
+        ol = oracle.Lattice3(nx, ny, nz, DT3)
+        f = [a.copy() for a in f0]
+        ol.step(f, ol.theta_vz(0.5, v_int, v_half), 3)
+        assert abs(out[0] - ol.energy(f)[0]) <= 1e-12 * ref[2]
+    # split kernel: the fallback path gives the same values
+    lat.set_kernel("split")
+    out2 = lat.step_norm(1).cpu().numpy()
+    ref2 = lat.norm()
+    assert abs(out2[0] - ref2[1]) <= 1e-15 * ref2[2] and abs(out2[1] - ref2[2]) <= 1e-15 * ref2[2]
