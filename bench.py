@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--workload", default="step3d", choices=["step3d", "batched2d", "adjoint3d", "plane2d"],
+                    help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
                          "for scaling hardware byte counters")
@@ -133,6 +135,143 @@ def cpu_baseline():
                       "site-updates/s is per cell-step, independent of lattice size" % (n, nsteps, dt)}
 
 
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(steps):
+    """64 uneven 2D lattices (sizes from {64, 96, ..., 1024}^2, per-site theta), complex64."""
+    import tempfile
+
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    lats = workloads.config_batched(device="cuda")
+    cells = sum(L["nx"] * L["ny"] for L in lats)
+    B = P.BatchedLattices(lats, dtype=torch.complex64, dt=workloads.DT2)
+    snap = [[t.clone() for t in B.state(b)] for b in range(B.count)]
+    cache = os.path.join(tempfile.gettempdir(), "dirac_tune_cache.json")
+    choice = B.autotune(cache)
+    res = {}
+    for mode, graph in ((1, False), (1, True), (0, False), (0, True)):
+        for b in range(B.count):                     # same initial state for every variant
+            for t, s0 in zip(B.state(b), snap[b]):
+                t.copy_(s0)
+        B.run(2, mode=mode, graph=False)
+        if graph:
+            B.run(steps, mode=mode, graph=True)      # capture + first replay
+        ms = _timed(lambda: B.run(steps, mode=mode, graph=graph))
+        res["mode%d%s" % (mode, "_graph" if graph else "")] = ms
+    # 64 single-lattice runs one after another (fused 2D kernel, same inputs)
+    solo_ms = 0.0
+    for L in lats:
+        lat = P.Lattice2D(L["nx"], L["ny"], dtype=torch.complex64, dt=workloads.DT2)
+        lat.load(L["state"])
+        lat.set_fields(L["m"], L["v_site"])
+        lat.step(2)
+        solo_ms += _timed(lambda: lat.step(steps))
+    best = min(res, key=res.get)
+    value = cells * steps / (res[best] * 1e-3)
+    alg = 80.0 * cells            # 8 complex64 amplitudes read+written + 4 FP32 theta read, per cell-step
+    return {"metric": "site-updates/s, 64 batched (2+1)D lattices, complex64, 500 steps", "value": value,
+            "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+            "ms_per_step": res[best] / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 uneven 2D lattices, sizes iid from {64,...,1024}^2, sum of 4 Gaussians V, "
+                                   "m in [0,1], per-site theta, complex64", "cells": cells, "best": best,
+                       "tile_choice": choice},
+            "variants_ms": res, "sequential_single_lattice_ms": solo_ms, "speedup_vs_sequential": solo_ms / res[best],
+            "roofline": {"bound": "hbm", "achieved": alg * steps / (res[best] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg * steps / (res[best] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": None, "alg_bytes_per_step": alg}}
+
+
+def bench_adjoint(steps, dtype_name):
+    """Gradient of the transmitted probability w.r.t. 32 V(z) nodes on 128^3, by the reversible adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    cfg = workloads.config_adjoint(128)
+    dtype = torch.complex128 if dtype_name == "f64" else torch.complex64
+    n = cfg["n"]
+    st = workloads.packet3d(n, n, n, cfg["center"], cfg["sigma"], cfg["k0"], cfg["m"], cfg["dt"], dtype=dtype,
+                            device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+    lat.set_kernel("split")
+    H_int = torch.from_numpy(cfg["H_int"])
+    H_half = torch.from_numpy(cfg["H_half"])
+    p = torch.tensor(cfg["p"], dtype=torch.float64, requires_grad=True)
+    vi = (H_int @ p.detach()).numpy()
+    vh = (H_half @ p.detach()).numpy()
+    lat.load(st)
+    lat.set_potential_z(cfg["m"], vi, vh)
+    lat.step(2)
+    lat.load(st)
+    fwd = _timed(lambda: lat.step(steps))
+    loss = P.DiracLoss.apply(p, lat, st, cfg["m"], H_int, H_half, steps, cfg["z0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = P.DiracLoss.apply(p, lat, st, cfg["m"], H_int, H_half, steps, cfg["z0"])
+    loss.backward()
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t0) * 1e3
+    rebuilt = [t.clone() for t in lat.state()]
+    err = math.sqrt(sum(float(torch.sum(torch.abs(a.to(torch.complex128) - b.to(torch.complex128)) ** 2))
+                        for a, b in zip(rebuilt, st)) / sum(float(torch.sum(torch.abs(b.to(torch.complex128)) ** 2))
+                                                            for b in st))
+    cells = n ** 3
+    return {"metric": "adjoint gradient time / forward time, (3+1)D 128^3, 400 steps, 32 V(z) nodes",
+            "value": total / fwd, "unit": "x forward", "n_gpus": 1, "steps": steps, "warmup": 2,
+            "ms_per_step": total / steps, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype_name, "data": "synthetic",
+            "config": {"workload": "(3+1)D 128^3 adjoint, V(z) from 32 periodic hat nodes, loss = P(z >= 64)",
+                       "cells": cells},
+            "forward_ms": fwd, "forward_plus_gradient_ms": total, "loss": float(loss.detach()),
+            "grad_norm": float(p.grad.norm()), "rebuilt_initial_state_rel_l2": err}
+
+
+def bench_plane2d(steps):
+    """(2+1)D 128^2, complex128, 200 steps: launch-bound; plain launches vs one captured graph."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    cfg = workloads.config1()
+    lat = P.Lattice2D(128, 128, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_potential_z(0.0)
+    lat.load(cfg["state"])
+    lat.step(2)
+    plain = _timed(lambda: lat.step(steps))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        lat.step(2)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            lat.step(steps)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = _timed(lambda: g.replay(), reps=5)
+    cells = 128 * 128
+    return {"metric": "site-updates/s, (2+1)D 128^2 complex128, 200 steps", "value": cells * steps / (graph * 1e-3),
+            "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2, "ms_per_step": graph / steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "(2+1)D 128^2 Gaussian packet, m=0, V=0, fused y-march kernel", "cells": cells},
+            "plain_launches_ms": plain, "graph_replay_ms": graph,
+            "plain_value": cells * steps / (plain * 1e-3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -140,6 +279,16 @@ def main():
               "(z-slab sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.workload == "batched2d":
+        print(json.dumps(bench_batched(500)), flush=True)
+        return
+    if args.workload == "adjoint3d":
+        for d in ("f64", "f32"):
+            print(json.dumps(bench_adjoint(400, d)), flush=True)
+        return
+    if args.workload == "plane2d":
+        print(json.dumps(bench_plane2d(200)), flush=True)
+        return
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3
     if args.calibrate_copy:

@@ -1,0 +1,287 @@
+"""GPU checks at the benchmark sizes, in the launch configuration bench.py times.
+
+At these sizes the oracle cannot run whole: parity is checked on sampled
+cells (the oracle advances a periodic sub-box around each sample whose
+light cone covers the steps taken), and otherwise through properties that
+hold at any size (closed-form plane waves, the conserved functional, time
+reversal, finite differences, bitwise agreement between kernels).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from closed_form import eigenket3, plane_wave3, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+DT3 = workloads.DT3
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1309_3452_amd as P
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.lib()
+    return P
+
+
+def free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def plane_wave_gpu(n, k, amps, w, dt, dtype, t_shift=0.0):
+    """Eq. (planeonlattice) on the device, built per axis (exact phases in FP64)."""
+    out = []
+    for a in range(8):
+        ox, oy, oz = workloads.OFF3[a]
+        t = (-0.5 * dt if a < 4 else 0.0) + t_shift
+        ax = [torch.exp(1j * k[q] * (torch.arange(n, dtype=torch.float64, device="cuda") + o))
+              for q, o in ((0, ox), (1, oy), (2, oz))]
+        ph = complex(math.cos(w * t), -math.sin(w * t)) * amps[a // 2]
+        out.append((ax[2][:, None, None] * ax[1][None, :, None] * (ax[0][None, None, :] * ph)).to(dtype))
+    return out
+
+
+def rel_l2_t(a_list, b_list):
+    num = sum(float(torch.sum(torch.abs(a.to(torch.complex128) - b.to(torch.complex128)) ** 2))
+              for a, b in zip(a_list, b_list))
+    den = sum(float(torch.sum(torch.abs(b.to(torch.complex128)) ** 2)) for b in b_list)
+    return math.sqrt(num / den)
+
+
+def test_plane_wave_256_fp64(P):
+    """Closed-form eigen-evolution (Eqs. planeonlattice, pwdsip) at 256^3 in FP64."""
+    n, steps, m = 256, 200, 0.5
+    k = (2 * math.pi * 3 / n, 2 * math.pi * 5 / n, 2 * math.pi * 46 / n)
+    w, amps = eigenket3(k, m, DT3, 1)
+    print("plane wave 256^3 fp64", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=DT3)
+    lat.set_potential_z(m)
+    lat.load(plane_wave_gpu(n, k, amps, w, DT3, torch.complex128))
+    e0 = lat.norm()
+    lat.step(steps)
+    expect = plane_wave_gpu(n, k, amps, w, DT3, torch.complex128, t_shift=steps * DT3)
+    assert rel_l2_t(lat.state(), expect) <= steps * 1e-15
+    assert abs(lat.norm()[0] - e0[0]) <= 1e-13 * e0[0]
+    del lat, expect
+    free()
+
+
+def test_plane_wave_512_fp32_phase_error(P):
+    """FP32 form: dispersion-phase error of a plane wave (k_z = 2 pi 46/512, m = 0.5,
+    V = 0) after 1000 steps against Eq. (pwdsip), and the drift of E_r."""
+    n, steps, m = 512, 1000, 0.5
+    k = (0.0, 0.0, 2 * math.pi * 46 / n)
+    w, amps = eigenket3(k, m, DT3, 1)
+    print("plane wave 512^3 fp32", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex64, dt=DT3)
+    lat.set_potential_z(m)
+    lat.load(plane_wave_gpu(n, k, amps, w, DT3, torch.complex64))
+    e0 = lat.norm()
+    lat.step(steps)
+    e1 = lat.norm()
+    expect = plane_wave_gpu(n, k, amps, w, DT3, torch.complex128, t_shift=steps * DT3)
+    inner = sum(complex(torch.sum(torch.conj(b) * a.to(torch.complex128))) for a, b in zip(lat.state(), expect))
+    nrm = sum(float(torch.sum(torch.abs(b) ** 2)) for b in expect)
+    phase_err = abs(math.atan2(inner.imag, inner.real))
+    amp_err = abs(abs(inner) / nrm - 1.0)
+    drift = abs(e1[0] - e0[0]) / abs(e0[0])
+    print("fp32 plane wave: phase error %.3e rad, amplitude error %.3e, E_r drift %.3e" % (phase_err, amp_err, drift))
+    assert drift <= 1e-5
+    assert phase_err <= 1e-3
+    del lat, expect
+    free()
+
+
+def test_packet_512_fp32_vs_fp64(P):
+    """FP32 form against the FP64 path on the 512^3 Klein-step workload, 1000 steps:
+    relative L2, global phase arg<psi64, psi32>, and E_r drift of each."""
+    n, steps = 512, 1000
+    print("packet 512^3 fp32 vs fp64", flush=True)
+    res = {}
+    for dtype in (torch.complex64, torch.complex128):
+        cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+        lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+        lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+        lat.load(cfg["state"])
+        del cfg
+        e0 = lat.norm()
+        lat.step(steps)
+        e1 = lat.norm()
+        res[dtype] = (lat, abs(e1[0] - e0[0]) / abs(e0[0]))
+        if dtype == torch.complex64:
+            s32 = [t.clone() for t in lat.state()]
+            del lat
+            res[dtype] = (None, res[dtype][1])
+            free()
+    lat64, d64 = res[torch.complex128]
+    d32 = res[torch.complex64][1]
+    s64 = lat64.state()
+    l2 = rel_l2_t(s32, s64)
+    inner = sum(complex(torch.sum(torch.conj(b) * a.to(torch.complex128))) for a, b in zip(s32, s64))
+    print("fp32 vs fp64 at 512^3 after %d steps: rel L2 %.3e, phase %.3e rad; E_r drift fp32 %.3e fp64 %.3e"
+          % (steps, l2, math.atan2(inner.imag, inner.real), d32, d64))
+    assert d32 <= 1e-5
+    assert d64 <= 1e-12
+    assert l2 <= 1e-2
+    del lat64, s32, s64
+    free()
+
+
+def test_sampled_oracle_parity_256_fp64(P):
+    """Klein-step workload at 256^3 (fused kernel, bench launch configuration): after
+    3 steps, sampled cells against the oracle run on a periodic sub-box of half-width
+    2*3+1 around each sample (the light cone grows two cells per step)."""
+    n, steps, R = 256, 3, 7
+    cfg = workloads.config_step3d(n, dtype=torch.complex128, device="cuda")
+    print("sampled parity 256^3", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    f0 = [t.cpu().numpy() for t in cfg["state"]]
+    del cfg["state"]
+    lat.step(steps)
+    got = [t.cpu().numpy() for t in lat.state()]
+    del lat
+    free()
+    g = np.random.default_rng(17)
+    samples = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(24)]
+    samples += [(n // 2, n // 2, n // 4), (0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 0, n // 2)]
+    B = 2 * R + 1
+    ol = oracle.Lattice3(B, B, B, cfg["dt"])
+    scale = max(float(np.abs(a).max()) for a in got)
+    vz = lambda z: 1.5 * (1.0 + np.tanh((z - n / 2.0) / 4.0)) / 2.0
+    for (i, j, k) in samples:
+        ix = (np.arange(i - R, i + R + 1)) % n
+        iy = (np.arange(j - R, j + R + 1)) % n
+        iz = (np.arange(k - R, k + R + 1)) % n
+        box = [np.ascontiguousarray(a[np.ix_(iz, iy, ix)]) for a in f0]
+        th = []
+        for a in range(8):
+            oz = workloads.OFF3[a][2]
+            z = (iz + oz)[:, None, None] * np.ones((1, B, B))
+            sgn = 1.0 if a < 4 else -1.0
+            th.append(np.ascontiguousarray(0.5 * cfg["dt"] * (sgn * cfg["m"] + vz(z))))
+        ol.step(box, th, steps)
+        for a in range(8):
+            assert abs(box[a][R, R, R] - got[a][k, j, i]) <= 1e-13 * scale, (i, j, k, a)
+
+
+def test_adjoint_fd_128_fp64(P):
+    """The reversible adjoint's dL/dp against central finite differences (h = 1e-6)
+    on the 128^3 adjoint workload (400 steps), FP64."""
+    cfg = workloads.config_adjoint(128)
+    n, steps = cfg["n"], cfg["steps"]
+    print("adjoint fd 128^3", flush=True)
+    st = workloads.packet3d(n, n, n, cfg["center"], cfg["sigma"], cfg["k0"], cfg["m"], cfg["dt"],
+                            dtype=torch.complex128, device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=cfg["dt"])
+    H_int = torch.from_numpy(cfg["H_int"])
+    H_half = torch.from_numpy(cfg["H_half"])
+    p = torch.tensor(cfg["p"], dtype=torch.float64, requires_grad=True)
+    loss = P.DiracLoss.apply(p, lat, st, cfg["m"], H_int, H_half, steps, cfg["z0"])
+    loss.backward()
+    grad = p.grad.numpy().copy()
+    rebuilt = [t.clone() for t in lat.state()]
+    assert rel_l2_t(rebuilt, st) <= 1e-12
+
+    def L(pv):
+        lat.load(st)
+        lat.set_potential_z(cfg["m"], cfg["H_int"] @ pv, cfg["H_half"] @ pv)
+        lat.step(steps)
+        return lat.observables(cfg["z0"])[0]
+    h = 1e-6
+    scale = np.abs(grad).max()
+    for q in (3, 15, 16, 17, 30):
+        e = np.zeros_like(cfg["p"])
+        e[q] = h
+        fd = (L(cfg["p"] + e) - L(cfg["p"] - e)) / (2 * h)
+        print("node %d: adjoint %.9e fd %.9e" % (q, grad[q], fd))
+        assert abs(fd - grad[q]) <= 1e-6 * scale
+    del lat
+    free()
+
+
+def test_batched_full_config_matches_solo(P):
+    """The 64-lattice batch (complex64, per-site theta): every lattice equals its own
+    single-lattice run bitwise (the same arithmetic in any tiling), both modes."""
+    lats = workloads.config_batched(device="cuda")
+    print("batched full config", flush=True)
+    steps = 20
+    solo = []
+    for L in lats:
+        lat = P.Lattice2D(L["nx"], L["ny"], dtype=torch.complex64, dt=workloads.DT2)
+        lat.load(L["state"])
+        lat.set_fields(L["m"], L["v_site"])
+        lat.step(steps)
+        solo.append([t.clone() for t in lat.state()])
+        del lat
+    for mode in (1, 0):
+        B = P.BatchedLattices(lats, dtype=torch.complex64, dt=workloads.DT2)
+        B.run(steps, mode=mode, graph=True)
+        for b in range(B.count):
+            for x, y in zip(B.state(b), solo[b]):
+                assert torch.equal(x, y), (mode, b)
+        del B
+    free()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_kernels_bitwise_equal(P, dtype):
+    """Split and fused kernels, and fused tilings, give identical bits (the same
+    expressions evaluated in the same order; no automatic contraction)."""
+    nx, ny, nz = 136, 40, 24
+    print("bitwise kernels %s" % dtype, flush=True)
+    g = np.random.default_rng(3)
+    f0 = [g.standard_normal((nz, ny, nx)) + 1j * g.standard_normal((nz, ny, nx)) for _ in range(8)]
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    outs = []
+    for kernel, ty, zc in (("split", 0, 0), ("fused", 4, 0), ("fused", 8, 5), ("fused", 8, 0)):
+        lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+        lat.set_kernel(kernel, ty, zc)
+        lat.set_potential_z(0.5, v_int, v_half)
+        lat.load(f0)
+        lat.step(7)
+        outs.append([t.clone() for t in lat.state()])
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert torch.equal(x, y)
+
+
+def test_graph_replay_single_lattice(P):
+    """A captured graph of 50 fused steps, replayed several times with eager work and
+    synchronisation in between, matches eager stepping every time."""
+    nx, ny, nz = 130, 24, 32
+    print("graph replay", flush=True)
+    g = np.random.default_rng(4)
+    f0 = [g.standard_normal((nz, ny, nx)) + 1j * g.standard_normal((nz, ny, nx)) for _ in range(8)]
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    eager = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
+    graphed = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
+    for lat in (eager, graphed):
+        lat.set_potential_z(0.5, v_int, v_half)
+        lat.load(f0)
+    graphed.step(2)                     # tables uploaded outside the capture
+    eager.step(2)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(cg, stream=s):
+            graphed.step(50)
+    torch.cuda.current_stream().wait_stream(s)
+    # the capture recorded launches without running them; the context's notion of
+    # which buffer holds the state advanced by 50 (even) steps, i.e. unchanged
+    for rep in range(4):
+        cg.replay()
+        torch.cuda.synchronize()
+        eager.step(50)
+        _ = torch.ones(10, device="cuda").sum().item()      # unrelated eager work
+        torch.cuda.synchronize()
+        for x, y in zip(graphed.state(), eager.state()):
+            assert torch.equal(x, y), rep
