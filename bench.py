@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
+                    help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d", choices=["step3d", "batched2d", "adjoint3d", "plane2d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -47,29 +49,30 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
+def kernel_source_hash(steps_per_launch=1):
     h = hashlib.sha256()
-    for f in ("fused.hip", "stencil3.h", "device.h", "internal.h"):
+    for f in ("fused2.hip" if steps_per_launch == 2 else "fused.hip", "stencil3.h", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1309_3452_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(dtype_tag, n):
+def profiled_traffic(dtype_tag, n, steps_per_launch=1):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "fused3d_%s_%d_counters.md" % (dtype_tag, n))
+    name = "fused3d_%s_%d_counters.md" if steps_per_launch == 1 else "fused3dx2_%s_%d_counters.md"
+    path = os.path.join(ROOT, "profiles", name % (dtype_tag, n))
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    if not m or not t or m.group(1) != kernel_source_hash(steps_per_launch):
         return None
     return float(t.group(1))
 
 
-def run_gpu(n, dtype, steps, warmup, tile_y, zchunk):
+def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel):
     import torch
 
     import paper_1309_3452_amd as P
@@ -77,7 +80,7 @@ def run_gpu(n, dtype, steps, warmup, tile_y, zchunk):
 
     cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
     lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
-    lat.set_kernel("fused", tile_y, zchunk)
+    lat.set_kernel(kernel, tile_y, zchunk)
     lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
     lat.load(cfg["state"])
     del cfg["state"]
@@ -86,29 +89,42 @@ def run_gpu(n, dtype, steps, warmup, tile_y, zchunk):
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    # one launch advances G steps (two-step kernel: 2); every NORM_EVERY steps the
+    # launch that ends there also sums E_r of its result
+    G = 2 if kernel in ("fused2", "auto") else 1
+    groups = []
+    s = 0
+    while s < steps:
+        g = min(G, steps - s)
+        groups.append((g, (s + g) % NORM_EVERY == 0))
+        s += g
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in groups]
     norms = torch.zeros((steps // NORM_EVERY + 1, 2), dtype=torch.float64, device="cuda")
     w0 = torch.cuda.Event(enable_timing=True)
     w1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     w0.record(stream)
-    for s in range(steps):
-        ev[s][0].record(stream)
-        if (s + 1) % NORM_EVERY == 0:
-            lat.step_norm(1, norms[(s + 1) // NORM_EVERY])   # step + E_r of the new state in one pass
+    done = 0
+    for q, (g, with_norm) in enumerate(groups):
+        ev[q][0].record(stream)
+        if with_norm:
+            lat.step_norm(g, norms[(done + g) // NORM_EVERY])   # steps + E_r of the new state in the same pass
         else:
-            lat.step(1)
-        ev[s][1].record(stream)
+            lat.step(g)
+        ev[q][1].record(stream)
+        done += g
     w1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    full = [q for q, (g, _) in enumerate(groups) if g == G]
+    launch_ms = sum(ev[q][0].elapsed_time(ev[q][1]) for q in full) / max(1, len(full))
     region_ms = w0.elapsed_time(w1)
     e_end = lat.norm()
     nr = norms[1:].cpu().numpy()
     drift_series = float(abs(nr[:, 0] - e_start[0]).max() / abs(e_start[0])) if len(nr) else 0.0
-    out = dict(wall_s=wall, region_ms=region_ms, kernel_ms=kernel_ms, e_start=e_start, e_end=e_end,
+    out = dict(wall_s=wall, region_ms=region_ms, launch_ms=launch_ms, steps_per_launch=G, launches=len(groups),
+               e_start=e_start, e_end=e_end,
                drift=abs(e_end[0] - e_start[0]) / abs(e_start[0]), drift_max=drift_series,
                plain_norm_change=abs(e_end[2] - e_start[2]) / e_start[2], steps_total=steps + warmup)
     del lat
@@ -299,14 +315,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
-    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk)
+    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(n, torch.complex128, args.fp64_steps or K, W, 0, 0)
+        r64 = run_gpu(n, torch.complex128, args.fp64_steps or K, W, 0, 0, args.kernel)
     value = cells * K / r32["wall_s"]
-    alg_bytes = 128.0 * cells           # 16 amplitudes x 8 B per cell-step, FP32
-    achieved = alg_bytes / (r32["kernel_ms"] * 1e-3) / 1e9
-    traffic = profiled_traffic("fp32", n)
+    G = r32["steps_per_launch"]
+    # algorithmic bytes per launch: 16 amplitudes x 8 B per cell-step (each amplitude
+    # read and written once per step) x the G steps one launch advances
+    alg_bytes = 128.0 * cells * G
+    achieved = alg_bytes / (r32["launch_ms"] * 1e-3) / 1e9
+    traffic = profiled_traffic("fp32", n, G)
+    kname = "k3_fused2<float> (two steps per launch" if G == 2 else "k3_fused<float> (one step per launch"
     line = {
         "metric": "site-updates/s & HBM-roofline %, FP32 vs FP64 3+1D 512^3 at stated norm error",
         "value": value,
@@ -322,25 +342,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": "(3+1)D %d^3 periodic lattice, complex64 storage and FP32 arithmetic, m=0.5, "
                                "V(z)=1.5(1+tanh((z-%d)/4))/2, Gaussian packet sigma=12 k0=(0,0,0.56), "
-                               "dt=0.9x stability bound, fused z-march kernel, FP64 E_r evaluated in-step every %d steps"
-                               % (n, n // 2, NORM_EVERY),
+                               "dt=0.9x stability bound, fused z-march kernel (%d steps per launch), "
+                               "FP64 E_r evaluated in-step every %d steps" % (n, n // 2, G, NORM_EVERY),
                    "nx": n, "ny": n, "nz": n, "cells": cells},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k3_fused<float> (one launch per step; every 10th launch also sums E_r)",
+                     "kernel": kname + "; every fifth launch also sums E_r)" if G == 2 else kname + "; every tenth launch also sums E_r)",
+                     "steps_per_launch": G,
                      "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": r32["kernel_ms"]},
+                     "avg_launch_ms": r32["launch_ms"],
+                     "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None},
         "norm_error": {"E_r_rel_drift_fp32": r32["drift"], "E_r_rel_drift_fp32_max_every10": r32["drift_max"],
                        "steps_total": r32["steps_total"], "plain_norm_rel_change": r32["plain_norm_change"]},
         "amplitude_updates_per_s": 8 * value,
     }
     if r64 is not None:
         v64 = cells * (args.fp64_steps or K) / r64["wall_s"]
-        a64 = 256.0 * cells / (r64["kernel_ms"] * 1e-3) / 1e9
+        G64 = r64["steps_per_launch"]
+        a64 = 256.0 * cells * G64 / (r64["launch_ms"] * 1e-3) / 1e9
         line["fp64"] = {"value": v64, "unit": "site-updates/s", "ms_per_step": r64["wall_s"] * 1e3 / (args.fp64_steps or K),
-                        "roofline_frac": a64 / HBM_PEAK_GBS, "achieved_GBs": a64, "avg_launch_ms": r64["kernel_ms"],
-                        "E_r_rel_drift": r64["drift"]}
+                        "roofline_frac": a64 / HBM_PEAK_GBS, "achieved_GBs": a64, "avg_launch_ms": r64["launch_ms"],
+                        "steps_per_launch": G64, "E_r_rel_drift": r64["drift"]}
         line["fp32_speedup_over_fp64"] = value / v64
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

@@ -62,9 +62,12 @@ enum dirac_status {
 
 /* step kernels (dirac_set_kernel) */
 enum dirac_kernel {
-    DIRAC_KERNEL_AUTO = 0,   /* fused where available                              */
+    DIRAC_KERNEL_AUTO = 0,   /* FUSED2 where it applies, else FUSED                */
     DIRAC_KERNEL_SPLIT = 1,  /* one launch per half-step, in place                 */
-    DIRAC_KERNEL_FUSED = 2   /* one launch per step, ping-pong between the buffers */
+    DIRAC_KERNEL_FUSED = 2,  /* one launch per step, ping-pong between the buffers */
+    DIRAC_KERNEL_FUSED2 = 3  /* one launch per two steps (3D, V(z) tables, nx even
+                                for complex64), ping-pong; an odd remainder and
+                                other cases take FUSED                            */
 };
 
 /* Human-readable name of a status code (static storage). */
@@ -143,11 +146,13 @@ int dirac_theta_from_fields(dirac_ctx *ctx, double m, void *const v_site[], void
 int dirac_set_theta_field(dirac_ctx *ctx, void *const theta[]);
 
 /* Choose the step kernel and its tiling; 0 = library default for a knob.
- *   tile_y: cells along y per workgroup of the 3D fused kernel: 4 or 8
- *           (default 4 for complex128, 8 for complex64); the tile is 64 cells in x
+ *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8
+ *           (default 8); its tile is 64 cells in x (128 for complex64 with nx even)
  *   zchunk: planes (3D) or rows (2D) per workgroup along the march of the fused
- *           kernel (default: enough chunks for ~2048 workgroups)
- * The reversed step and the adjoint always use the split kernels. */
+ *           kernels (default: enough chunks for ~1024 workgroups)
+ * The two-step kernel uses 64 x 8 tiles (complex64) or 32 x 8 (complex128).
+ * Every kernel gives the same bits.  The reversed step and the adjoint always
+ * use the split kernels. */
 int dirac_set_kernel(dirac_ctx *ctx, int kernel, int tile_y, int zchunk);
 
 /*

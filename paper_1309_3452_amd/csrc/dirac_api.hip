@@ -199,7 +199,12 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
 
 int kernel_choice(const dirac_ctx *c) {
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
+    // the fused kernels address a plane with 32-bit byte offsets
+    const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
+    if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
     if (c->kernel == DIRAC_KERNEL_FUSED) return DIRAC_KERNEL_FUSED;
+    if (c->ndim == 3 && fused3x2_supported((int)c->nx, c->dtype == DIRAC_C64, c->site_mode))
+        return DIRAC_KERNEL_FUSED2;
     return DIRAC_KERNEL_FUSED;
 }
 
@@ -207,8 +212,17 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
     int rc = upload_tables(c, s);
     if (rc) return rc;
     const bool site = c->site_mode;
-    const bool fused = !reverse && kernel_choice(c) == DIRAC_KERNEL_FUSED;
-    for (int64_t t = 0; t < n; ++t) {
+    const int kc = reverse ? DIRAC_KERNEL_SPLIT : kernel_choice(c);
+    const bool fused = kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2;
+    int64_t t = 0;
+    if (kc == DIRAC_KERNEL_FUSED2) {
+        for (; t + 2 <= n; t += 2) {
+            FusedArgs<R> a = fused_args<R>(c);
+            HIPCHK(c, launch_fused3x2<R>(a, s));
+            c->cur = 1 - c->cur;
+        }
+    }
+    for (; t < n; ++t) {
         if (fused) {
             FusedArgs<R> a = fused_args<R>(c);
             if (c->ndim == 3) HIPCHK(c, launch_fused3<R>(a, site, c->tile_y, s));
@@ -411,7 +425,7 @@ int dirac_theta_from_fields(dirac_ctx *c, double m, void *const v_site[], void *
 
 int dirac_set_kernel(dirac_ctx *c, int kernel, int tile_y, int zchunk) {
     if (!c) return DIRAC_E_ARG;
-    if (kernel < DIRAC_KERNEL_AUTO || kernel > DIRAC_KERNEL_FUSED) return fail(c, DIRAC_E_ARG, "bad kernel %d", kernel);
+    if (kernel < DIRAC_KERNEL_AUTO || kernel > DIRAC_KERNEL_FUSED2) return fail(c, DIRAC_E_ARG, "bad kernel %d", kernel);
     if (tile_y != 0 && tile_y != 4 && tile_y != 8) return fail(c, DIRAC_E_ARG, "tile_y must be 0, 4 or 8");
     if (zchunk < 0) return fail(c, DIRAC_E_ARG, "zchunk must be >= 0");
     c->kernel = kernel;
@@ -441,11 +455,40 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
     if (rc) return rc;
     if (n < 1 || !dev_out) return fail(c, DIRAC_E_ARG, "need n >= 1 and an output");
     hipStream_t s = (hipStream_t)stream;
-    rc = dirac_step(c, n - 1, stream);
-    if (rc) return rc;
     double *part = (double *)scratch_at(c, off_partial(c));
     const int cap = (kReduceBlocks * kObsVals) / 2;
-    if (c->ndim == 3 && kernel_choice(c) == DIRAC_KERNEL_FUSED) {
+    const int kc = kernel_choice(c);
+    if (c->ndim == 3 && kc == DIRAC_KERNEL_FUSED2 && n >= 2) {
+        rc = dirac_step(c, n - 2, stream);
+        if (rc) return rc;
+        rc = upload_tables(c, s);
+        if (rc) return rc;
+        int nb = 0;
+        hipError_t e;
+        if (c->dtype == DIRAC_C64) {
+            FusedArgs<float> a = fused_args<float>(c);
+            a.npart = part;
+            a.npart_cap = cap;
+            e = launch_fused3x2<float>(a, s, &nb);
+        } else {
+            FusedArgs<double> a = fused_args<double>(c);
+            a.npart = part;
+            a.npart_cap = cap;
+            e = launch_fused3x2<double>(a, s, &nb);
+        }
+        if (e == hipSuccess) {
+            c->cur = 1 - c->cur;
+            HIPCHK(c, launch_final_sum(part, nb, 2, (double *)dev_out, s));
+            return DIRAC_OK;
+        }
+        if (nb <= cap) HIPCHK(c, e);   // a real launch failure; otherwise fall through
+        rc = dirac_step(c, 1, stream);
+        if (rc) return rc;
+    } else {
+        rc = dirac_step(c, n - 1, stream);
+        if (rc) return rc;
+    }
+    if (c->ndim == 3 && (kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2)) {
         int nb = 0;
         hipError_t e;
         if (c->dtype == DIRAC_C64) {

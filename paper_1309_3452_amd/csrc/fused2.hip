@@ -1,0 +1,389 @@
+// Two time steps per launch ((3+1)D, V(z) coefficient tables): temporal
+// blocking of the z-march, so each amplitude is read once and written once
+// per two steps of Sect. 2 (Eqs. ss1-ss4).
+//
+// A workgroup owns an x-y tile of TW x TY cells and a chunk [z0, z1) of
+// planes.  Four levels run as a pipeline along z, each one plane behind the
+// previous:
+//   level 1  A,B after step 1 at plane p        (Eqs. ss1, ss2 on the old C,D)
+//   level 2  C,D after step 1 at plane p-1      (Eqs. ss3, ss4)
+//   level 3  A,B after step 2 at plane p-2      (stored for p-2 in [z0, z1))
+//   level 4  C,D after step 2 at plane p-3      (stored for p-3 in [z0, z1))
+// Each half-step reaches half a cell in x and y, so the two steps need the
+// old C,D on the tile plus a two-cell ring, level 1 on a ring of up to two
+// cells, levels 2 and 3 on a one-cell ring and level 4 on the tile.  Every
+// level is evaluated on a rectangle that covers what the next one reads; the
+// ring is recomputed by each workgroup rather than exchanged, so the state
+// ping-pongs between two buffers exactly as in the one-step kernel.
+//
+// LDS holds, as (TW + 4) x (TY + 4) regions (cell (x, y) of the tile at
+// (y + 2)(TW + 4) + x + 2): the old C of 2 planes and D of 3 planes (one plane
+// ahead for the z-neighbour of B, one more in flight) and one plane of each
+// level's output.  The old C,D region rows (ring columns included) are copied
+// global -> LDS asynchronously, one plane ahead.  Thread t owns region cell t
+// of every level: its z-neighbours and previous values X- stay in registers or
+// are re-read from the level planes in LDS.
+//
+// The same stencil and update helpers as the other kernels evaluate every
+// value, with the same operation order, so the result is bitwise that of two
+// one-step launches.
+#include "device.h"
+#include "internal.h"
+#include "stencil3.h"
+#include "march2.h"
+
+namespace dirac {
+
+namespace {
+
+__device__ __forceinline__ int logical_block2() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if ((nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+    return b;
+}
+
+template <typename R> __device__ __forceinline__ Coef<R> tcoef(const R *tab, int nz, int cls, int pk) {
+    const R *e = tab + ((size_t)cls * nz + pk) * 4;
+    Coef<R> k;
+    k.c1 = mk2(e[0], e[1]);
+    k.c2 = mk2(e[2], e[3]);
+    return k;
+}
+
+template <typename C> __device__ __forceinline__ C ld_at(const C *base, uint32_t boff) {
+    return *(const C *)((const char *)base + boff);
+}
+
+typedef float nt2f __attribute__((ext_vector_type(2)));
+typedef double nt2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt(float2 *p, float2 v) { __builtin_nontemporal_store(nt2f{v.x, v.y}, (nt2f *)p); }
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) { __builtin_nontemporal_store(nt2d{v.x, v.y}, (nt2d *)p); }
+template <typename C> __device__ __forceinline__ void st_at(C *base, uint32_t boff, C v) {
+    st_nt((C *)((char *)base + boff), v);
+}
+
+// Asynchronous global -> LDS copy: lane l's 16 bytes land at lds_wave_base + 16 l.
+__device__ __forceinline__ void g2lds16(const void *gsrc, void *lds_wave_base) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)gsrc,
+                                     (__attribute__((address_space(3))) void *)lds_wave_base, 16, 0, 0);
+}
+
+template <typename R, int TW, int TY, int NT, bool NORM>
+__global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
+    using C = cx<R>;
+    constexpr int W = TW + 4, H = TY + 4, RN = W * H;
+    constexpr int PAD = W + 2;                        // keeps +-1, +-W reads of edge cells inside sm
+    constexpr int CPL = 16 / (int)sizeof(C);          // cells per 16-byte unit
+    static_assert(RN <= NT, "one region cell per thread");
+    static_assert((W / CPL) <= 64, "one wave instruction per region row");
+    static_assert(PAD % 2 == 0 && W % 2 == 0 && RN % 2 == 0, "16-byte alignment of the LDS rows");
+    // LDS arrays (RN cells each): 0-1 C slot 0, 2-3 C slot 1, 4-9 D slots 0..2,
+    // 10-13 level-1 A0 A1 B0 B1, 14-17 level-2 C0 C1 D0 D1, 18-21 level-3 A0 A1 B0 B1
+    __shared__ __align__(16) C sm[PAD + 22 * RN + PAD];
+    auto arr = [&](int k) -> C * { return sm + PAD + k * RN; };
+
+    int L = logical_block2();
+    const int tx = L % a.ntx;
+    L /= a.ntx;
+    const int ty = L % a.nty;
+    const int zc = L / a.nty;
+    const int x0 = tx * TW, y0 = ty * TY;
+    const int w = min(TW, a.nx - x0), h = min(TY, a.ny - y0);
+    const int z0 = zc * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    constexpr uint32_t CS = sizeof(C);
+
+    // the region cell of this thread: (xr, yr) relative to the tile origin
+    const int i = t;
+    const int xr = t % W - 2, yr = t / W - 2;
+    const bool in1 = t < RN && xr < w + 2 && yr < h + 2;                       // levels 1 (ring 2)
+    const bool in2 = in1 && xr >= -1 && xr <= w && yr >= -1 && yr <= h;        // levels 2, 3 (ring 1)
+    const bool in4 = in1 && xr >= 0 && xr < w && yr >= 0 && yr < h;            // level 4 (tile)
+    uint32_t go = in1 ? ((uint32_t)wrapn(y0 + yr, ny) * (uint32_t)nx + (uint32_t)wrapn(x0 + xr, nx)) * CS : 0u;
+
+    const C *in[8];
+    C *out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        in[q] = (const C *)a.in[q];
+        out[q] = (C *)a.out[q];
+    }
+    const R rx = a.rx, ry = a.ry, rz = a.rz;
+    const C zero = mk2((R)0, (R)0);
+
+    // whole region rows (ring columns included) of the old C (arrays 4, 5) of
+    // plane pc into C slot cs and of D (arrays 6, 7) of plane pd into D slot ds;
+    // lane j moves cells 2j, 2j+1 (complex64) or cell j (complex128) of the row,
+    // wrapped in x per 16-byte unit (nx is even for complex64, so no unit
+    // straddles the wrap)
+    const int rl = (w + 4) / CPL;                     // active lanes per row
+    const uint32_t lxo = (uint32_t)wrapn(x0 - 2 + lane * CPL, nx) * CS;
+    auto copy_rows = [&](int pc, int cs, int pd, int ds, bool with_c) {
+        const size_t Pc = (size_t)wrapn(pc, nz) * plane, Pd = (size_t)wrapn(pd, nz) * plane;
+        for (int item = wv; item < 4 * H; item += NT / 64) {
+            const int k = item / H, yy = item % H;
+            if (yy >= h + 4 || (k < 2 && !with_c)) continue;
+            const C *src = (k < 2 ? in[4 + k] + Pc : in[4 + k] + Pd) + (size_t)wrapn(y0 + yy - 2, ny) * nx;
+            C *dst = (k < 2 ? arr(2 * cs + k) : arr(4 + 2 * ds + (k - 2))) + yy * W;
+            if (lane < rl) g2lds16((const char *)src + lxo, dst);
+        }
+    };
+
+    // registers carried along the march (own cell)
+    C cprev[2] = {zero, zero}, dprev[2] = {zero, zero};   // old C, D of plane p-1
+    C pab[4] = {zero, zero, zero, zero};                  // old A, B of plane p
+    C ab1h2[4] = {zero, zero, zero, zero};                // level 1 of plane p-2
+    C cd1h2[4] = {zero, zero, zero, zero};                // level 2 of plane p-3
+    C b2h2[2] = {zero, zero};                             // level 3 B of plane p-4
+    double nrm[2] = {0.0, 0.0};
+
+    const int ps = z0 - 3, pe = z1 + 2;
+    {
+        // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
+        const int cs = ps & 1;
+        copy_rows(ps, cs, ps, wrapn(ps, 3), true);
+        copy_rows(ps, cs, ps + 1, wrapn(ps + 1, 3), false);
+        const size_t Pm = (size_t)wrapn(ps - 1, nz) * plane, P0 = (size_t)wrapn(ps, nz) * plane;
+        if (in1) {
+            cprev[0] = ld_at(in[4] + Pm, go);
+            cprev[1] = ld_at(in[5] + Pm, go);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pab[q] = ld_at(in[q] + P0, go);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+    for (int p = ps; p <= pe; ++p) {
+        // keep the per-lane offset opaque, so that addresses stay a wave-uniform
+        // plane base plus a 32-bit lane offset instead of hoisted 64-bit pairs
+        asm volatile("" : "+v"(go));
+        const int cs = p & 1, ds = wrapn(p, 3), dsn = wrapn(p + 1, 3);
+        const bool more = p < pe;
+        C pabn[4] = {zero, zero, zero, zero};
+        if (more) {
+            // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
+            copy_rows(p + 1, (p + 1) & 1, p + 2, wrapn(p + 2, 3), true);
+            if (in1) {
+                const size_t Pn = (size_t)wrapn(p + 1, nz) * plane;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pabn[q] = ld_at(in[q] + Pn, go);
+            }
+        }
+
+        // level 1: A,B of plane p after step 1
+        C ab1[4] = {zero, zero, zero, zero}, cown[2] = {zero, zero}, down[2] = {zero, zero};
+        if (in1) {
+            const int pk = wrapn(p, nz);
+            const Coef<R> kA = tcoef(a.tab, nz, 0, pk), kB = tcoef(a.tab, nz, 1, pk);
+            const C *C0 = arr(2 * cs), *C1 = arr(2 * cs + 1);
+            const C *D0 = arr(4 + 2 * ds), *D1 = arr(5 + 2 * ds);
+            const C *D0n = arr(4 + 2 * dsn), *D1n = arr(5 + 2 * dsn);
+            cown[0] = C0[i];
+            cown[1] = C1[i];
+            down[0] = D0[i];
+            down[1] = D1[i];
+            const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
+                                              cown[0], cprev[0], C0[i + 1], C0[i + W],
+                                              cown[1], cprev[1], C1[i - W], C1[i - 1],
+                                              down[0], D0[i - 1], D0[i + W], D0n[i],
+                                              down[1], D1[i - W], D1[i + 1], D1n[i]);
+            ab1[0] = update(pab[0], S.s0, kA);
+            ab1[1] = update(pab[1], S.s1, kA);
+            ab1[2] = update(pab[2], S.s2, kB);
+            ab1[3] = update(pab[3], S.s3, kB);
+        }
+        // level 2: C,D of plane p-1 after step 1 (LDS: level 1 of plane p-1)
+        C cd1[4] = {zero, zero, zero, zero}, ab1h1[4] = {zero, zero, zero, zero};
+        const int q2 = p - 1;
+        // the own values of a level's LDS plane are read whenever that plane
+        // was produced (the next plane's window needs them even where this
+        // level is not evaluated); the level itself runs on the planes the
+        // next level consumes
+        const C *A0 = arr(10), *A1 = arr(11), *B0 = arr(12), *B1 = arr(13);
+        if (in2 && q2 >= z0 - 3) {
+            ab1h1[0] = A0[i];
+            ab1h1[1] = A1[i];
+            ab1h1[2] = B0[i];
+            ab1h1[3] = B1[i];
+        }
+        if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
+            const int qk = wrapn(q2, nz);
+            const Coef<R> kC = tcoef(a.tab, nz, 2, qk), kD = tcoef(a.tab, nz, 3, qk);
+            const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
+                                              ab1h1[0], ab1[0], A0[i + 1], A0[i + W],
+                                              ab1h1[1], ab1[1], A1[i - 1], A1[i - W],
+                                              ab1h1[2], ab1h2[2], B0[i - 1], B0[i + W],
+                                              ab1h1[3], ab1h2[3], B1[i + 1], B1[i - W]);
+            cd1[0] = update(cprev[0], S.s0, kC);
+            cd1[1] = update(cprev[1], S.s1, kC);
+            cd1[2] = update(dprev[0], S.s2, kD);
+            cd1[3] = update(dprev[1], S.s3, kD);
+        }
+        // level 3: A,B of plane p-2 after step 2 (LDS: level 2 of plane p-2)
+        C ab2[4] = {zero, zero, zero, zero}, cd1h1[4] = {zero, zero, zero, zero};
+        const int q3 = p - 2;
+        const C *C0 = arr(14), *C1 = arr(15), *D0 = arr(16), *D1 = arr(17);
+        if (in2 && q3 >= z0 - 2) {
+            cd1h1[0] = C0[i];
+            cd1h1[1] = C1[i];
+            cd1h1[2] = D0[i];
+            cd1h1[3] = D1[i];
+        }
+        if (in2 && q3 >= z0 - 1 && q3 <= z1) {
+            const int qk = wrapn(q3, nz);
+            const Coef<R> kA = tcoef(a.tab, nz, 0, qk), kB = tcoef(a.tab, nz, 1, qk);
+            const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
+                                              cd1h1[0], cd1h2[0], C0[i + 1], C0[i + W],
+                                              cd1h1[1], cd1h2[1], C1[i - W], C1[i - 1],
+                                              cd1h1[2], D0[i - 1], D0[i + W], cd1[2],
+                                              cd1h1[3], D1[i - W], D1[i + 1], cd1[3]);
+            ab2[0] = update(ab1h2[0], S.s0, kA);
+            ab2[1] = update(ab1h2[1], S.s1, kA);
+            ab2[2] = update(ab1h2[2], S.s2, kB);
+            ab2[3] = update(ab1h2[3], S.s3, kB);
+            if (in4 && q3 >= z0 && q3 < z1) {
+                const size_t Pq = (size_t)qk * plane;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) st_at(out[q] + Pq, go, ab2[q]);
+                if constexpr (NORM) {
+                    double pp = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        pp += (double)ab2[q].x * (double)ab2[q].x + (double)ab2[q].y * (double)ab2[q].y;
+                    nrm[0] += pp;
+                    nrm[1] += pp;
+                }
+            }
+        }
+        // level 4: C,D of plane p-3 after step 2 on the tile (LDS: level 3 of plane p-3)
+        C ab2h1[4] = {zero, zero, zero, zero};
+        const int q4 = p - 3;
+        const C *A20 = arr(18), *A21 = arr(19), *B20 = arr(20), *B21 = arr(21);
+        if (in4 && q4 >= z0 - 1) {
+            ab2h1[0] = A20[i];
+            ab2h1[1] = A21[i];
+            ab2h1[2] = B20[i];
+            ab2h1[3] = B21[i];
+        }
+        if (in4 && q4 >= z0 && q4 < z1) {
+            const int qk = wrapn(q4, nz);
+            const Coef<R> kC = tcoef(a.tab, nz, 2, qk), kD = tcoef(a.tab, nz, 3, qk);
+            const C *A0 = A20, *A1 = A21, *B0 = B20, *B1 = B21;
+            const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
+                                              ab2h1[0], ab2[0], A0[i + 1], A0[i + W],
+                                              ab2h1[1], ab2[1], A1[i - 1], A1[i - W],
+                                              ab2h1[2], b2h2[0], B0[i - 1], B0[i + W],
+                                              ab2h1[3], b2h2[1], B1[i + 1], B1[i - W]);
+            C o[4];
+            o[0] = update(cd1h2[0], S.s0, kC);
+            o[1] = update(cd1h2[1], S.s1, kC);
+            o[2] = update(cd1h2[2], S.s2, kD);
+            o[3] = update(cd1h2[3], S.s3, kD);
+            const size_t Pq = (size_t)qk * plane;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) st_at(out[4 + q] + Pq, go, o[q]);
+            if constexpr (NORM) {
+                // E_r in its C,D-summed form: |Y|^2 + Re conj(Y) S_Y(A,B)
+                const C sv[4] = {S.s0, S.s1, S.s2, S.s3};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double yre = (double)o[q].x, yim = (double)o[q].y;
+                    const double pp = yre * yre + yim * yim;
+                    nrm[0] += pp + (yre * (double)sv[q].x + yim * (double)sv[q].y);
+                    nrm[1] += pp;
+                }
+            }
+        }
+
+        __syncthreads();
+        // this iteration's level outputs become the LDS planes of the next one
+        if (in1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                arr(10 + q)[i] = ab1[q];
+                arr(14 + q)[i] = cd1[q];
+                arr(18 + q)[i] = ab2[q];
+            }
+        }
+        // advance the z windows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ab1h2[q] = ab1h1[q];
+            cd1h2[q] = cd1h1[q];
+            pab[q] = pabn[q];
+        }
+        b2h2[0] = ab2h1[2];
+        b2h2[1] = ab2h1[3];
+        cprev[0] = cown[0];
+        cprev[1] = cown[1];
+        dprev[0] = down[0];
+        dprev[1] = down[1];
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+    if constexpr (NORM) {
+        double *red = (double *)sm;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm[q] += __shfl_xor(nrm[q], off, 64);
+        }
+        if (lane == 0) {
+            red[2 * wv] = nrm[0];
+            red[2 * wv + 1] = nrm[1];
+        }
+        __syncthreads();
+        if (t == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < NT / 64; ++q) {
+                s0 += red[2 * q];
+                s1 += red[2 * q + 1];
+            }
+            a.npart[2 * blockIdx.x] = s0;
+            a.npart[2 * blockIdx.x + 1] = s1;
+        }
+    }
+}
+
+int chunks_for(int64_t tiles, int nz, int target) {
+    int64_t c = (target + tiles - 1) / tiles;
+    if (c < 1) c = 1;
+    if (c > nz) c = nz;
+    return (int)c;
+}
+
+}  // namespace
+
+bool fused3x2_supported(int nx, bool fp32, bool site) { return !site && (!fp32 || nx % 2 == 0); }
+
+template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStream_t s, int *nblocks_out) {
+    FusedArgs<R> a = a0;
+    if (a.tab == nullptr || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
+    constexpr int TW = sizeof(R) == 4 ? 64 : 32, TY = 8, NT = sizeof(R) == 4 ? 1024 : 512;
+    a.ntx = (a.nx + TW - 1) / TW;
+    a.nty = (a.ny + TY - 1) / TY;
+    const int64_t tiles = (int64_t)a.ntx * a.nty;
+    if (a.zchunk <= 0) {
+        const int nzc = chunks_for(tiles, a.nz, 1024);
+        a.zchunk = (a.nz + nzc - 1) / nzc;
+    }
+    a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
+    const int64_t nblk = tiles * a.nzc;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    if (nblocks_out) *nblocks_out = (int)nblk;
+    const bool norm = a.npart != nullptr;
+    if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;
+    if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true>), dim3((unsigned)nblk), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false>), dim3((unsigned)nblk), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fused3x2<float>(const FusedArgs<float> &, hipStream_t, int *);
+template hipError_t launch_fused3x2<double>(const FusedArgs<double> &, hipStream_t, int *);
+
+}  // namespace dirac

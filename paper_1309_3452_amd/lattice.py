@@ -127,8 +127,9 @@ class Lattice:
             ptr_array([t.data_ptr() for t in self.theta]), _stream_handle()), self._ctx)
 
     def set_kernel(self, kind: str = "auto", tile_y: int = 0, zchunk: int = 0):
+        """kind: "auto", "split", "fused" (one step per launch) or "fused2" (two)."""
         code = {"auto": _abi.DIRAC_KERNEL_AUTO, "split": _abi.DIRAC_KERNEL_SPLIT,
-                "fused": _abi.DIRAC_KERNEL_FUSED}[kind]
+                "fused": _abi.DIRAC_KERNEL_FUSED, "fused2": _abi.DIRAC_KERNEL_FUSED2}[kind]
         check(lib().dirac_set_kernel(self._ctx, code, int(tile_y), int(zchunk)), self._ctx)
 
     # -- time stepping -------------------------------------------------------

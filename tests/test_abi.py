@@ -73,6 +73,7 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_bind_scratch(c, ctypes.c_void_p(256), 16) == -2      # too small (checked before use)
     assert L.dirac_bind_scratch(c, ctypes.c_void_p(255), nb.value) == -1   # misaligned
     assert L.dirac_set_kernel(c, 7, 0, 0) == -1
+    assert L.dirac_set_kernel(c, 3, 0, 0) == 0
     assert L.dirac_set_kernel(c, 2, 5, 0) == -1
     assert L.dirac_set_mass_potential_z(c, 0.5, None, None, 7) == -2   # nz mismatch
     L.dirac_destroy(c)

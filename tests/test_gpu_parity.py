@@ -87,7 +87,7 @@ def test_2d_site_fields_parity(P, kernel, shape):
 # (3+1)D
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("kernel,tile_y,zchunk", [("split", 0, 0), ("fused", 4, 0), ("fused", 8, 7),
-                                                   ("fused", 4, 64)])
+                                                   ("fused", 4, 64), ("fused2", 0, 0), ("fused2", 0, 3)])
 @pytest.mark.parametrize("shape", [(70, 20, 22), (64, 8, 16), (5, 3, 1)])
 def test_3d_potential_z_parity(P, kernel, tile_y, zchunk, shape):
     nx, ny, nz = shape
@@ -154,7 +154,7 @@ def test_3d_reverse_parity(P):
 # (relative ~6e-8 each), accumulating coherently at worst: bound 1e-6 per
 # step relative L2 against the FP64 oracle.
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("kernel", ["split", "fused"])
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
 @pytest.mark.parametrize("nx,tile_y", [(70, 8), (71, 8), (262, 4)])
 def test_3d_fp32_vs_oracle(P, kernel, nx, tile_y):
     ny, nz = 17, 12
@@ -248,15 +248,16 @@ def test_batched_vs_oracle(P, mode, graph):
 # In-step conserved functional (fused kernel) against the standalone reduction
 # and the oracle: the same FP64 sums in another order.
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", ["fused", "fused2"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("shape", [(70, 20, 22), (130, 9, 5)])
-def test_step_norm_matches_reduction(P, dtype, shape):
+def test_step_norm_matches_reduction(P, dtype, shape, kernel):
     nx, ny, nz = shape
-    print("step_norm %s %s" % (shape, dtype), flush=True)
+    print("step_norm %s %s %s" % (shape, dtype, kernel), flush=True)
     v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
     f0 = rand_state((nz, ny, nx), 8, 91)
     lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
-    lat.set_kernel("fused")
+    lat.set_kernel(kernel)
     lat.set_potential_z(0.5, v_int, v_half)
     lat.load(f0)
     out = lat.step_norm(3).cpu().numpy()
@@ -278,3 +279,28 @@ def test_step_norm_matches_reduction(P, dtype, shape):
     out2 = lat.step_norm(1).cpu().numpy()
     ref2 = lat.norm()
     assert abs(out2[0] - ref2[1]) <= 1e-15 * ref2[2] and abs(out2[1] - ref2[2]) <= 1e-15 * ref2[2]
+
+
+# --------------------------------------------------------------------------
+# Two steps per launch: the same bits as one-step launches (same helpers, same
+# operation order), over ragged tiles, chunk boundaries, odd step counts and
+# tiny lattices whose rings wrap onto themselves.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("shape,zchunk,steps", [((70, 20, 22), 0, 6), ((64, 8, 16), 0, 7), ((130, 9, 5), 2, 5),
+                                                ((2, 1, 3), 0, 4), ((6, 4, 1), 0, 3), ((36, 17, 9), 4, 8)])
+def test_fused2_bitwise_equals_one_step(P, dtype, shape, zchunk, steps):
+    nx, ny, nz = shape
+    print("fused2 bitwise %s %s zc=%d n=%d" % (shape, dtype, zchunk, steps), flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 97)
+    res = []
+    for kernel in ("fused2", "fused"):
+        lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+        lat.set_kernel(kernel, 0, zchunk)
+        lat.set_potential_z(0.4, v_int, v_half)
+        lat.load(f0)
+        lat.step(steps)
+        res.append([t.cpu() for t in lat.state()])
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
