@@ -17,8 +17,8 @@
 // ping-pongs between two buffers exactly as in the one-step kernel.
 //
 // LDS holds, as (TW + 4) x (TY + 4) regions (cell (x, y) of the tile at
-// (y + 2)(TW + 4) + x + 2): the old C of 2 planes and D of 3 planes (one plane
-// ahead for the z-neighbour of B, one more in flight) and one plane of each
+// (y + 2)(TW + 4) + x + 2): the old C of plane p, D of planes p and p+1 (the
+// z-neighbour of B), the next C and D planes in flight, and one plane of each
 // level's output.  The old C,D region rows (ring columns included) are copied
 // global -> LDS asynchronously, one plane ahead.  Thread t owns region cell t
 // of every level: its z-neighbours and previous values X- stay in registers or
@@ -69,18 +69,26 @@ __device__ __forceinline__ void g2lds16(const void *gsrc, void *lds_wave_base) {
 }
 
 template <typename R, int TW, int TY, int NT, bool NORM>
-__global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
+__global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int W = TW + 4, H = TY + 4, RN = W * H;
-    constexpr int PAD = W + 2;                        // keeps +-1, +-W reads of edge cells inside sm
+    constexpr int PAD = W + 2;                        // keeps +-1, +-W reads of edge cells inside an array set
     constexpr int CPL = 16 / (int)sizeof(C);          // cells per 16-byte unit
     static_assert(RN <= NT, "one region cell per thread");
     static_assert((W / CPL) <= 64, "one wave instruction per region row");
     static_assert(PAD % 2 == 0 && W % 2 == 0 && RN % 2 == 0, "16-byte alignment of the LDS rows");
-    // LDS arrays (RN cells each): 0-1 C slot 0, 2-3 C slot 1, 4-9 D slots 0..2,
-    // 10-13 level-1 A0 A1 B0 B1, 14-17 level-2 C0 C1 D0 D1, 18-21 level-3 A0 A1 B0 B1
-    __shared__ __align__(16) C sm[PAD + 22 * RN + PAD];
-    auto arr = [&](int k) -> C * { return sm + PAD + k * RN; };
+    // LDS (RN cells per array).  The asynchronous copies land only in sStage,
+    // which the stencils never read, so the compiler need not wait for them
+    // before the stencils' LDS reads; the staged planes move into sOld at the
+    // end of the iteration.
+    //   sOld:   0-1 C(p), 2-3 D(p), 4-5 D(p+1)
+    //   sStage: 0-1 C(p+1), 2-3 D(p+2) in flight
+    //   sLev:   0-3 level-1 A0 A1 B0 B1, 4-7 level-2 C0 C1 D0 D1, 8-11 level-3 A0 A1 B0 B1
+    __shared__ __align__(16) C sOld[PAD + 6 * RN + PAD];
+    __shared__ __align__(16) C sStage[4 * RN];
+    __shared__ __align__(16) C sLev[PAD + 12 * RN + PAD];
+    auto old_ = [&](int k) -> C * { return sOld + PAD + k * RN; };
+    auto lev = [&](int k) -> C * { return sLev + PAD + k * RN; };
 
     int L = logical_block2();
     const int tx = L % a.ntx;
@@ -121,14 +129,14 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
     // straddles the wrap)
     const int rl = (w + 4) / CPL;                     // active lanes per row
     const uint32_t lxo = (uint32_t)wrapn(x0 - 2 + lane * CPL, nx) * CS;
-    auto copy_rows = [&](int pc, int cs, int pd, int ds, bool with_c) {
+    // dst(k): LDS array of C0, C1, D0, D1 (k = 0..3)
+    auto copy_rows = [&](int pc, int pd, bool with_c, auto dst_of) {
         const size_t Pc = (size_t)wrapn(pc, nz) * plane, Pd = (size_t)wrapn(pd, nz) * plane;
         for (int item = wv; item < 4 * H; item += NT / 64) {
             const int k = item / H, yy = item % H;
             if (yy >= h + 4 || (k < 2 && !with_c)) continue;
             const C *src = (k < 2 ? in[4 + k] + Pc : in[4 + k] + Pd) + (size_t)wrapn(y0 + yy - 2, ny) * nx;
-            C *dst = (k < 2 ? arr(2 * cs + k) : arr(4 + 2 * ds + (k - 2))) + yy * W;
-            if (lane < rl) g2lds16((const char *)src + lxo, dst);
+            if (lane < rl) g2lds16((const char *)src + lxo, dst_of(k) + yy * W);
         }
     };
 
@@ -143,9 +151,8 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
     const int ps = z0 - 3, pe = z1 + 2;
     {
         // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
-        const int cs = ps & 1;
-        copy_rows(ps, cs, ps, wrapn(ps, 3), true);
-        copy_rows(ps, cs, ps + 1, wrapn(ps + 1, 3), false);
+        copy_rows(ps, ps, true, [&](int k) { return old_(k); });
+        copy_rows(ps, ps + 1, false, [&](int k) { return old_(2 + k); });
         const size_t Pm = (size_t)wrapn(ps - 1, nz) * plane, P0 = (size_t)wrapn(ps, nz) * plane;
         if (in1) {
             cprev[0] = ld_at(in[4] + Pm, go);
@@ -161,12 +168,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         // keep the per-lane offset opaque, so that addresses stay a wave-uniform
         // plane base plus a 32-bit lane offset instead of hoisted 64-bit pairs
         asm volatile("" : "+v"(go));
-        const int cs = p & 1, ds = wrapn(p, 3), dsn = wrapn(p + 1, 3);
         const bool more = p < pe;
         C pabn[4] = {zero, zero, zero, zero};
         if (more) {
             // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
-            copy_rows(p + 1, (p + 1) & 1, p + 2, wrapn(p + 2, 3), true);
+            copy_rows(p + 1, p + 2, true, [&](int k) { return sStage + k * RN; });
             if (in1) {
                 const size_t Pn = (size_t)wrapn(p + 1, nz) * plane;
 #pragma unroll
@@ -178,10 +184,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         C ab1[4] = {zero, zero, zero, zero}, cown[2] = {zero, zero}, down[2] = {zero, zero};
         if (in1) {
             const int pk = wrapn(p, nz);
-            const Coef<R> kA = tcoef(a.tab, nz, 0, pk), kB = tcoef(a.tab, nz, 1, pk);
-            const C *C0 = arr(2 * cs), *C1 = arr(2 * cs + 1);
-            const C *D0 = arr(4 + 2 * ds), *D1 = arr(5 + 2 * ds);
-            const C *D0n = arr(4 + 2 * dsn), *D1n = arr(5 + 2 * dsn);
+            const Coef<R> kA = tcoef(tab, nz, 0, pk), kB = tcoef(tab, nz, 1, pk);
+            const C *C0 = old_(0), *C1 = old_(1);
+            const C *D0 = old_(2), *D1 = old_(3);
+            const C *D0n = old_(4), *D1n = old_(5);
             cown[0] = C0[i];
             cown[1] = C1[i];
             down[0] = D0[i];
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         // was produced (the next plane's window needs them even where this
         // level is not evaluated); the level itself runs on the planes the
         // next level consumes
-        const C *A0 = arr(10), *A1 = arr(11), *B0 = arr(12), *B1 = arr(13);
+        const C *A0 = lev(0), *A1 = lev(1), *B0 = lev(2), *B1 = lev(3);
         if (in2 && q2 >= z0 - 3) {
             ab1h1[0] = A0[i];
             ab1h1[1] = A1[i];
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         }
         if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
             const int qk = wrapn(q2, nz);
-            const Coef<R> kC = tcoef(a.tab, nz, 2, qk), kD = tcoef(a.tab, nz, 3, qk);
+            const Coef<R> kC = tcoef(tab, nz, 2, qk), kD = tcoef(tab, nz, 3, qk);
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab1h1[0], ab1[0], A0[i + 1], A0[i + W],
                                               ab1h1[1], ab1[1], A1[i - 1], A1[i - W],
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         // level 3: A,B of plane p-2 after step 2 (LDS: level 2 of plane p-2)
         C ab2[4] = {zero, zero, zero, zero}, cd1h1[4] = {zero, zero, zero, zero};
         const int q3 = p - 2;
-        const C *C0 = arr(14), *C1 = arr(15), *D0 = arr(16), *D1 = arr(17);
+        const C *C0 = lev(4), *C1 = lev(5), *D0 = lev(6), *D1 = lev(7);
         if (in2 && q3 >= z0 - 2) {
             cd1h1[0] = C0[i];
             cd1h1[1] = C1[i];
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         }
         if (in2 && q3 >= z0 - 1 && q3 <= z1) {
             const int qk = wrapn(q3, nz);
-            const Coef<R> kA = tcoef(a.tab, nz, 0, qk), kB = tcoef(a.tab, nz, 1, qk);
+            const Coef<R> kA = tcoef(tab, nz, 0, qk), kB = tcoef(tab, nz, 1, qk);
             const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
                                               cd1h1[0], cd1h2[0], C0[i + 1], C0[i + W],
                                               cd1h1[1], cd1h2[1], C1[i - W], C1[i - 1],
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         // level 4: C,D of plane p-3 after step 2 on the tile (LDS: level 3 of plane p-3)
         C ab2h1[4] = {zero, zero, zero, zero};
         const int q4 = p - 3;
-        const C *A20 = arr(18), *A21 = arr(19), *B20 = arr(20), *B21 = arr(21);
+        const C *A20 = lev(8), *A21 = lev(9), *B20 = lev(10), *B21 = lev(11);
         if (in4 && q4 >= z0 - 1) {
             ab2h1[0] = A20[i];
             ab2h1[1] = A21[i];
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         }
         if (in4 && q4 >= z0 && q4 < z1) {
             const int qk = wrapn(q4, nz);
-            const Coef<R> kC = tcoef(a.tab, nz, 2, qk), kD = tcoef(a.tab, nz, 3, qk);
+            const Coef<R> kC = tcoef(tab, nz, 2, qk), kD = tcoef(tab, nz, 3, qk);
             const C *A0 = A20, *A1 = A21, *B0 = B20, *B1 = B21;
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab2h1[0], ab2[0], A0[i + 1], A0[i + W],
@@ -299,15 +305,26 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
             }
         }
 
+        // all LDS reads of this iteration done, all copies landed
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        // this iteration's level outputs become the LDS planes of the next one
+        // this iteration's level outputs become the LDS planes of the next one;
+        // the staged old planes move up
         if (in1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                arr(10 + q)[i] = ab1[q];
-                arr(14 + q)[i] = cd1[q];
-                arr(18 + q)[i] = ab2[q];
+                lev(q)[i] = ab1[q];
+                lev(4 + q)[i] = cd1[q];
+                lev(8 + q)[i] = ab2[q];
             }
+        }
+        if (more && t < RN) {
+            old_(0)[i] = sStage[i];
+            old_(1)[i] = sStage[RN + i];
+            old_(2)[i] = old_(4)[i];
+            old_(3)[i] = old_(5)[i];
+            old_(4)[i] = sStage[2 * RN + i];
+            old_(5)[i] = sStage[3 * RN + i];
         }
         // advance the z windows
 #pragma unroll
@@ -322,12 +339,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a) {
         cprev[1] = cown[1];
         dprev[0] = down[0];
         dprev[1] = down[1];
-        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
 
     if constexpr (NORM) {
-        double *red = (double *)sm;
+        double *red = (double *)sLev;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
@@ -378,8 +394,8 @@ template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStre
     if (nblocks_out) *nblocks_out = (int)nblk;
     const bool norm = a.npart != nullptr;
     if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;
-    if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true>), dim3((unsigned)nblk), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false>), dim3((unsigned)nblk), dim3(NT), 0, s, a);
+    if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true>), dim3((unsigned)nblk), dim3(NT), 0, s, a, a.tab);
+    else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false>), dim3((unsigned)nblk), dim3(NT), 0, s, a, a.tab);
     return hipGetLastError();
 }
 
