@@ -20,9 +20,9 @@
 // (y + 2)(TW + 4) + x + 2): the old C of plane p, D of planes p and p+1 (the
 // z-neighbour of B), the next C and D planes in flight, and one plane of each
 // level's output.  The old C,D region rows (ring columns included) are copied
-// global -> LDS asynchronously, one plane ahead.  Thread t owns region cell t
-// of every level: its z-neighbours and previous values X- stay in registers or
-// are re-read from the level planes in LDS.
+// global -> LDS asynchronously, one plane ahead.  Each thread owns one region
+// cell of every level: its z-neighbours and previous values X- stay in
+// registers or are re-read from the level planes in LDS.
 //
 // The same stencil and update helpers as the other kernels evaluate every
 // value, with the same operation order, so the result is bitwise that of two
@@ -68,13 +68,45 @@ __device__ __forceinline__ void g2lds16(const void *gsrc, void *lds_wave_base) {
                                      (__attribute__((address_space(3))) void *)lds_wave_base, 16, 0, 0);
 }
 
+// Thread -> region cell.  The tile comes first (wave k holds tile row k, so
+// stores are whole aligned rows), then the one-cell ring (levels 1-3), then the
+// two-cell ring (level 1 only); with 16 waves the ring cells skip waves 12-14
+// so that the four SIMDs (wave w on SIMD w mod 4) get similar work.  Returns
+// the slot (-1: no cell) and the cell's coordinates relative to the tile.
+template <int TW, int TY, int NT> __device__ __forceinline__ int region_slot(int t, int &xr, int &yr) {
+    constexpr int N0 = TW * TY, N1 = 2 * (TW + 2) + 2 * TY, N2 = 2 * (TW + 4) + 2 * (TY + 2);
+    constexpr int SKIP0 = NT == 1024 ? 768 : NT, SKIP1 = NT == 1024 ? 960 : NT;
+    int r = t < SKIP0 ? t : (t >= SKIP1 ? t - (SKIP1 - SKIP0) : -1);
+    if (r >= N0 + N1 + N2) r = -1;
+    xr = -3;
+    yr = -3;
+    if (r < 0) return -1;
+    int u = r;
+    if (u < N0) {
+        xr = u % TW;
+        yr = u / TW;
+    } else if ((u -= N0) < N1) {
+        if (u < TW + 2) { xr = u - 1; yr = -1; }
+        else if (u < 2 * (TW + 2)) { xr = u - (TW + 2) - 1; yr = TY; }
+        else if (u < 2 * (TW + 2) + TY) { xr = -1; yr = u - 2 * (TW + 2); }
+        else { xr = TW; yr = u - 2 * (TW + 2) - TY; }
+    } else {
+        u -= N1;
+        if (u < TW + 4) { xr = u - 2; yr = -2; }
+        else if (u < 2 * (TW + 4)) { xr = u - (TW + 4) - 2; yr = TY + 1; }
+        else if (u < 2 * (TW + 4) + TY + 2) { xr = -2; yr = u - 2 * (TW + 4) - 1; }
+        else { xr = TW + 1; yr = u - 2 * (TW + 4) - (TY + 2) - 1; }
+    }
+    return r;
+}
+
 template <typename R, int TW, int TY, int NT, bool NORM>
 __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int W = TW + 4, H = TY + 4, RN = W * H;
     constexpr int PAD = W + 2;                        // keeps +-1, +-W reads of edge cells inside an array set
     constexpr int CPL = 16 / (int)sizeof(C);          // cells per 16-byte unit
-    static_assert(RN <= NT, "one region cell per thread");
+    static_assert(RN <= NT - (NT == 1024 ? 192 : 0), "one region cell per thread");
     static_assert((W / CPL) <= 64, "one wave instruction per region row");
     static_assert(PAD % 2 == 0 && W % 2 == 0 && RN % 2 == 0, "16-byte alignment of the LDS rows");
     // LDS (RN cells per array).  The asynchronous copies land only in sStage,
@@ -105,9 +137,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     constexpr uint32_t CS = sizeof(C);
 
     // the region cell of this thread: (xr, yr) relative to the tile origin
-    const int i = t;
-    const int xr = t % W - 2, yr = t / W - 2;
-    const bool in1 = t < RN && xr < w + 2 && yr < h + 2;                       // levels 1 (ring 2)
+    int xr, yr;
+    const int r = region_slot<TW, TY, NT>(t, xr, yr);
+    const int i = (yr + 2) * W + xr + 2;              // LDS index of the cell
+    const bool in1 = r >= 0 && xr < w + 2 && yr < h + 2;                       // levels 1 (ring 2)
     const bool in2 = in1 && xr >= -1 && xr <= w && yr >= -1 && yr <= h;        // levels 2, 3 (ring 1)
     const bool in4 = in1 && xr >= 0 && xr < w && yr >= 0 && yr < h;            // level 4 (tile)
     uint32_t go = in1 ? ((uint32_t)wrapn(y0 + yr, ny) * (uint32_t)nx + (uint32_t)wrapn(x0 + xr, nx)) * CS : 0u;
@@ -146,6 +179,13 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     C ab1h2[4] = {zero, zero, zero, zero};                // level 1 of plane p-2
     C cd1h2[4] = {zero, zero, zero, zero};                // level 2 of plane p-3
     C b2h2[2] = {zero, zero};                             // level 3 B of plane p-4
+    // per-iteration values; declared once so that lanes outside a level's box
+    // keep stale (unused) values instead of being cleared every plane
+    C pabn[4] = {zero, zero, zero, zero};
+    C ab1[4] = {zero, zero, zero, zero}, cown[2] = {zero, zero}, down[2] = {zero, zero};
+    C cd1[4] = {zero, zero, zero, zero}, ab1h1[4] = {zero, zero, zero, zero};
+    C ab2[4] = {zero, zero, zero, zero}, cd1h1[4] = {zero, zero, zero, zero};
+    C ab2h1[4] = {zero, zero, zero, zero};
     double nrm[2] = {0.0, 0.0};
 
     const int ps = z0 - 3, pe = z1 + 2;
@@ -169,7 +209,6 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         // plane base plus a 32-bit lane offset instead of hoisted 64-bit pairs
         asm volatile("" : "+v"(go));
         const bool more = p < pe;
-        C pabn[4] = {zero, zero, zero, zero};
         if (more) {
             // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
             copy_rows(p + 1, p + 2, true, [&](int k) { return sStage + k * RN; });
@@ -181,7 +220,6 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         }
 
         // level 1: A,B of plane p after step 1
-        C ab1[4] = {zero, zero, zero, zero}, cown[2] = {zero, zero}, down[2] = {zero, zero};
         if (in1) {
             const int pk = wrapn(p, nz);
             const Coef<R> kA = tcoef(tab, nz, 0, pk), kB = tcoef(tab, nz, 1, pk);
@@ -203,7 +241,6 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab1[3] = update(pab[3], S.s3, kB);
         }
         // level 2: C,D of plane p-1 after step 1 (LDS: level 1 of plane p-1)
-        C cd1[4] = {zero, zero, zero, zero}, ab1h1[4] = {zero, zero, zero, zero};
         const int q2 = p - 1;
         // the own values of a level's LDS plane are read whenever that plane
         // was produced (the next plane's window needs them even where this
@@ -230,7 +267,6 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             cd1[3] = update(dprev[1], S.s3, kD);
         }
         // level 3: A,B of plane p-2 after step 2 (LDS: level 2 of plane p-2)
-        C ab2[4] = {zero, zero, zero, zero}, cd1h1[4] = {zero, zero, zero, zero};
         const int q3 = p - 2;
         const C *C0 = lev(4), *C1 = lev(5), *D0 = lev(6), *D1 = lev(7);
         if (in2 && q3 >= z0 - 2) {
@@ -266,7 +302,6 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             }
         }
         // level 4: C,D of plane p-3 after step 2 on the tile (LDS: level 3 of plane p-3)
-        C ab2h1[4] = {zero, zero, zero, zero};
         const int q4 = p - 3;
         const C *A20 = lev(8), *A21 = lev(9), *B20 = lev(10), *B21 = lev(11);
         if (in4 && q4 >= z0 - 1) {
@@ -318,7 +353,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                 lev(8 + q)[i] = ab2[q];
             }
         }
-        if (more && t < RN) {
+        if (more && r >= 0) {
             old_(0)[i] = sStage[i];
             old_(1)[i] = sStage[RN + i];
             old_(2)[i] = old_(4)[i];
