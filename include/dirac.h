@@ -132,18 +132,33 @@ int dirac_set_mass_potential_z(dirac_ctx *ctx, double m, const double *v_int, co
                                int64_t nz);
 
 /*
- * Per-site mass and potential.  v_site[a] is a device array (real, float for
- * DIRAC_C64 and double for DIRAC_C128, one value per cell) holding V at the
- * sites of state array a, or NULL for V = 0 there.  theta[a] are caller-owned
- * device arrays of the same type and size that receive
- * theta = (dt/2)(+-m + V) (+ for A,B / u, - for C,D / v); they stay bound and
- * are read by every later step until replaced.  Asynchronous on stream.
+ * Per-site mass and potential (the time-averaged term of Eqs. ss1-ss4 with
+ * theta = (dt/2)(+-m + V) at every amplitude's own site: + for A,B / u, - for
+ * C,D / v).  v_site[a] is a device array (real, float for DIRAC_C64 and double
+ * for DIRAC_C128, one value per cell) holding V at the sites of state array a,
+ * or NULL for V = 0 there.  coef[a] are caller-owned device arrays, one record
+ * per cell, that receive the per-site coefficient record:
+ *   DIRAC_C128: theta itself (double);
+ *   DIRAC_C64:  gamma = 1 - alpha = 2 i theta / (1 + i theta) as a complex64
+ *               (8 bytes per site), rounded once to the float pair closest to
+ *               |1 - gamma| = 1 (beta = 1 - gamma/2 is derived in the kernels),
+ *               so no step re-evaluates the Cayley factors.
+ * theta is formed in FP64.  The arrays stay bound and are read by every later
+ * step until replaced.  Asynchronous on stream.
  */
-int dirac_theta_from_fields(dirac_ctx *ctx, double m, void *const v_site[], void *const theta[],
+int dirac_theta_from_fields(dirac_ctx *ctx, double m, void *const v_site[], void *const coef[],
                             void *stream);
 
-/* Bind already computed per-site theta arrays (same type and layout as above). */
-int dirac_set_theta_field(dirac_ctx *ctx, void *const theta[]);
+/* Bind already computed per-site coefficient arrays (format as above). */
+int dirac_set_theta_field(dirac_ctx *ctx, void *const coef[]);
+
+/*
+ * The complex64 per-site coefficient record from theta: coef[t] = gamma(theta[t])
+ * (format of dirac_theta_from_fields) for t < n.  theta: device array of n
+ * doubles; coef: device array of n complex64.  Context-free.  Asynchronous on
+ * stream; DIRAC_E_ARG for null pointers or n < 0, DIRAC_E_HIP on launch failure.
+ */
+int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream);
 
 /* Choose the step kernel and its tiling; 0 = library default for a knob.
  *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8
@@ -159,6 +174,11 @@ int dirac_set_kernel(dirac_ctx *ctx, int kernel, int tile_y, int zchunk);
  * Advance the bound state by n >= 0 full steps (Sect. 2: A,B from n-1/2 to
  * n+1/2 by Eqs. ss1, ss2, then C,D from n to n+1 by Eqs. ss3, ss4; Sect. 3:
  * u then v by Eqs. scheme2Deq-scheme4thline).  Asynchronous on stream.
+ * Each fused launch moves the state to the other bound buffer set (FUSED2:
+ * floor(n/2) two-step launches plus one one-step launch if n is odd; FUSED: n
+ * launches; SPLIT: in place).  A stream capture of step calls replays
+ * correctly any number of times only if the captured calls leave the state in
+ * the buffer set they started from: compare dirac_current before and after.
  */
 int dirac_step(dirac_ctx *ctx, int64_t n, void *stream);
 
@@ -241,10 +261,11 @@ int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const 
 
 /*
  * Bind the buffers of every lattice: state[4*b + a], partner[4*b + a] and
- * theta[4*b + a] for array a (u0 u1 v0 v1) of lattice b -- device pointers in
- * the single-lattice layout; theta real, float for C64 and double for C128,
- * holding (dt/2)(+-m + V) per site.  Also binds the scratch (see
- * dirac_scratch_bytes on the batch context).
+ * coef[4*b + a] for array a (u0 u1 v0 v1) of lattice b -- device pointers in
+ * the single-lattice layout; coef holds the per-site coefficient record of
+ * theta = (dt/2)(+-m + V) in the format of dirac_theta_from_fields (double
+ * theta for C128, complex64 gamma for C64, e.g. from dirac_coef_from_theta).
+ * Also binds the scratch (see dirac_scratch_bytes on the batch context).
  */
 int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[], void *const theta[],
                      void *scratch, size_t scratch_bytes);

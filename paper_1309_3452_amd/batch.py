@@ -40,8 +40,17 @@ class BatchedLattices:
                 v = torch.zeros(shp, dtype=torch.float64, device=self.device) if vs is None else \
                     torch.as_tensor(vs[a]).to(device=self.device, dtype=torch.float64)
                 sgn = 1.0 if a < 2 else -1.0
-                # theta = (dt/2)(+-m + V) per site (u: +m, v: -m), Eqs. scheme2Deq-scheme4thline
-                th.append((half * (sgn * m + v)).to(self.real_dtype).contiguous())
+                # theta = (dt/2)(+-m + V) per site (u: +m, v: -m), Eqs. scheme2Deq-scheme4thline,
+                # in FP64; complex64 batches bind the per-site gamma record made from it
+                theta = (half * (sgn * m + v)).contiguous()
+                if dtype == torch.complex64:
+                    coef = torch.empty(shp, dtype=torch.complex64, device=self.device)
+                    check(lib().dirac_coef_from_theta(ctypes.c_void_p(coef.data_ptr()),
+                                                      ctypes.c_void_p(theta.data_ptr()), theta.numel(),
+                                                      _stream_handle()))
+                    th.append(coef)
+                else:
+                    th.append(theta)
             self.theta.append(th)
         nbytes = ctypes.c_size_t()
         check(lib().dirac_scratch_bytes(ctx, ctypes.byref(nbytes)), ctx)

@@ -56,35 +56,55 @@ void cayley64(double th, double out[4]) {
 }
 
 // FP32 increment-form coefficients gamma = 2 i th / (1 + i th), beta = 1 / (1 + i th).
-// The rounded pair (gamma_re, gamma_im) is chosen among nearby floats to make
-// |1 - gamma|^2 = 1 as closely as FP32 allows (the factor multiplying X- is
-// then unit-modulus to ~1e-10, so the conserved functional does not drift
-// systematically where theta is constant over space).
+// The rounded pair (gamma_re, gamma_im) is chosen among pairs within
+// 1e-6 max(1, |gamma|) of the exact value to make |1 - gamma|^2 = 1 as closely
+// as FP32 allows (the factor multiplying X- is then unit-modulus to a few
+// 1e-9 typically, so the conserved functional does not drift systematically
+// where theta is constant over space).  Candidates: each component in turn as
+// the primary (up to 8 ulps from exact), the other derived from the unit
+// modulus on the side of the circle where the exact value lies (alpha_re
+// changes sign at |th| = 1) and tried within 2 ulps; ties go to the pair
+// closest to the exact value.  Same rule as the per-site records on the device.
+float step_f(float x, int dir) { return nextafterf(x, dir < 0 ? -INFINITY : INFINITY); }
 void cayley32(double th, float out[4]) {
 #pragma clang fp contract(off)
-    double d = 1.0 + th * th;
-    double gr0 = 2.0 * th * th / d, gi0 = 2.0 * th / d;
+    const double d = 1.0 + th * th;
+    const double gr0 = 2.0 * th * th / d, gi0 = 2.0 * th / d, ar0 = (1.0 - th * th) / d;
+    const double lim = 1e-6 * fmax(1.0, sqrt(gr0 * gr0 + gi0 * gi0));
     float best_r = (float)gr0, best_i = (float)gi0;
-    double best = 1e300;
-    float gi = (float)gi0;
-    for (int di = -4; di <= 4; ++di) {
-        float ci = gi;
-        for (int q = 0; q < (di < 0 ? -di : di); ++q) ci = nextafterf(ci, di < 0 ? -INFINITY : INFINITY);
-        double cid = (double)ci;
-        double gr_exact = cid * cid / (1.0 + sqrt(1.0 - cid * cid));
-        float cr = (float)gr_exact;
-        for (int dr = -2; dr <= 2; ++dr) {
+    double best = 1e300, best_d = 1e300;
+    auto consider = [&](float c, float ci) {
+        const double cd = (double)c, cid = (double)ci;
+        const double dist = fabs(cd - gr0) + fabs(cid - gi0);
+        if (dist > lim) return;
+        const double one_m = 1.0 - cd;
+        const double err = fabs(one_m * one_m + cid * cid - 1.0);
+        if (err < best || (err == best && dist < best_d)) {
+            best = err;
+            best_d = dist;
+            best_r = c;
+            best_i = ci;
+        }
+    };
+    for (int da = -8; da <= 8; ++da) {
+        float ci = (float)gi0;
+        for (int q = 0; q < (da < 0 ? -da : da); ++q) ci = step_f(ci, da);
+        const double cid = (double)ci;
+        const double sq = sqrt(fmax(0.0, 1.0 - cid * cid));
+        const float cr = ar0 >= 0.0 ? (float)(cid * cid / (1.0 + sq)) : (float)(1.0 + sq);
+        for (int db = -2; db <= 2; ++db) {
             float c = cr;
-            for (int q = 0; q < (dr < 0 ? -dr : dr); ++q) c = nextafterf(c, dr < 0 ? -INFINITY : INFINITY);
-            double one_m = 1.0 - (double)c;
-            double err = fabs(one_m * one_m + cid * cid - 1.0);
-            // prefer the candidate closest to the exact coefficients among equal errors
-            double dist = fabs((double)c - gr0) + fabs(cid - gi0);
-            if (err < best || (err == best && dist < fabs((double)best_r - gr0) + fabs((double)best_i - gi0))) {
-                best = err;
-                best_r = c;
-                best_i = ci;
-            }
+            for (int q = 0; q < (db < 0 ? -db : db); ++q) c = step_f(c, db);
+            consider(c, ci);
+        }
+        float c = (float)gr0;
+        for (int q = 0; q < (da < 0 ? -da : da); ++q) c = step_f(c, da);
+        const double a = 1.0 - (double)c;
+        const float ci0 = (float)copysign(sqrt(fmax(0.0, 1.0 - a * a)), gi0);
+        for (int db = -2; db <= 2; ++db) {
+            float cj = ci0;
+            for (int q = 0; q < (db < 0 ? -db : db); ++q) cj = step_f(cj, db);
+            consider(c, cj);
         }
     }
     out[0] = best_r;
@@ -401,6 +421,13 @@ int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
         if (!theta[q]) return fail(c, DIRAC_E_ARG, "null theta array %d", q);
     for (int q = 0; q < 8; ++q) c->theta[q] = q < narr ? theta[q] : nullptr;
     c->site_mode = true;
+    return DIRAC_OK;
+}
+
+int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream) {
+    if (!coef || !theta || n < 0) return DIRAC_E_ARG;
+    if (n == 0) return DIRAC_OK;
+    if (launch_coef_from_theta(coef, (const double *)theta, n, (hipStream_t)stream) != hipSuccess) return DIRAC_E_HIP;
     return DIRAC_OK;
 }
 

@@ -41,7 +41,7 @@ __device__ __forceinline__ int logical_block() {
 template <typename R, bool SITE>
 __device__ __forceinline__ Coef<R> fcoef(const FusedArgs<R> &a, int arr, int cls, int pk, size_t idx) {
     if constexpr (SITE) {
-        return coef_theta(a.th[arr][idx]);
+        return coef_site_at<R>(a.th[arr], idx, (R)1);
     } else {
         const R *e = a.tab + ((size_t)cls * a.nz + pk) * 4;
         Coef<R> k;

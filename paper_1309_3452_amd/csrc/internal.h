@@ -15,7 +15,7 @@ struct CPtr8 {
 // `f` holds the 8 (3D) or 4 (2D) state arrays, updated in place.
 template <typename R> struct HalfArgs {
     void *f[8];
-    const R *th[8];       // per-site theta (site mode), else null
+    const R *th[8];       // per-site coefficients (site mode: theta, or gamma pairs for FP32), else null
     const R *tab;         // [class][nz][4] coefficient table (profile mode), else null
     R rx, ry, rz;         // signed: negated for the reversed step
     R tsgn;               // +1 forward, -1 reversed (site mode)
@@ -75,6 +75,7 @@ template <typename R> hipError_t launch_obs3(const ReduceArgs<R> &a, hipStream_t
 template <typename R> hipError_t launch_seed3(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);
 template <typename R> hipError_t launch_theta_fields(void *const th[8], void *const v[8], int narr, int64_t ncell,
                                                      double half_dt, double m, hipStream_t s);
+hipError_t launch_coef_from_theta(void *coef, const double *theta, int64_t n, hipStream_t s);
 hipError_t launch_final_sum(const double *partial, int nblocks, int nv, double *out, hipStream_t s);
 
 // 2D split kernels (kernels2d.hip)

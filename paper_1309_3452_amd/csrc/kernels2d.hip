@@ -14,7 +14,7 @@ constexpr int kTX = 64, kTY = 4;
 template <typename R, bool SITE>
 __device__ __forceinline__ Coef<R> coef2(const HalfArgs<R> &a, int arr, int q, size_t c) {
     if constexpr (SITE) {
-        return coef_theta((R)(a.tsgn * a.th[arr][c]));
+        return coef_site_at<R>(a.th[arr], c, a.tsgn);
     } else {
         const R *e = a.tab + (size_t)q * a.nz * 4;    // plane 0 of class q
         Coef<R> k;

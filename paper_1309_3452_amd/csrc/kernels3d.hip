@@ -34,7 +34,7 @@ template <typename R> __device__ __forceinline__ Coef<R> tab_coef(const R *tab, 
 template <typename R, bool SITE>
 __device__ __forceinline__ Coef<R> coef_at(const HalfArgs<R> &a, int arr, int q, int k, size_t c) {
     if constexpr (SITE) {
-        return coef_theta((R)(a.tsgn * a.th[arr][c]));
+        return coef_site_at<R>(a.th[arr], c, a.tsgn);
     } else {
         return tab_coef(a.tab, q, a.nz, k);
     }
@@ -259,6 +259,13 @@ __global__ __launch_bounds__(256) void k3_seed(ReduceArgs<R> a, CPtr8 lam) {
     }
 }
 
+// Per-site coefficient arrays from V: theta = (dt/2)(+-m + V) in FP64, stored
+// as theta (complex128 lattices) or as the rounded gamma pair (complex64).
+__device__ __forceinline__ void put_site_coef(double *th, int64_t t, double theta) { th[t] = theta; }
+__device__ __forceinline__ void put_site_coef(float *th, int64_t t, double theta) {
+    ((float2 *)th)[t] = gamma32_search(theta);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_theta_fields(CPtr8 th, CPtr8 v, int narr, int64_t ncell, double half_dt,
                                                        double m) {
@@ -268,9 +275,14 @@ __global__ __launch_bounds__(256) void k_theta_fields(CPtr8 th, CPtr8 v, int nar
             // + for the first sheet's arrays (A,B / u), - for the second (C,D / v)
             double sgn = (q < narr / 2) ? 1.0 : -1.0;
             double vv = v.p[q] ? (double)((const R *)v.p[q])[t] : 0.0;
-            ((R *)th.p[q])[t] = (R)(half_dt * (sgn * m + vv));
+            put_site_coef((R *)th.p[q], t, half_dt * (sgn * m + vv));
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_coef_from_theta(float2 *coef, const double *theta, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        coef[t] = gamma32_search(theta[t]);
 }
 
 __global__ __launch_bounds__(256) void k_final_sum(const double *partial, int nblocks, int nv, double *out) {
@@ -337,6 +349,11 @@ hipError_t launch_theta_fields(void *const th[8], void *const v[8], int narr, in
     }
     hipLaunchKernelGGL((k_theta_fields<R>), dim3(grid_for(ncell, 256, 8192)), dim3(256), 0, s, t, vv, narr, ncell,
                        half_dt, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_from_theta(void *coef, const double *theta, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_coef_from_theta, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (float2 *)coef, theta, n);
     return hipGetLastError();
 }
 

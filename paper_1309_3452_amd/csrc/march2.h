@@ -21,7 +21,7 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 template <typename R, bool SITE>
 __device__ __forceinline__ Coef<R> fcoef2(const FusedArgs<R> &a, int arr, size_t idx) {
     if constexpr (SITE) {
-        return coef_theta(a.th[arr][idx]);
+        return coef_site_at<R>(a.th[arr], idx, (R)1);
     } else {
         const R *e = a.tab + (size_t)(arr < 2 ? 0 : 3) * a.nz * 4;
         Coef<R> k;

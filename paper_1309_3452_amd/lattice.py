@@ -115,9 +115,11 @@ class Lattice:
         self._pin = (vi, vh)
 
     def set_fields(self, m: float, v_site=None):
-        """Per-site potential: v_site[a] holds V at the sites of state array a."""
-        self.theta = [torch.empty(self.tshape, dtype=self.real_dtype, device=self.device)
-                      for _ in range(self.narr)]
+        """Per-site potential: v_site[a] holds V at the sites of state array a.
+        The per-site coefficient records are theta (complex128 lattices) or
+        gamma = 1 - alpha (complex64 lattices), see dirac_theta_from_fields."""
+        cdt = torch.complex64 if self.dtype == torch.complex64 else torch.float64
+        self.theta = [torch.empty(self.tshape, dtype=cdt, device=self.device) for _ in range(self.narr)]
         vs = None
         if v_site is not None:
             vs = [torch.as_tensor(v).to(device=self.device, dtype=self.real_dtype).contiguous() for v in v_site]

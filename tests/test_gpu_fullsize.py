@@ -254,7 +254,7 @@ def test_kernels_bitwise_equal(P, dtype):
 
 
 def test_graph_replay_single_lattice(P):
-    """A captured graph of 50 fused steps, replayed several times with eager work and
+    """A captured graph of 100 fused steps, replayed several times with eager work and
     synchronisation in between, matches eager stepping every time."""
     nx, ny, nz = 130, 24, 32
     print("graph replay", flush=True)
@@ -271,16 +271,18 @@ def test_graph_replay_single_lattice(P):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     cg = torch.cuda.CUDAGraph()
+    cur0 = graphed.current
     with torch.cuda.stream(s):
         with torch.cuda.graph(cg, stream=s):
-            graphed.step(50)
+            graphed.step(100)           # 50 two-step launches: an even number of buffer flips
     torch.cuda.current_stream().wait_stream(s)
-    # the capture recorded launches without running them; the context's notion of
-    # which buffer holds the state advanced by 50 (even) steps, i.e. unchanged
+    # the capture recorded launches without running them; a replayable capture
+    # ends on the buffer set it started from
+    assert graphed.current == cur0
     for rep in range(4):
         cg.replay()
         torch.cuda.synchronize()
-        eager.step(50)
+        eager.step(100)
         _ = torch.ones(10, device="cuda").sum().item()      # unrelated eager work
         torch.cuda.synchronize()
         for x, y in zip(graphed.state(), eager.state()):

@@ -304,3 +304,106 @@ def test_fused2_bitwise_equals_one_step(P, dtype, shape, zchunk, steps):
         res.append([t.cpu() for t in lat.state()])
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# complex64 per-site coefficient records: gamma = 1 - alpha rounded once per
+# site so that |1 - gamma| = 1 as closely as FP32 allows; beta = 1 - gamma/2.
+# --------------------------------------------------------------------------
+def test_fp32_site_coefficients(P):
+    import ctypes
+    g = np.random.default_rng(7)
+    th = np.concatenate([g.uniform(-2.0, 2.0, 200000), [0.0, 1e-8, -1e-8, 0.3, -0.3]])
+    t = torch.from_numpy(th).cuda()
+    out = torch.empty(th.size, dtype=torch.complex64, device="cuda")
+    out_neg = torch.empty_like(out)
+    tn = (-t).contiguous()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert P.lib().dirac_coef_from_theta(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                         th.size, s) == 0
+    assert P.lib().dirac_coef_from_theta(ctypes.c_void_p(out_neg.data_ptr()), ctypes.c_void_p(tn.data_ptr()),
+                                         th.size, s) == 0
+    assert P.lib().dirac_coef_from_theta(None, None, 1, s) == -1
+    gam = out.cpu().numpy().astype(np.complex128)
+    # unit modulus of the factor multiplying X- (the paper's alpha), per site
+    unit = np.abs((1.0 - gam.real) ** 2 + gam.imag ** 2 - 1.0)
+    # the FP32 grid leaves a residual of at most a few 1e-8 within 1e-6 of the
+    # exact value (typically ~1e-9)
+    assert unit.max() <= 8e-8, unit.max()
+    assert np.median(unit) <= 3e-9, np.median(unit)
+    exact = 2j * th / (1.0 + 1j * th)
+    # close to 2 i theta / (1 + i theta) on both sides of |theta| = 1, where the
+    # real part of the Cayley factor changes sign
+    assert np.max(np.abs(gam - exact) / np.maximum(1.0, np.abs(exact))) <= 1.01e-6
+    # theta -> -theta gives the conjugate record exactly (the reversed step uses this)
+    gn = out_neg.cpu().numpy()
+    assert np.array_equal(gn.real, out.cpu().numpy().real) and np.array_equal(gn.imag, -out.cpu().numpy().imag)
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_3d_site_fields_fp32_vs_oracle(P, kernel):
+    nx, ny, nz = 66, 9, 12
+    print("3d fields fp32 %s" % kernel, flush=True)
+    g = np.random.default_rng(43)
+    f0 = rand_state((nz, ny, nx), 8, 44)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((nz, ny, nx))).astype(np.float32) for _ in range(8)]
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
+    lat.set_kernel(kernel)
+    lat.load(f0)
+    f0_32 = np_state(lat.state())
+    lat.set_fields(0.3, [torch.from_numpy(v) for v in V])
+    lat.step(30)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    th = [np.ascontiguousarray(0.5 * DT3 * ((1.0 if a < 4 else -1.0) * 0.3 + V[a].astype(np.float64)))
+          for a in range(8)]
+    f = [a.copy() for a in f0_32]
+    ol.step(f, th, 30)
+    # a few FP32 roundings per amplitude and step (see the FP32 section above)
+    assert rel_l2(np_state(lat.state()), f) <= 30 * 1e-6
+    # the reversed step (conjugate records) brings the state back
+    lat.reverse(30)
+    assert rel_l2(np_state(lat.state()), f0_32) <= 60 * 1e-6
+
+
+def test_batched_fp32_site_vs_oracle(P):
+    sizes = [(64, 64), (96, 130), (17, 250), (1, 7)]
+    g = np.random.default_rng(83)
+    lats = []
+    for (nx, ny) in sizes:
+        lats.append(dict(nx=nx, ny=ny, m=float(g.uniform(0, 1)),
+                         v_site=[np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))).astype(np.float32)
+                                 for _ in range(4)],
+                         state=rand_state((ny, nx), 4, int(g.integers(1 << 30)))))
+    B = P.BatchedLattices(lats, dtype=torch.complex64, dt=DT2)
+    f32 = [np_state(B.state(b)) for b in range(len(lats))]
+    steps = 40
+    B.run(steps, mode=1, graph=False)
+    for b, L in enumerate(lats):
+        ol = oracle.Lattice2(L["nx"], L["ny"], DT2)
+        th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * L["m"] + L["v_site"][a].astype(np.float64)))
+              for a in range(4)]
+        f = [a.copy() for a in f32[b]]
+        ol.step(f, th, steps)
+        assert rel_l2(np_state(B.state(b)), f) <= steps * 1e-6, b
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
+def test_3d_fp32_large_theta_vs_oracle(P, kernel):
+    """|theta| > 1 on part of the lattice (strong potential step): the FP32 table
+    coefficients must sit on the correct side of the unit circle there."""
+    nx, ny, nz = 64, 10, 16
+    print("3d fp32 large theta %s" % kernel, flush=True)
+    v_int, v_half = workloads.step_potential(nz, 6.0, 8.0, 2.0)
+    f0 = rand_state((nz, ny, nx), 8, 71)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex64, dt=DT3)
+    lat.set_kernel(kernel)
+    lat.set_potential_z(0.5, v_int, v_half)
+    th_max = 0.5 * DT3 * (0.5 + max(np.max(v_int), np.max(v_half)))
+    assert th_max > 1.2
+    lat.load(f0)
+    f0_32 = np_state(lat.state())
+    lat.step(20)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    f = [a.copy() for a in f0_32]
+    ol.step(f, ol.theta_vz(0.5, v_int, v_half), 20)
+    assert rel_l2(np_state(lat.state()), f) <= 20 * 1e-6
