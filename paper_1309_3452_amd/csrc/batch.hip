@@ -2,16 +2,17 @@
 // masses and potentials (per-site theta) advanced together.
 //
 // Work is a flat list of items (lattice, x strip, y chunk); each item is one
-// workgroup's fused (2+1)D step over its strip and chunk (march2.h).
-//  mode 1: one launch per step over all items of all lattices;
-//  mode 0: one persistent launch for all steps.  Each workgroup takes items
-//          round-robin; before starting step s of an item of lattice b it
-//          waits until all items of b have finished step s-1 (a per-lattice
-//          counter, release/acquire at device scope).  The wait is bounded: a
-//          workgroup that waits too long raises a device-wide abort flag and
-//          every workgroup leaves, so the launch always ends; the host then
-//          reports the failure.  The grid is sized to the co-resident
-//          occupancy so all workgroups run at once.
+// workgroup's fused (2+1)D pass over its strip and chunk: one step (march2.h)
+// or two (march2x2.h), per the tuning candidate.
+//  mode 1: one launch per pass over all items of all lattices;
+//  mode 0: one persistent launch for all steps, one-step passes.  Each
+//          workgroup takes items round-robin; before starting step s of an
+//          item of lattice b it waits until all items of b have finished step
+//          s-1 (a per-lattice counter, release/acquire at device scope).  The
+//          wait is bounded: a workgroup that waits too long raises a
+//          device-wide abort flag and every workgroup leaves, so the launch
+//          always ends; the host then reports the failure.  The grid is sized
+//          to the co-resident occupancy so all workgroups run at once.
 // Both modes can be captured once into a HIP graph and replayed.  The tile
 // shape (strip width x chunk height) is chosen by timing candidates
 // (dirac_batch_autotune), with an optional JSON cache keyed by device and
@@ -28,6 +29,7 @@
 #include "ctx.h"
 #include "internal.h"
 #include "march2.h"
+#include "march2x2.h"
 
 using namespace dirac;
 
@@ -44,12 +46,15 @@ struct BatchItem {
     int lat, tx, yc, pad;
 };
 
+// strip width x chunk height, and steps per pass (1: march2, 2: march2x2)
 struct Cand {
-    int txb, ly;
+    int txb, ly, spp;
 };
-const Cand kCands[] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}, {256, 64}};
+const Cand kCands[] = {{64, 16, 1},  {64, 32, 1},  {128, 16, 1}, {128, 32, 1}, {128, 64, 1}, {256, 16, 1},
+                       {256, 32, 1}, {256, 64, 1}, {64, 64, 2},  {128, 32, 2}, {128, 64, 2}, {128, 128, 2},
+                       {256, 32, 2}, {256, 64, 2}, {256, 128, 2}};
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
-constexpr int kDefaultCand = 3;
+constexpr int kDefaultCand = 10;
 constexpr long kSpinLimit = 1L << 22;
 
 int bfail(dirac_ctx *c, int code, const char *fmt, ...) {
@@ -133,6 +138,20 @@ __global__ __launch_bounds__(TXB) void kb_step(const BatchLat *lats, const Batch
     const BatchLat &L = lats[w.lat];
     FusedArgs<R> a = item_args<R>(L, parity, ly, rx, ry);
     march2<R, true, TXB>(a, w.tx, w.yc, uu);
+}
+
+// Two steps per launch: every item's strip and chunk by march2x2.
+template <typename R, int TW>
+__global__ __launch_bounds__(TW + 64) void kb_step2(const BatchLat *lats, const BatchItem *items, int ly, int parity,
+                                                    R rx, R ry) {
+    constexpr int W = TW + 4;
+    __shared__ __align__(16) cx<R> sOld[2 + 4 * W + 2];
+    __shared__ __align__(16) cx<R> sStage[2 * W];
+    __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
+    const BatchItem w = items[blockIdx.x];
+    const BatchLat &L = lats[w.lat];
+    FusedArgs<R> a = item_args<R>(L, parity, ly, rx, ry);
+    march2x2<R, true, TW>(a, nullptr, w.tx, w.yc, sOld, sStage, sLev);
 }
 
 template <typename R, int TXB>
@@ -230,26 +249,64 @@ int upload_batch(dirac_ctx *c, int q, hipStream_t s, int64_t *nitems_out) {
     return DIRAC_OK;
 }
 
+// Two-step passes move whole rows in 16-byte units with a per-unit x wrap,
+// which needs an even row length for complex64: otherwise one-step passes.
+bool two_step_ok(const dirac_ctx *c) {
+    if (c->dtype != DIRAC_C64) return true;
+    for (int64_t b = 0; b < c->count; ++b)
+        if (c->bnx[(size_t)b] % 2 != 0) return false;
+    return true;
+}
+
+// Launch n steps starting from buffer set parity0; *flips receives the number
+// of ping-pong launches made (the state ends in set parity0 ^ (flips & 1)).
 template <typename R> int enqueue_run(dirac_ctx *c, int q, int64_t nitems, int64_t n, int mode, int parity0,
-                                      hipStream_t s) {
+                                      hipStream_t s, int64_t *flips) {
     const BLayout Ly = blayout(c);
     char *base = (char *)c->scratch;
     const BatchLat *lats = (const BatchLat *)(base + Ly.lats);
     const BatchItem *items = (const BatchItem *)(base + Ly.items);
     unsigned *done = (unsigned *)(base + Ly.done);
-    const Cand k = kCands[q];
+    Cand k = kCands[q];
+    if (k.spp == 2 && !two_step_ok(c)) k.spp = 1;
     const R r = (R)c->dt;
+    *flips = 0;
     if (n == 0) return DIRAC_OK;
+    const dim3 g((unsigned)nitems);
+    int par = parity0;
+    auto one_step = [&]() -> int {
+        if (k.txb == 64) hipLaunchKernelGGL((kb_step<R, 64>), g, dim3(64), 0, s, lats, items, k.ly, par, r, r);
+        else if (k.txb == 128) hipLaunchKernelGGL((kb_step<R, 128>), g, dim3(128), 0, s, lats, items, k.ly, par, r, r);
+        else hipLaunchKernelGGL((kb_step<R, 256>), g, dim3(256), 0, s, lats, items, k.ly, par, r, r);
+        BCHK(c, hipGetLastError());
+        par ^= 1;
+        ++*flips;
+        return DIRAC_OK;
+    };
+    auto two_steps = [&]() -> int {
+        if (k.txb == 64) hipLaunchKernelGGL((kb_step2<R, 64>), g, dim3(128), 0, s, lats, items, k.ly, par, r, r);
+        else if (k.txb == 128) hipLaunchKernelGGL((kb_step2<R, 128>), g, dim3(192), 0, s, lats, items, k.ly, par, r, r);
+        else hipLaunchKernelGGL((kb_step2<R, 256>), g, dim3(320), 0, s, lats, items, k.ly, par, r, r);
+        BCHK(c, hipGetLastError());
+        par ^= 1;
+        ++*flips;
+        return DIRAC_OK;
+    };
+    int64_t rest = n;
     if (mode == 1) {
-        for (int64_t t = 0; t < n; ++t) {
-            const int par = (int)((parity0 + t) & 1);
-            dim3 g((unsigned)nitems);
-            if (k.txb == 64) hipLaunchKernelGGL((kb_step<R, 64>), g, dim3(64), 0, s, lats, items, k.ly, par, r, r);
-            else if (k.txb == 128) hipLaunchKernelGGL((kb_step<R, 128>), g, dim3(128), 0, s, lats, items, k.ly, par, r, r);
-            else hipLaunchKernelGGL((kb_step<R, 256>), g, dim3(256), 0, s, lats, items, k.ly, par, r, r);
-            BCHK(c, hipGetLastError());
+        if (k.spp == 2)
+            for (; rest >= 2; rest -= 2) {
+                int rc = two_steps();
+                if (rc) return rc;
+            }
+        for (; rest > 0; --rest) {
+            int rc = one_step();
+            if (rc) return rc;
         }
-    } else {
+        return DIRAC_OK;
+    }
+    // mode 0: one persistent launch of one-step passes over all n steps
+    {
         int grid = 0;
         if (persistent_grid<R>(k.txb, &grid) || grid < 1)
             return bfail(c, DIRAC_E_HIP, "could not size the persistent grid");
@@ -259,21 +316,28 @@ template <typename R> int enqueue_run(dirac_ctx *c, int q, int64_t nitems, int64
         unsigned *abort_flag = done + c->count;
         if (k.txb == 64)
             hipLaunchKernelGGL((kb_persist<R, 64>), dim3(grid), dim3(64), 0, s, lats, items, (int)nitems, k.ly,
-                               parity0, (int)n, done, abort_flag, r, r);
+                               par, (int)n, done, abort_flag, r, r);
         else if (k.txb == 128)
             hipLaunchKernelGGL((kb_persist<R, 128>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
-                               parity0, (int)n, done, abort_flag, r, r);
+                               par, (int)n, done, abort_flag, r, r);
         else
             hipLaunchKernelGGL((kb_persist<R, 256>), dim3(grid), dim3(256), 0, s, lats, items, (int)nitems, k.ly,
-                               parity0, (int)n, done, abort_flag, r, r);
+                               par, (int)n, done, abort_flag, r, r);
         BCHK(c, hipGetLastError());
+        par ^= (int)(n & 1);
+        *flips += n;
+        rest = 0;
+    }
+    for (; rest > 0; --rest) {
+        int rc = one_step();
+        if (rc) return rc;
     }
     return DIRAC_OK;
 }
 
-int enqueue(dirac_ctx *c, int q, int64_t nitems, int64_t n, int mode, int parity0, hipStream_t s) {
-    return c->dtype == DIRAC_C64 ? enqueue_run<float>(c, q, nitems, n, mode, parity0, s)
-                                 : enqueue_run<double>(c, q, nitems, n, mode, parity0, s);
+int enqueue(dirac_ctx *c, int q, int64_t nitems, int64_t n, int mode, int parity0, hipStream_t s, int64_t *flips) {
+    return c->dtype == DIRAC_C64 ? enqueue_run<float>(c, q, nitems, n, mode, parity0, s, flips)
+                                 : enqueue_run<double>(c, q, nitems, n, mode, parity0, s, flips);
 }
 
 int check_abort(dirac_ctx *c, hipStream_t s) {
@@ -438,12 +502,14 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
         int64_t nitems = 0;
         int rc = upload_batch(c, q, s, &nitems);
         if (rc) return rc;
-        rc = enqueue(c, q, nitems, n, mode, c->cur, s);
+        int64_t flips = 0;
+        rc = enqueue(c, q, nitems, n, mode, c->cur, s, &flips);
         if (rc) return rc;
         if (mode == 0) {
             rc = check_abort(c, s);
             if (rc) return rc;
         }
+        if (flips & 1) c->cur = 1 - c->cur;
     } else {
         if (!(c->graph_exec && c->graph_n == n && c->graph_mode == (mode | (q << 4)) && c->graph_cur == c->cur)) {
             drop_graph(c);
@@ -452,7 +518,9 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
             int rc = upload_batch(c, q, c->graph_stream, &nitems);
             if (rc) return rc;
             BCHK(c, hipStreamBeginCapture(c->graph_stream, hipStreamCaptureModeRelaxed));
-            rc = enqueue(c, q, nitems, n, mode, c->cur, c->graph_stream);
+            int64_t flips = 0;
+            rc = enqueue(c, q, nitems, n, mode, c->cur, c->graph_stream, &flips);
+            c->graph_flips = flips;
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(c->graph_stream, &g);
             if (rc) {
@@ -471,8 +539,8 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
             int rc = check_abort(c, s);
             if (rc) return rc;
         }
+        if (c->graph_flips & 1) c->cur = 1 - c->cur;
     }
-    if (n & 1) c->cur = 1 - c->cur;
     return DIRAC_OK;
 }
 
@@ -528,18 +596,21 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
         hipEvent_t e0, e1;
         BCHK(c, hipEventCreate(&e0));
         BCHK(c, hipEventCreate(&e1));
-        const int warm = 2, timed = 8;   // even counts keep the state in the bound buffer set
+        const int warm = 2, timed = 8;
         for (int mode = 1; mode >= 0; --mode) {
             float best = 1e30f;
             for (int q = 0; q < kNumCands; ++q) {
                 int64_t nitems = 0;
                 int rc = upload_batch(c, q, s, &nitems);
                 if (rc) return rc;
-                rc = enqueue(c, q, nitems, warm, mode, c->cur, s);
+                int64_t flips = 0;
+                rc = enqueue(c, q, nitems, warm, mode, c->cur, s, &flips);
                 if (rc) return rc;
+                if (flips & 1) c->cur = 1 - c->cur;
                 BCHK(c, hipEventRecord(e0, s));
-                rc = enqueue(c, q, nitems, timed, mode, c->cur, s);
+                rc = enqueue(c, q, nitems, timed, mode, c->cur, s, &flips);
                 if (rc) return rc;
+                if (flips & 1) c->cur = 1 - c->cur;
                 BCHK(c, hipEventRecord(e1, s));
                 BCHK(c, hipEventSynchronize(e1));
                 if (mode == 0 && check_abort(c, s)) continue;   // candidate unusable here

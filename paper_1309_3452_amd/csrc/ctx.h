@@ -49,5 +49,6 @@ struct dirac_ctx {
     int64_t graph_n = -1;
     int graph_mode = -1;
     int graph_cur = -1;
+    int64_t graph_flips = 0;      // ping-pong launches in the captured graph
     hipStream_t graph_stream = nullptr;
 };

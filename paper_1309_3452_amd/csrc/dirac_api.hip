@@ -225,6 +225,12 @@ int kernel_choice(const dirac_ctx *c) {
     if (c->kernel == DIRAC_KERNEL_FUSED) return DIRAC_KERNEL_FUSED;
     if (c->ndim == 3 && fused3x2_supported((int)c->nx, c->dtype == DIRAC_C64, c->site_mode))
         return DIRAC_KERNEL_FUSED2;
+    // (2+1)D: two-step passes need long y chunks (a six-row pipeline per
+    // chunk), so small lattices keep the one-step march, which spreads them
+    // over more workgroups; an explicit FUSED2 request is honoured
+    if (c->ndim == 2 && fused2x2_supported((int)c->nx, c->dtype == DIRAC_C64) &&
+        (c->kernel == DIRAC_KERNEL_FUSED2 || c->nx * c->ny >= (int64_t)1 << 20))
+        return DIRAC_KERNEL_FUSED2;
     return DIRAC_KERNEL_FUSED;
 }
 
@@ -238,7 +244,8 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
     if (kc == DIRAC_KERNEL_FUSED2) {
         for (; t + 2 <= n; t += 2) {
             FusedArgs<R> a = fused_args<R>(c);
-            HIPCHK(c, launch_fused3x2<R>(a, s));
+            if (c->ndim == 3) HIPCHK(c, launch_fused3x2<R>(a, s));
+            else HIPCHK(c, launch_fused2x2<R>(a, site, s));
             c->cur = 1 - c->cur;
         }
     }

@@ -544,19 +544,28 @@ hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStrea
 
 template <typename R> hipError_t launch_fused2(const FusedArgs<R> &a0, bool site, hipStream_t s) {
     FusedArgs<R> a = a0;
-    constexpr int TXB = 128;
+    // small lattices (cache-resident, latency-bound): 64-wide strips and short
+    // chunks, so that many workgroups each march a few rows
+    const bool small = (int64_t)a.nx * a.ny < ((int64_t)1 << 18);
+    const int TXB = small ? 64 : 128;
     a.ntx = (a.nx + TXB - 1) / TXB;
     a.nty = 1;
     if (a.zchunk <= 0) {
         const int nc = default_chunks(a.ntx, a.ny, 4096);
         a.zchunk = (a.ny + nc - 1) / nc;
-        if (a.zchunk < 8 && a.ny >= 8) a.zchunk = 8;
+        const int zmin = small ? 4 : 8;
+        if (a.zchunk < zmin && a.ny >= zmin) a.zchunk = zmin;
     }
     a.nzc = (a.ny + a.zchunk - 1) / a.zchunk;
     const int64_t nblk = (int64_t)a.ntx * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    if (site) hipLaunchKernelGGL((k2_fused<R, true, TXB>), dim3((unsigned)nblk), dim3(TXB), 0, s, a);
-    else hipLaunchKernelGGL((k2_fused<R, false, TXB>), dim3((unsigned)nblk), dim3(TXB), 0, s, a);
+    if (TXB == 64) {
+        if (site) hipLaunchKernelGGL((k2_fused<R, true, 64>), dim3((unsigned)nblk), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k2_fused<R, false, 64>), dim3((unsigned)nblk), dim3(64), 0, s, a);
+    } else {
+        if (site) hipLaunchKernelGGL((k2_fused<R, true, 128>), dim3((unsigned)nblk), dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((k2_fused<R, false, 128>), dim3((unsigned)nblk), dim3(128), 0, s, a);
+    }
     return hipGetLastError();
 }
 

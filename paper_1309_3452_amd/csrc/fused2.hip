@@ -31,6 +31,7 @@
 #include "internal.h"
 #include "stencil3.h"
 #include "march2.h"
+#include "march2x2.h"
 
 namespace dirac {
 
@@ -401,6 +402,16 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     }
 }
 
+template <typename R, bool SITE, int TW>
+__global__ __launch_bounds__(TW + 64) void k2_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
+    constexpr int W = TW + 4;
+    __shared__ __align__(16) cx<R> sOld[2 + 4 * W + 2];
+    __shared__ __align__(16) cx<R> sStage[2 * W];
+    __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
+    const int L = logical_block2();
+    march2x2<R, SITE, TW>(a, tab, L % a.ntx, L / a.ntx, sOld, sStage, sLev);
+}
+
 int chunks_for(int64_t tiles, int nz, int target) {
     int64_t c = (target + tiles - 1) / tiles;
     if (c < 1) c = 1;
@@ -434,6 +445,29 @@ template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStre
     return hipGetLastError();
 }
 
+bool fused2x2_supported(int nx, bool fp32) { return !fp32 || nx % 2 == 0; }
+
+template <typename R> hipError_t launch_fused2x2(const FusedArgs<R> &a0, bool site, hipStream_t s) {
+    FusedArgs<R> a = a0;
+    if ((sizeof(R) == 4 && a.nx % 2 != 0) || (!site && a.tab == nullptr)) return hipErrorInvalidValue;
+    constexpr int TW = 128;
+    a.ntx = (a.nx + TW - 1) / TW;
+    a.nty = 1;
+    if (a.zchunk <= 0) {
+        const int nc = chunks_for(a.ntx, a.ny, 2048);
+        a.zchunk = (a.ny + nc - 1) / nc;
+        if (a.zchunk < 32 && a.ny >= 32) a.zchunk = 32;
+    }
+    a.nzc = (a.ny + a.zchunk - 1) / a.zchunk;
+    const int64_t nblk = (int64_t)a.ntx * a.nzc;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    if (site) hipLaunchKernelGGL((k2_fused2<R, true, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, a.tab);
+    else hipLaunchKernelGGL((k2_fused2<R, false, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, a.tab);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fused2x2<float>(const FusedArgs<float> &, bool, hipStream_t);
+template hipError_t launch_fused2x2<double>(const FusedArgs<double> &, bool, hipStream_t);
 template hipError_t launch_fused3x2<float>(const FusedArgs<float> &, hipStream_t, int *);
 template hipError_t launch_fused3x2<double>(const FusedArgs<double> &, hipStream_t, int *);
 

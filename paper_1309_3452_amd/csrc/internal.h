@@ -70,6 +70,9 @@ template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a, bool site,
 // Two steps per launch (fused2.hip); V(z) tables only, nx even for complex64.
 bool fused3x2_supported(int nx, bool fp32, bool site);
 template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a, hipStream_t s, int *nblocks_out = nullptr);
+// (2+1)D two steps per launch (fused2.hip, march2x2.h); nx even for complex64.
+bool fused2x2_supported(int nx, bool fp32);
+template <typename R> hipError_t launch_fused2x2(const FusedArgs<R> &a, bool site, hipStream_t s);
 template <typename R> hipError_t launch_norm3(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_obs3(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_seed3(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);

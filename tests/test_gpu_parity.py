@@ -407,3 +407,68 @@ def test_3d_fp32_large_theta_vs_oracle(P, kernel):
     f = [a.copy() for a in f0_32]
     ol.step(f, ol.theta_vz(0.5, v_int, v_half), 20)
     assert rel_l2(np_state(lat.state()), f) <= 20 * 1e-6
+
+
+# --------------------------------------------------------------------------
+# (2+1)D two steps per launch: the same bits as one-step launches.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("site", [False, True])
+@pytest.mark.parametrize("shape,steps", [((128, 128), 6), ((70, 33), 7), ((2, 5), 4), ((130, 1), 3), ((258, 40), 8)])
+def test_fused2_2d_bitwise_equals_one_step(P, dtype, site, shape, steps):
+    nx, ny = shape
+    print("fused2 2d bitwise %s %s site=%s n=%d" % (shape, dtype, site, steps), flush=True)
+    g = np.random.default_rng(101)
+    f0 = rand_state((ny, nx), 4, 102)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)]
+    res = []
+    for kernel in ("fused2", "fused"):
+        lat = P.Lattice2D(nx, ny, dtype=dtype, dt=DT2)
+        lat.set_kernel(kernel)
+        if site:
+            lat.set_fields(0.4, [torch.from_numpy(v) for v in V])
+        else:
+            lat.set_potential_z(0.4)
+        lat.load(f0)
+        lat.step(steps)
+        res.append([t.cpu() for t in lat.state()])
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
+def _batch_key(P, lats, dtype):
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    cells = sum(L["nx"] * L["ny"] for L in lats)
+    mx = max(L["nx"] for L in lats)
+    my = max(L["ny"] for L in lats)
+    return "%s/%s/n%d/cells%d/max%dx%d" % (arch, "c64" if dtype == torch.complex64 else "c128", len(lats), cells, mx, my)
+
+
+@pytest.mark.parametrize("cand", [0, 5, 7, 8, 9, 12, 14])
+@pytest.mark.parametrize("mode", [1, 0])
+def test_batched_candidates_vs_oracle(P, cand, mode, tmp_path):
+    """Every tile shape (one- and two-step passes, strip widths 64-256), forced through
+    the tuning cache, against the oracle (complex128, 1e-13)."""
+    import json
+    print("batched cand=%d mode=%d" % (cand, mode), flush=True)
+    sizes = [(64, 64), (96, 130), (200, 33), (17, 250), (2, 7), (300, 96)]
+    g = np.random.default_rng(91)
+    lats = []
+    for (nx, ny) in sizes:
+        lats.append(dict(nx=nx, ny=ny, m=float(g.uniform(0, 1)),
+                         v_site=[np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)],
+                         state=rand_state((ny, nx), 4, int(g.integers(1 << 30)))))
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({_batch_key(P, lats, torch.complex128): [cand, cand]}))
+    B = P.BatchedLattices(lats, dtype=torch.complex128, dt=DT2)
+    assert B.autotune(str(cache)) == (cand, cand)
+    steps = 9
+    B.run(steps, mode=mode, graph=(cand % 2 == 0))
+    for b, L in enumerate(lats):
+        ol = oracle.Lattice2(L["nx"], L["ny"], DT2)
+        th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * L["m"] + L["v_site"][a]))
+              for a in range(4)]
+        f = [a.copy() for a in L["state"]]
+        ol.step(f, th, steps)
+        assert rel_l2(np_state(B.state(b)), f) <= 1e-13, b
