@@ -54,6 +54,8 @@ def lib():
         P = ctypes.c_void_p
         for name in ("oracle_step3", "oracle_reverse3", "oracle_step2", "oracle_reverse2"):
             getattr(L, name).argtypes = [P, P, P, P]
+        for name in ("oracle_step3c", "oracle_step2c"):
+            getattr(L, name).argtypes = [P, P, P, P, P]
         for name in ("oracle_energy3", "oracle_energy2"):
             getattr(L, name).argtypes = [P, P, P, P]
         L.oracle_observe3.argtypes = [P, P, ctypes.c_double, P]
@@ -124,8 +126,14 @@ class Lattice3:
         return [np.ascontiguousarray(0.5 * self.dt * ((1.0 if a < 4 else -1.0) * m + zsheet[a]))
                 for a in range(8)]
 
-    def step(self, f, th, n=1):
+    def step(self, f, th, n=1, thi=None):
+        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential)."""
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
+        if thi is not None:
+            ti = _ptrs(thi, np.float64)
+            for _ in range(n):
+                _check(lib().oracle_step3c(self.n, self.r, p, t, ti), "oracle_step3c")
+            return
         for _ in range(n):
             _check(lib().oracle_step3(self.n, self.r, p, t), "oracle_step3")
 
@@ -181,8 +189,14 @@ class Lattice2:
             th.append(np.ascontiguousarray(0.5 * self.dt * (sgn * mv + vv), dtype=np.float64))
         return th
 
-    def step(self, f, th, n=1):
+    def step(self, f, th, n=1, thi=None):
+        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential)."""
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
+        if thi is not None:
+            ti = _ptrs(thi, np.float64)
+            for _ in range(n):
+                _check(lib().oracle_step2c(self.n, self.r, p, t, ti), "oracle_step2c")
+            return
         for _ in range(n):
             _check(lib().oracle_step2(self.n, self.r, p, t), "oracle_step2")
 

@@ -72,8 +72,10 @@ class Dense3:
 
     def step_matrix(self, theta):
         """One full step for per-site theta (vector of length dim; first half on
-        sheet n for A,B, second half on sheet n+1/2 for C,D)."""
-        theta = np.asarray(theta, np.float64)
+        sheet n for A,B, second half on sheet n+1/2 for C,D); theta may be
+        complex (a complex potential)."""
+        theta = np.asarray(theta)
+        theta = theta.astype(np.complex128) if np.iscomplexobj(theta) else theta.astype(np.float64)
         h = self.dim // 2
         alpha = (1 - 1j * theta) / (1 + 1j * theta)
         beta = 1.0 / (1 + 1j * theta)
@@ -135,7 +137,8 @@ class Dense2:
         return K
 
     def step_matrix(self, theta):
-        theta = np.asarray(theta, np.float64)
+        theta = np.asarray(theta)
+        theta = theta.astype(np.complex128) if np.iscomplexobj(theta) else theta.astype(np.float64)
         h = self.dim // 2
         alpha = (1 - 1j * theta) / (1 + 1j * theta)
         beta = 1.0 / (1 + 1j * theta)

@@ -151,6 +151,21 @@ static void cayley(double th, cplx *alpha, cplx *beta) {
     *beta = 1.0 / d - I * (th / d);
 }
 
+/* The same relation for a complex theta = th + i thi (a complex potential V,
+ * whose imaginary part damps or amplifies, Sect. 3 stability discussion):
+ * alpha = (1 - i theta)/(1 + i theta), beta = 1/(1 + i theta) in complex
+ * arithmetic.  thi = 0 is left to cayley() above. */
+static void cayley_c(double th, double thi, cplx *alpha, cplx *beta) {
+    if (thi == 0.0) {
+        cayley(th, alpha, beta);
+        return;
+    }
+    cplx t = th + I * thi;
+    cplx d = 1.0 + I * t;
+    *beta = 1.0 / d;
+    *alpha = (1.0 - I * t) / d;
+}
+
 /* doubled position of cell (i,j,k) of array a */
 #define POS3(a, i, j, k) (2 * (i) + OFF3[a][0]), (2 * (j) + OFF3[a][1]), (2 * (k) + OFF3[a][2])
 
@@ -162,7 +177,7 @@ static void cayley(double th, cplx *alpha, cplx *beta) {
  * components, so the update is done in place.
  */
 static void half3(const lat3 *L, int a_lo, const double r[3], const double *const th[8],
-                  double tsgn, double sgn) {
+                  const double *const thi[8], double tsgn, double sgn) {
     for (int a = a_lo; a < a_lo + 4; ++a) {
         int comp = a / 2;
 #pragma omp parallel for schedule(static)
@@ -171,7 +186,8 @@ static void half3(const lat3 *L, int a_lo, const double r[3], const double *cons
                 for (int64_t i = 0; i < L->nx; ++i) {
                     int64_t c = (k * L->ny + j) * L->nx + i;
                     cplx al, be;
-                    cayley(tsgn * th[a][c], &al, &be);
+                    if (thi) cayley_c(tsgn * th[a][c], tsgn * thi[a][c], &al, &be);
+                    else cayley(tsgn * th[a][c], &al, &be);
                     cplx s = stencil3(L, comp, POS3(a, i, j, k), r);
                     L->f[a][c] = al * L->f[a][c] - sgn * be * s;
                 }
@@ -195,8 +211,20 @@ int oracle_step3(const int64_t n[3], const double r[3], void *const f[8], const 
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half3(&L, 0, r, th, 1.0, 1.0);
-    half3(&L, 4, r, th, 1.0, 1.0);
+    half3(&L, 0, r, th, NULL, 1.0, 1.0);
+    half3(&L, 4, r, th, NULL, 1.0, 1.0);
+    return g_bad_lookup ? -2 : 0;
+}
+
+/* oracle_step3 with a complex theta: thi[a] holds Im theta at the sites of
+ * array a, i.e. (dt/2) Im V (the mass is real). */
+int oracle_step3c(const int64_t n[3], const double r[3], void *const f[8], const double *const th[8],
+                  const double *const thi[8]) {
+    lat3 L;
+    if (mk3(&L, n, f) || !thi) return -1;
+    g_bad_lookup = 0;
+    half3(&L, 0, r, th, thi, 1.0, 1.0);
+    half3(&L, 4, r, th, thi, 1.0, 1.0);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -206,8 +234,8 @@ int oracle_reverse3(const int64_t n[3], const double r[3], void *const f[8], con
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half3(&L, 4, r, th, -1.0, -1.0);
-    half3(&L, 0, r, th, -1.0, -1.0);
+    half3(&L, 4, r, th, NULL, -1.0, -1.0);
+    half3(&L, 0, r, th, NULL, -1.0, -1.0);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -445,7 +473,7 @@ static cplx stencil2(const lat2 *L, int comp, int64_t X, int64_t Y, const double
 }
 
 static void half2(const lat2 *L, int a_lo, const double r[3], const double *const th[4],
-                  double tsgn, double sgn) {
+                  const double *const thi[4], double tsgn, double sgn) {
     for (int a = a_lo; a < a_lo + 2; ++a) {
         int comp = a / 2;
 #pragma omp parallel for schedule(static)
@@ -453,7 +481,8 @@ static void half2(const lat2 *L, int a_lo, const double r[3], const double *cons
             for (int64_t i = 0; i < L->nx; ++i) {
                 int64_t c = j * L->nx + i;
                 cplx al, be;
-                cayley(tsgn * th[a][c], &al, &be);
+                if (thi) cayley_c(tsgn * th[a][c], tsgn * thi[a][c], &al, &be);
+                else cayley(tsgn * th[a][c], &al, &be);
                 cplx s = stencil2(L, comp, 2 * i + OFF2[a][0], 2 * j + OFF2[a][1], r);
                 L->f[a][c] = al * L->f[a][c] - sgn * be * s;
             }
@@ -476,8 +505,19 @@ int oracle_step2(const int64_t n[2], const double r[3], void *const f[4], const 
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half2(&L, 0, r, th, 1.0, 1.0);
-    half2(&L, 2, r, th, 1.0, 1.0);
+    half2(&L, 0, r, th, NULL, 1.0, 1.0);
+    half2(&L, 2, r, th, NULL, 1.0, 1.0);
+    return g_bad_lookup ? -2 : 0;
+}
+
+/* oracle_step2 with a complex theta (thi = Im theta per site, see oracle_step3c). */
+int oracle_step2c(const int64_t n[2], const double r[3], void *const f[4], const double *const th[4],
+                  const double *const thi[4]) {
+    lat2 L;
+    if (mk2(&L, n, f) || !thi) return -1;
+    g_bad_lookup = 0;
+    half2(&L, 0, r, th, thi, 1.0, 1.0);
+    half2(&L, 2, r, th, thi, 1.0, 1.0);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -485,8 +525,8 @@ int oracle_reverse2(const int64_t n[2], const double r[3], void *const f[4], con
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half2(&L, 2, r, th, -1.0, -1.0);
-    half2(&L, 0, r, th, -1.0, -1.0);
+    half2(&L, 2, r, th, NULL, -1.0, -1.0);
+    half2(&L, 0, r, th, NULL, -1.0, -1.0);
     return g_bad_lookup ? -2 : 0;
 }
 

@@ -500,3 +500,109 @@ def test_adjoint_theta_gradient_fd(dim):
             vals.append(loss(f))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - gth[a][idx]) < 1e-6 * max(1.0, abs(fd)), (a, idx, fd, gth[a][idx])
+
+
+# --------------------------------------------------------------------------
+# Complex potential (absorbing layers): theta = (dt/2)(+-m + V) with complex V.
+# Sect. 3 stability discussion: the growth factors have modulus below one when
+# the imaginary part has the damping sign.  In the Cayley form used here that
+# sign is Im V < 0 (|1 - i theta| < |1 + i theta| iff Im theta < 0).
+# --------------------------------------------------------------------------
+def _rand_thi(shape, count, g, lo=-0.4, hi=0.2):
+    return [np.ascontiguousarray(g.uniform(lo, hi, shape)) for _ in range(count)]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_complex_theta_dense_matches_oracle(dim):
+    """Brute force: the oracle's complex-theta step equals the dense one-step
+    matrix assembled from coordinates with alpha, beta of the complex theta."""
+    g = rng(201)
+    if dim == 3:
+        lat, D, cnt = oracle.Lattice3(3, 2, 4, DT3), Dense3(3, 2, 4, DT3), 8
+    else:
+        lat, D, cnt = oracle.Lattice2(4, 3, DT2), Dense2(4, 3, DT2), 4
+    f = rand_state(lat.shape, cnt, g)
+    x = D.pack(f)
+    for _ in range(3):
+        th = rand_theta(lat.shape, cnt, g)
+        thi = _rand_thi(lat.shape, cnt, g)
+        lat.step(f, th, thi=thi)
+        x = D.step_matrix(D.pack(th).real + 1j * D.pack(thi).real) @ x
+    assert rel_l2([D.pack(f)], [x]) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_complex_theta_dissipation_identity(dim):
+    """Multiplying (X+ - X-) + S_X = -i theta (X+ + X-) by conj(X+ + X-), taking
+    real parts and summing over both half-steps, the cross terms telescope into
+    the conserved functional (anti-Hermitian stencils), leaving
+      E_r(n+1) - E_r(n) = sum_sites Im(theta) |X+ + X-|^2
+    exactly; it vanishes for real theta (the Lemma of Sect. 2) and is <= 0 when
+    Im theta <= 0 everywhere."""
+    g = rng(202)
+    if dim == 3:
+        lat, cnt = oracle.Lattice3(6, 5, 7, DT3), 8
+    else:
+        lat, cnt = oracle.Lattice2(9, 8, DT2), 4
+    f0 = rand_state(lat.shape, cnt, g)
+    th = rand_theta(lat.shape, cnt, g)
+    for lo, hi in ((-0.3, 0.25), (-0.3, 0.0)):
+        thi = _rand_thi(lat.shape, cnt, g, lo, hi)
+        f = [a.copy() for a in f0]
+        e0 = lat.energy(f)[0]
+        lat.step(f, th, thi=thi)
+        e1 = lat.energy(f)[0]
+        rhs = sum(float(np.sum(thi[a] * np.abs(f[a] + f0[a]) ** 2)) for a in range(cnt))
+        scale = sum(float(np.sum(np.abs(a) ** 2)) for a in f0)
+        assert abs((e1 - e0) - rhs) <= 1e-13 * scale, (e1 - e0, rhs)
+        if hi <= 0.0:
+            assert e1 < e0
+
+
+def _amplification_2d(k, m, V, dt):
+    """2x2 amplification matrix of the (2+1)D scheme for a plane wave (u at
+    n-1/2, v at n) with uniform complex V: Fourier symbols of the stencils of
+    Eqs. scheme2Deq-scheme4thline on the staggered positions,
+      (1 + i th_u) u+ = (1 - i th_u) u- - s_u v-,
+      (1 + i th_v) v+ = (1 - i th_v) v- - s_v u+,
+    s_u = r (2i sin(kx/2) + 2 sin(ky/2)), s_v = r (2i sin(kx/2) - 2 sin(ky/2))."""
+    r = dt
+    th_u, th_v = 0.5 * dt * (m + V), 0.5 * dt * (-m + V)
+    su = r * (2j * np.sin(k[0] / 2) + 2 * np.sin(k[1] / 2))
+    sv = r * (2j * np.sin(k[0] / 2) - 2 * np.sin(k[1] / 2))
+    S = np.array([[1 + 1j * th_u, 0], [sv, 1 + 1j * th_v]])
+    T = np.array([[1 - 1j * th_u, -su], [0, 1 - 1j * th_v]])
+    return np.linalg.solve(S, T)
+
+
+@pytest.mark.parametrize("V", [-0.2j, 0.3 - 0.4j, 0.8j, 0.5])
+def test_complex_potential_plane_wave_2d(V):
+    """A plane-wave eigenvector of the amplification matrix decays (or grows) by
+    its eigenvalue per step in the oracle; the matrix's determinant and trace
+    are the paper's Q and P (P with the Delta_t^2 factor on the 4 c^2 term
+    restored); |lambda| < 1 exactly when Im V < 0."""
+    m, dt, n = 0.3, DT2, 32
+    k = (2 * np.pi * 3 / n, 2 * np.pi * 5 / n)
+    G = _amplification_2d(k, m, V, dt)
+    # the paper's closed forms (hbar = c = 1, unit spacing)
+    N = 4 + (m * m - V * V) * dt * dt + 4j * V * dt
+    Q = (4 + (m * m - V * V) * dt * dt - 4j * V * dt) / N
+    P = -2 * ((m * m - V * V) * dt * dt - 4 * (1 - 2 * dt * dt)
+              - 4 * dt * dt * (np.cos(k[0]) + np.cos(k[1]))) / N
+    assert abs(np.linalg.det(G) - Q) < 1e-13 and abs(np.trace(G) - P) < 1e-13
+    lam, vec = np.linalg.eig(G)
+    for q in range(2):
+        if np.imag(V) < 0:
+            assert abs(lam[q]) < 1.0
+        elif np.imag(V) > 0:
+            assert abs(lam[q]) > 1.0
+        else:
+            assert abs(abs(lam[q]) - 1.0) < 1e-14
+        f = plane_wave2((n, n), k, vec[:, q], 0.0, dt)
+        lat = oracle.Lattice2(n, n, dt)
+        th = [np.full((n, n), 0.5 * dt * ((1.0 if a < 2 else -1.0) * m + np.real(V))) for a in range(4)]
+        thi = [np.full((n, n), 0.5 * dt * np.imag(V)) for a in range(4)]
+        f0 = [a.copy() for a in f]
+        steps = 20
+        lat.step(f, th, steps, thi=thi)
+        assert rel_l2(f, [lam[q] ** steps * a for a in f0]) < 1e-12
