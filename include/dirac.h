@@ -132,6 +132,20 @@ int dirac_set_mass_potential_z(dirac_ctx *ctx, double m, const double *v_int, co
                                int64_t nz);
 
 /*
+ * Imaginary part of a z-dependent potential, V(z) = V_re(z) + i W(z): absorbing
+ * layers (the growth factors of Sect. 3's stability analysis have modulus
+ * below one where the imaginary part has the damping sign; in the Cayley form
+ * alpha = (1 - i theta)/(1 + i theta) used here that is W < 0).  w_int[k] =
+ * W(z = k) (A, D sites), w_half[k] = W(z = k+1/2) (B, C sites): host arrays of
+ * nz doubles, or both NULL (or all zero) for none.  Combines with
+ * dirac_set_mass_potential_z; the tables hold the complex Cayley factors from
+ * the next launch on.  With W != 0 the functional E_r decreases by
+ * sum Im(theta) |X+ + X-|^2 per step; the reversed step amplifies (it is the
+ * exact inverse) and dirac_adjoint_vz is refused (DIRAC_E_STATE).
+ */
+int dirac_set_potential_im_z(dirac_ctx *ctx, const double *w_int, const double *w_half, int64_t nz);
+
+/*
  * Per-site mass and potential (the time-averaged term of Eqs. ss1-ss4 with
  * theta = (dt/2)(+-m + V) at every amplitude's own site: + for A,B / u, - for
  * C,D / v).  v_site[a] is a device array (real, float for DIRAC_C64 and double
@@ -159,6 +173,15 @@ int dirac_set_theta_field(dirac_ctx *ctx, void *const coef[]);
  * stream; DIRAC_E_ARG for null pointers or n < 0, DIRAC_E_HIP on launch failure.
  */
 int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream);
+
+/*
+ * As dirac_coef_from_theta for a complex theta = theta[t] + i theta_im[t]
+ * (theta_im: device array of n doubles, (dt/2) Im V per site, or NULL): the
+ * complex64 record gamma = 1 - alpha, rounded once from FP64 where Im theta !=
+ * 0 (|alpha| != 1 there) and by the unit-modulus search elsewhere.  Per-site
+ * complex potentials are supported for complex64 lattices and batches.
+ */
+int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im, int64_t n, void *stream);
 
 /* Choose the step kernel and its tiling; 0 = library default for a knob.
  *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8

@@ -26,7 +26,8 @@ EXPORTS = (
     "dirac_set_mass_potential_z", "dirac_theta_from_fields", "dirac_set_theta_field", "dirac_set_kernel",
     "dirac_step", "dirac_step_norm", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
-    "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta",
+    "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
+    "dirac_coef_from_theta_c",
 )
 
 
@@ -77,6 +78,8 @@ def lib():
         "dirac_batch_norms": ([P, ctypes.POINTER(D), P], I),
         "dirac_batch_autotune": ([P, ctypes.c_char_p, ctypes.POINTER(I), P], I),
         "dirac_coef_from_theta": ([P, P, I64, P], I),
+        "dirac_coef_from_theta_c": ([P, P, P, I64, P], I),
+        "dirac_set_potential_im_z": ([P, P, P, I64], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -11,8 +11,9 @@ from .lattice import _dtype_code, _stream_handle
 
 
 class BatchedLattices:
-    """lattices: sequence of dicts with nx, ny, m, v_site (4 real arrays or None)
-    and state (4 complex arrays of shape (ny, nx)).  dt common, unit spacing."""
+    """lattices: sequence of dicts with nx, ny, m, v_site (4 real arrays or None),
+    optionally w_site (4 arrays: Im V, complex64 batches) and state (4 complex
+    arrays of shape (ny, nx)).  dt common, unit spacing."""
 
     def __init__(self, lattices, dtype=torch.complex64, dt=0.5, device="cuda"):
         self.device = torch.device(device)
@@ -43,11 +44,17 @@ class BatchedLattices:
                 # theta = (dt/2)(+-m + V) per site (u: +m, v: -m), Eqs. scheme2Deq-scheme4thline,
                 # in FP64; complex64 batches bind the per-site gamma record made from it
                 theta = (half * (sgn * m + v)).contiguous()
+                ws = L.get("w_site")
+                if ws is not None and dtype != torch.complex64:
+                    raise ValueError("per-site complex potentials are supported for complex64 batches")
                 if dtype == torch.complex64:
+                    thi = None if ws is None else \
+                        (half * torch.as_tensor(ws[a]).to(device=self.device, dtype=torch.float64)).contiguous()
                     coef = torch.empty(shp, dtype=torch.complex64, device=self.device)
-                    check(lib().dirac_coef_from_theta(ctypes.c_void_p(coef.data_ptr()),
-                                                      ctypes.c_void_p(theta.data_ptr()), theta.numel(),
-                                                      _stream_handle()))
+                    check(lib().dirac_coef_from_theta_c(ctypes.c_void_p(coef.data_ptr()),
+                                                        ctypes.c_void_p(theta.data_ptr()),
+                                                        ctypes.c_void_p(thi.data_ptr()) if thi is not None else None,
+                                                        theta.numel(), _stream_handle()))
                     th.append(coef)
                 else:
                     th.append(theta)

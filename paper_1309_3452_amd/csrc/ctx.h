@@ -28,6 +28,7 @@ struct dirac_ctx {
     // mass and V(z) profile, or per-site theta
     double m = 0.0;
     std::vector<double> v_int, v_half;
+    std::vector<double> w_int, w_half;    // Im V(z) (absorbing layers), empty if none
     bool tab_dirty = true;
     std::vector<double> tab_host64;
     std::vector<float> tab_host32;

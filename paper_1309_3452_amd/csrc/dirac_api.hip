@@ -113,6 +113,37 @@ void cayley32(double th, float out[4]) {
     out[3] = (float)(-th / d);
 }
 
+// Complex theta = th + i thi (a complex potential; Im V damps for Im V < 0):
+// with 1 + i theta = (1 - thi) + i th and 1 - i theta = (1 + thi) - i th,
+//   beta = ((1 - thi) - i th)/den,  alpha = ((1 - thi^2 - th^2) - 2 i th)/den,
+//   den = (1 - thi)^2 + th^2.
+void cayley64c(double th, double thi, double out[4]) {
+#pragma clang fp contract(off)
+    if (thi == 0.0) {
+        cayley64(th, out);
+        return;
+    }
+    const double den = (1.0 - thi) * (1.0 - thi) + th * th;
+    out[0] = (1.0 - thi * thi - th * th) / den;
+    out[1] = -((2.0 * th) / den);
+    out[2] = (1.0 - thi) / den;
+    out[3] = -(th / den);
+}
+// FP32 increment form for a complex theta: gamma = 1 - alpha and beta rounded
+// from FP64 (|alpha| != 1, so the unit-modulus search does not apply).
+void cayley32c(double th, double thi, float out[4]) {
+    if (thi == 0.0) {
+        cayley32(th, out);
+        return;
+    }
+    double c[4];
+    cayley64c(th, thi, c);
+    out[0] = (float)(1.0 - c[0]);
+    out[1] = (float)(-c[1]);
+    out[2] = (float)c[2];
+    out[3] = (float)c[3];
+}
+
 // theta of class q (A, B, C, D) at plane k: (dt/2)(+-m + V at the class's z).
 double theta_of(const dirac_ctx *c, int q, int64_t k) {
     double h = 0.5 * c->dt;
@@ -120,6 +151,11 @@ double theta_of(const dirac_ctx *c, int q, int64_t k) {
     if (!c->v_int.empty()) v = (q == 0 || q == 3) ? c->v_int[k] : c->v_half[k];
     double sgn = (q < 2) ? 1.0 : -1.0;
     return h * (sgn * c->m + v);
+}
+// Im theta of class q at plane k: (dt/2) Im V at the class's z (m is real).
+double theta_im_of(const dirac_ctx *c, int q, int64_t k) {
+    if (c->w_int.empty()) return 0.0;
+    return 0.5 * c->dt * ((q == 0 || q == 3) ? c->w_int[k] : c->w_half[k]);
 }
 
 template <typename R> size_t tab_bytes(const dirac_ctx *c) { return (size_t)4 * c->nz * 4 * sizeof(R); }
@@ -150,8 +186,9 @@ int upload_tables(dirac_ctx *c, hipStream_t s) {
         for (int dir = 0; dir < 2; ++dir)
             for (int q = 0; q < 4; ++q)
                 for (int64_t k = 0; k < nz; ++k) {
-                    double th = theta_of(c, q, k);
-                    cayley64(dir == 0 ? th : -th, &c->tab_host64[(((size_t)dir * 4 + q) * nz + k) * 4]);
+                    double th = theta_of(c, q, k), thi = theta_im_of(c, q, k);
+                    cayley64c(dir == 0 ? th : -th, dir == 0 ? thi : -thi,
+                              &c->tab_host64[(((size_t)dir * 4 + q) * nz + k) * 4]);
                 }
         size_t half = tab_bytes<double>(c);
         HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c)), c->tab_host64.data(), half, hipMemcpyHostToDevice, s));
@@ -162,8 +199,9 @@ int upload_tables(dirac_ctx *c, hipStream_t s) {
         for (int dir = 0; dir < 2; ++dir)
             for (int q = 0; q < 4; ++q)
                 for (int64_t k = 0; k < nz; ++k) {
-                    double th = theta_of(c, q, k);
-                    cayley32(dir == 0 ? th : -th, &c->tab_host32[(((size_t)dir * 4 + q) * nz + k) * 4]);
+                    double th = theta_of(c, q, k), thi = theta_im_of(c, q, k);
+                    cayley32c(dir == 0 ? th : -th, dir == 0 ? thi : -thi,
+                              &c->tab_host32[(((size_t)dir * 4 + q) * nz + k) * 4]);
                 }
         size_t half = tab_bytes<float>(c);
         HIPCHK(c, hipMemcpyAsync(scratch_at(c, off_tab(c)), c->tab_host32.data(), half, hipMemcpyHostToDevice, s));
@@ -398,6 +436,32 @@ int dirac_bind_scratch(dirac_ctx *c, void *dev, size_t bytes) {
     return DIRAC_OK;
 }
 
+int dirac_set_potential_im_z(dirac_ctx *c, const double *w_int, const double *w_half, int64_t nz) {
+    if (!c) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    if (nz != c->nz) return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice nz %lld", (long long)nz, (long long)c->nz);
+    if ((w_int == nullptr) != (w_half == nullptr)) return fail(c, DIRAC_E_ARG, "w_int and w_half: both or neither");
+    std::vector<double> wi, wh;
+    if (w_int) {
+        wi.assign(w_int, w_int + nz);
+        wh.assign(w_half, w_half + nz);
+        bool any = false;
+        for (int64_t k = 0; k < nz; ++k) {
+            if (!isfinite(wi[k]) || !isfinite(wh[k]))
+                return fail(c, DIRAC_E_NONFINITE, "non-finite Im V at k=%lld", (long long)k);
+            any = any || wi[k] != 0.0 || wh[k] != 0.0;
+        }
+        if (!any) {
+            wi.clear();
+            wh.clear();
+        }
+    }
+    c->w_int.swap(wi);
+    c->w_half.swap(wh);
+    c->tab_dirty = true;
+    return DIRAC_OK;
+}
+
 int dirac_set_mass_potential_z(dirac_ctx *c, double m, const double *v_int, const double *v_half, int64_t nz) {
     if (!c || !isfinite(m)) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
@@ -432,9 +496,15 @@ int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
 }
 
 int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream) {
+    return dirac_coef_from_theta_c(coef, theta, nullptr, n, stream);
+}
+
+int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im, int64_t n, void *stream) {
     if (!coef || !theta || n < 0) return DIRAC_E_ARG;
     if (n == 0) return DIRAC_OK;
-    if (launch_coef_from_theta(coef, (const double *)theta, n, (hipStream_t)stream) != hipSuccess) return DIRAC_E_HIP;
+    if (launch_coef_from_theta(coef, (const double *)theta, (const double *)theta_im, n, (hipStream_t)stream) !=
+        hipSuccess)
+        return DIRAC_E_HIP;
     return DIRAC_OK;
 }
 
@@ -632,6 +702,8 @@ int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int,
     if (rc) return rc;
     if (c->ndim != 3) return fail(c, DIRAC_E_STATE, "the V(z) gradient is defined for 3D lattices");
     if (c->site_mode) return fail(c, DIRAC_E_STATE, "needs a V(z) profile (dirac_set_mass_potential_z)");
+    if (!c->w_int.empty())
+        return fail(c, DIRAC_E_STATE, "the reversal-based adjoint needs a real potential (no absorbing layers)");
     if (n < 0 || !lam || !dLdV_int || !dLdV_half) return fail(c, DIRAC_E_ARG, "bad arguments");
     for (int q = 0; q < 8; ++q)
         if (!lam[q]) return fail(c, DIRAC_E_ARG, "null lam array %d", q);

@@ -78,7 +78,8 @@ template <typename R> hipError_t launch_obs3(const ReduceArgs<R> &a, hipStream_t
 template <typename R> hipError_t launch_seed3(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);
 template <typename R> hipError_t launch_theta_fields(void *const th[8], void *const v[8], int narr, int64_t ncell,
                                                      double half_dt, double m, hipStream_t s);
-hipError_t launch_coef_from_theta(void *coef, const double *theta, int64_t n, hipStream_t s);
+hipError_t launch_coef_from_theta(void *coef, const double *theta, const double *theta_im, int64_t n,
+                                  hipStream_t s);
 hipError_t launch_final_sum(const double *partial, int nblocks, int nv, double *out, hipStream_t s);
 
 // 2D split kernels (kernels2d.hip)

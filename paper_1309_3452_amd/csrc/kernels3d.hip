@@ -280,9 +280,20 @@ __global__ __launch_bounds__(256) void k_theta_fields(CPtr8 th, CPtr8 v, int nar
     }
 }
 
-__global__ __launch_bounds__(256) void k_coef_from_theta(float2 *coef, const double *theta, int64_t n) {
+// gamma = 1 - alpha for a complex theta = th + i thi (absorbing potential):
+// rounded once from FP64; real theta keeps the unit-modulus search.
+__device__ inline float2 gamma32_complex(double th, double thi) {
+#pragma clang fp contract(off)
+    if (thi == 0.0) return gamma32_search(th);
+    const double den = (1.0 - thi) * (1.0 - thi) + th * th;
+    const double ar = (1.0 - thi * thi - th * th) / den, ai = -((2.0 * th) / den);
+    return make_float2((float)(1.0 - ar), (float)(-ai));
+}
+
+__global__ __launch_bounds__(256) void k_coef_from_theta(float2 *coef, const double *theta, const double *theta_im,
+                                                         int64_t n) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        coef[t] = gamma32_search(theta[t]);
+        coef[t] = gamma32_complex(theta[t], theta_im ? theta_im[t] : 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_final_sum(const double *partial, int nblocks, int nv, double *out) {
@@ -352,8 +363,10 @@ hipError_t launch_theta_fields(void *const th[8], void *const v[8], int narr, in
     return hipGetLastError();
 }
 
-hipError_t launch_coef_from_theta(void *coef, const double *theta, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_coef_from_theta, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (float2 *)coef, theta, n);
+hipError_t launch_coef_from_theta(void *coef, const double *theta, const double *theta_im, int64_t n,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_coef_from_theta, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (float2 *)coef, theta,
+                       theta_im, n);
     return hipGetLastError();
 }
 

@@ -114,11 +114,46 @@ class Lattice:
                                                vh.ctypes.data_as(ctypes.c_void_p), self.nz), self._ctx)
         self._pin = (vi, vh)
 
-    def set_fields(self, m: float, v_site=None):
-        """Per-site potential: v_site[a] holds V at the sites of state array a.
-        The per-site coefficient records are theta (complex128 lattices) or
+    def set_absorber_z(self, w_int=None, w_half=None):
+        """Imaginary part W(z) of the potential (absorbing layers where W < 0),
+        sampled like V(z); None clears it (see dirac_set_potential_im_z)."""
+        if w_int is None:
+            check(lib().dirac_set_potential_im_z(self._ctx, None, None, self.nz), self._ctx)
+            return
+        import numpy as np
+        wi = np.ascontiguousarray(w_int, dtype=np.float64)
+        wh = np.ascontiguousarray(w_half, dtype=np.float64)
+        if wi.shape != (self.nz,) or wh.shape != (self.nz,):
+            raise ValueError("w_int and w_half need nz entries")
+        check(lib().dirac_set_potential_im_z(self._ctx, wi.ctypes.data_as(ctypes.c_void_p),
+                                             wh.ctypes.data_as(ctypes.c_void_p), self.nz), self._ctx)
+        self._pin_w = (wi, wh)
+
+    def set_fields(self, m: float, v_site=None, w_site=None):
+        """Per-site potential: v_site[a] holds V at the sites of state array a,
+        w_site[a] (optional, complex64 lattices) its imaginary part.  The
+        per-site coefficient records are theta (complex128 lattices) or
         gamma = 1 - alpha (complex64 lattices), see dirac_theta_from_fields."""
         cdt = torch.complex64 if self.dtype == torch.complex64 else torch.float64
+        if w_site is not None:
+            if self.dtype != torch.complex64:
+                raise ValueError("per-site complex potentials are supported for complex64 lattices")
+            # theta = (dt/2)(+-m + V) + i (dt/2) W in FP64, then the library's records
+            half = 0.5 * self.dt
+            self.theta = []
+            for a in range(self.narr):
+                sgn = 1.0 if a < self.narr // 2 else -1.0
+                v = torch.zeros(self.tshape, dtype=torch.float64, device=self.device) if v_site is None else \
+                    torch.as_tensor(v_site[a]).to(device=self.device, dtype=torch.float64)
+                w = torch.as_tensor(w_site[a]).to(device=self.device, dtype=torch.float64)
+                th = (half * (sgn * float(m) + v)).contiguous()
+                thi = (half * w).contiguous()
+                rec = torch.empty(self.tshape, dtype=torch.complex64, device=self.device)
+                check(lib().dirac_coef_from_theta_c(ctypes.c_void_p(rec.data_ptr()), ctypes.c_void_p(th.data_ptr()),
+                                                    ctypes.c_void_p(thi.data_ptr()), th.numel(), _stream_handle()))
+                self.theta.append(rec)
+            check(lib().dirac_set_theta_field(self._ctx, ptr_array([t.data_ptr() for t in self.theta])), self._ctx)
+            return
         self.theta = [torch.empty(self.tshape, dtype=cdt, device=self.device) for _ in range(self.narr)]
         vs = None
         if v_site is not None:

@@ -76,6 +76,19 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_set_kernel(c, 3, 0, 0) == 0
     assert L.dirac_set_kernel(c, 2, 5, 0) == -1
     assert L.dirac_set_mass_potential_z(c, 0.5, None, None, 7) == -2   # nz mismatch
+    # imaginary potential: validated before any HIP call
+    nz = 4
+    c3 = ctypes.c_void_p()
+    assert L.dirac_create(ctypes.byref(c3), 3, 4, 4, nz, 2, 0.5, 1.0, 1.0, 1.0, 0) == 0
+    w = (ctypes.c_double * nz)(-0.1, 0.0, 0.0, -0.1)
+    bad = (ctypes.c_double * nz)(-0.1, float("nan"), 0.0, 0.0)
+    assert L.dirac_set_potential_im_z(c3, w, w, nz + 1) == -2
+    assert L.dirac_set_potential_im_z(c3, w, None, nz) == -1
+    assert L.dirac_set_potential_im_z(c3, bad, w, nz) == -4
+    assert L.dirac_set_potential_im_z(c3, w, w, nz) == 0
+    assert L.dirac_set_potential_im_z(c3, None, None, nz) == 0
+    assert L.dirac_coef_from_theta_c(None, None, None, 1, None) == -1
+    L.dirac_destroy(c3)
     L.dirac_destroy(c)
     L.dirac_destroy(None)
 

@@ -472,3 +472,112 @@ def test_batched_candidates_vs_oracle(P, cand, mode, tmp_path):
         f = [a.copy() for a in L["state"]]
         ol.step(f, th, steps)
         assert rel_l2(np_state(B.state(b)), f) <= 1e-13, b
+
+
+# --------------------------------------------------------------------------
+# Complex potential: absorbing layers (Im V < 0 damps in the Cayley form).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 30e-6)])
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
+def test_3d_absorbing_layers_vs_oracle(P, kernel, dtype, tol):
+    nx, ny, nz = 70, 20, 22
+    print("3d absorber %s %s" % (kernel, dtype), flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    w_int, w_half = workloads.absorber(nz, 5.0, 0.8)
+    f0 = rand_state((nz, ny, nx), 8, 131)
+    lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+    lat.set_kernel(kernel)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.set_absorber_z(w_int, w_half)
+    lat.load(f0)
+    f0 = np_state(lat.state())
+    e0 = lat.norm()[0]
+    lat.step(30)
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    th = ol.theta_vz(0.5, v_int, v_half)
+    zs = [w_int, w_int, w_half, w_half, w_half, w_half, w_int, w_int]    # A,A,B,B,C,C,D,D
+    thi = [np.ascontiguousarray(np.broadcast_to((0.5 * DT3 * zs[a])[:, None, None], (nz, ny, nx)))
+           for a in range(8)]
+    f = [a.copy() for a in f0]
+    ol.step(f, th, 30, thi=thi)
+    assert rel_l2(np_state(lat.state()), f) <= tol
+    e1 = lat.norm()[0]
+    assert e1 < e0 and abs(e1 - ol.energy(f)[0]) <= (1e-12 if dtype == torch.complex128 else 1e-5) * abs(e0)
+    if dtype == torch.complex128:
+        with pytest.raises(P.DiracError):
+            lat.adjoint_vz(1, lat.seed_region(nz / 2.0))
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
+def test_2d_absorbing_frame_fp32_vs_oracle(P, kernel):
+    nx, ny = 96, 80
+    print("2d absorbing frame %s" % kernel, flush=True)
+    g = np.random.default_rng(141)
+    f0 = rand_state((ny, nx), 4, 142)
+    V = [np.ascontiguousarray(0.3 * g.standard_normal((ny, nx))).astype(np.float32) for _ in range(4)]
+    wx = workloads.absorber(nx, 8.0, 0.6, offsets=(0.0, 0.5))
+    wy = workloads.absorber(ny, 8.0, 0.6, offsets=(0.0, 0.5))
+    offs = oracle.OFFSETS2
+    W = [np.ascontiguousarray(wy[1 if offs[a][1] else 0][:, None] + wx[1 if offs[a][0] else 0][None, :])
+         for a in range(4)]
+    lat = P.Lattice2D(nx, ny, dtype=torch.complex64, dt=DT2)
+    lat.set_kernel(kernel)
+    lat.load(f0)
+    f0_32 = np_state(lat.state())
+    lat.set_fields(0.4, [torch.from_numpy(v) for v in V], [torch.from_numpy(w) for w in W])
+    e0 = lat.norm()[0]
+    lat.step(40)
+    ol = oracle.Lattice2(nx, ny, DT2)
+    th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * 0.4 + V[a].astype(np.float64)))
+          for a in range(4)]
+    thi = [np.ascontiguousarray(0.5 * DT2 * W[a]) for a in range(4)]
+    f = [a.copy() for a in f0_32]
+    ol.step(f, th, 40, thi=thi)
+    assert rel_l2(np_state(lat.state()), f) <= 40e-6
+    assert lat.norm()[0] < e0
+
+
+def test_batched_absorbing_fp32_vs_oracle(P):
+    sizes = [(64, 64), (96, 130), (32, 250)]
+    g = np.random.default_rng(151)
+    lats = []
+    for (nx, ny) in sizes:
+        wy = workloads.absorber(ny, 6.0, 0.5)
+        W = [np.ascontiguousarray(np.broadcast_to(wy[1 if oracle.OFFSETS2[a][1] else 0][:, None], (ny, nx)))
+             for a in range(4)]
+        lats.append(dict(nx=nx, ny=ny, m=float(g.uniform(0, 1)),
+                         v_site=[np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))).astype(np.float32)
+                                 for _ in range(4)], w_site=W,
+                         state=rand_state((ny, nx), 4, int(g.integers(1 << 30)))))
+    B = P.BatchedLattices(lats, dtype=torch.complex64, dt=DT2)
+    f32 = [np_state(B.state(b)) for b in range(len(lats))]
+    steps = 30
+    B.run(steps, mode=1, graph=False)
+    for b, L in enumerate(lats):
+        ol = oracle.Lattice2(L["nx"], L["ny"], DT2)
+        th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * L["m"] + L["v_site"][a].astype(np.float64)))
+              for a in range(4)]
+        thi = [np.ascontiguousarray(0.5 * DT2 * L["w_site"][a]) for a in range(4)]
+        f = [a.copy() for a in f32[b]]
+        ol.step(f, th, steps, thi=thi)
+        assert rel_l2(np_state(B.state(b)), f) <= steps * 1e-6, b
+
+
+def test_absorbing_dissipation_identity_gpu(P):
+    """E_r(n+1) - E_r(n) = sum Im(theta)|X+ + X-|^2 on the GPU states (FP64)."""
+    nx, ny, nz = 40, 12, 24
+    v_int, v_half = workloads.step_potential(nz, 1.0, nz / 2.0, 2.0)
+    w_int, w_half = workloads.absorber(nz, 6.0, 1.0)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.set_absorber_z(w_int, w_half)
+    lat.load(rand_state((nz, ny, nx), 8, 161))
+    zs = [w_int, w_int, w_half, w_half, w_half, w_half, w_int, w_int]
+    for _ in range(3):
+        pre = np_state(lat.state())
+        e0 = lat.norm()[0]
+        lat.step(1)
+        post = np_state(lat.state())
+        e1 = lat.norm()[0]
+        rhs = sum(float(np.sum((0.5 * DT3 * zs[a])[:, None, None] * np.abs(post[a] + pre[a]) ** 2)) for a in range(8))
+        assert abs((e1 - e0) - rhs) <= 1e-12 * abs(e0)

@@ -109,6 +109,20 @@ def step_potential(nz, V0=1.5, zc=None, w=4.0):
     return f(k), f(k + 0.5)
 
 
+def absorber(n, width, w0, offsets=(0.0, 0.5)):
+    """Imaginary potential of absorbing layers at both ends of a periodic axis
+    of n cells: W = -w0 ((width - d)/width)^2 within `width` cells of the
+    boundary, d the distance to it, 0 elsewhere; sampled at each offset
+    (returns one float64 array of length n per offset)."""
+    out = []
+    for o in offsets:
+        z = np.arange(n, dtype=np.float64) + o
+        d = np.minimum(z, n - z)                  # distance to the periodic boundary
+        w = np.where(d < width, -w0 * ((width - d) / width) ** 2, 0.0)
+        out.append(w)
+    return out
+
+
 def hat_basis(nz, nodes=32):
     """Periodic piecewise-linear hats h_i(z) on nodes z_i = i nz/nodes: returns
     (H_int, H_half) of shape (nz, nodes) sampled at z = k and k + 1/2."""
