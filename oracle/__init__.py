@@ -54,7 +54,8 @@ def lib():
         P = ctypes.c_void_p
         for name in ("oracle_step3", "oracle_reverse3", "oracle_step2", "oracle_reverse2"):
             getattr(L, name).argtypes = [P, P, P, P]
-        for name in ("oracle_step3c", "oracle_step2c"):
+        for name in ("oracle_step3c", "oracle_step2c", "oracle_step3_links", "oracle_step2_links",
+                     "oracle_energy3_links", "oracle_energy2_links"):
             getattr(L, name).argtypes = [P, P, P, P, P]
         for name in ("oracle_energy3", "oracle_energy2"):
             getattr(L, name).argtypes = [P, P, P, P]
@@ -126,9 +127,17 @@ class Lattice3:
         return [np.ascontiguousarray(0.5 * self.dt * ((1.0 if a < 4 else -1.0) * m + zsheet[a]))
                 for a in range(8)]
 
-    def step(self, f, th, n=1, thi=None):
-        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential)."""
+    def step(self, f, th, n=1, thi=None, links=None):
+        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential);
+        links (optional): 24 complex arrays U[6 a + t] of gauge factors (vector potential)."""
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
+        if links is not None:
+            if thi is not None:
+                raise ValueError("links with a complex theta are not combined here")
+            u = _ptrs(links, np.complex128)
+            for _ in range(n):
+                _check(lib().oracle_step3_links(self.n, self.r, p, t, u), "oracle_step3_links")
+            return
         if thi is not None:
             ti = _ptrs(thi, np.float64)
             for _ in range(n):
@@ -136,6 +145,13 @@ class Lattice3:
             return
         for _ in range(n):
             _check(lib().oracle_step3(self.n, self.r, p, t), "oracle_step3")
+
+    def energy_links(self, f, links):
+        """E_r with gauge links (see oracle_energy3_links)."""
+        out = (ctypes.c_double * 3)()
+        _check(lib().oracle_energy3_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
+                                          out), "oracle_energy3_links")
+        return tuple(out)
 
     def reverse(self, f, th, n=1):
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
@@ -189,9 +205,17 @@ class Lattice2:
             th.append(np.ascontiguousarray(0.5 * self.dt * (sgn * mv + vv), dtype=np.float64))
         return th
 
-    def step(self, f, th, n=1, thi=None):
-        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential)."""
+    def step(self, f, th, n=1, thi=None, links=None):
+        """n steps; thi (optional): Im theta per site, (dt/2) Im V (complex potential);
+        links (optional): 8 complex arrays U[4 a + t] of gauge factors (vector potential)."""
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
+        if links is not None:
+            if thi is not None:
+                raise ValueError("links with a complex theta are not combined here")
+            u = _ptrs(links, np.complex128)
+            for _ in range(n):
+                _check(lib().oracle_step2_links(self.n, self.r, p, t, u), "oracle_step2_links")
+            return
         if thi is not None:
             ti = _ptrs(thi, np.float64)
             for _ in range(n):
@@ -199,6 +223,13 @@ class Lattice2:
             return
         for _ in range(n):
             _check(lib().oracle_step2(self.n, self.r, p, t), "oracle_step2")
+
+    def energy_links(self, f, links):
+        """E_r with gauge links (see oracle_energy2_links)."""
+        out = (ctypes.c_double * 3)()
+        _check(lib().oracle_energy2_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
+                                          out), "oracle_energy2_links")
+        return tuple(out)
 
     def reverse(self, f, th, n=1):
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)

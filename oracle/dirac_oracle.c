@@ -144,6 +144,64 @@ static cplx stencil3(const lat3 *L, int comp, int64_t X, int64_t Y, int64_t Z, c
     return s;
 }
 
+/*
+ * Gauge links (a vector potential by the Peierls substitution of Sect. 4).  A
+ * unit factor per half-link: in term t of S_X at an A,B site X (term order of
+ * ST3: +z -z +x -x +y -y) the neighbour value is multiplied by U[6 a + t] at
+ * X's cell, a the array of X.  At a C,D site Y the same half-link enters
+ * conjugated: Y's neighbour X contributes with conj of X's factor for Y.  With
+ * U = exp(-i q/(hbar c) times the line integral of A from X to Y) this is the
+ * Peierls substitution, and to first order in A it is the rule of Sect. 4,
+ * d_j psi -> d_j psi - i (q/(hbar c)) A_j times the mean of the two values.
+ * The coupling stays anti-Hermitian, so E_r (with the same factors in S_X)
+ * is conserved for a static potential.
+ */
+static int locate3(const lat3 *L, int comp, int64_t X, int64_t Y, int64_t Z, int64_t *cell) {
+    X = wrap(X, 2 * L->nx);
+    Y = wrap(Y, 2 * L->ny);
+    Z = wrap(Z, 2 * L->nz);
+    for (int s = 0; s < 2; ++s) {
+        int a = 2 * comp + s;
+        if ((X & 1) == OFF3[a][0] && (Y & 1) == OFF3[a][1] && (Z & 1) == OFF3[a][2]) {
+            *cell = ((Z >> 1) * L->ny + (Y >> 1)) * L->nx + (X >> 1);
+            return a;
+        }
+    }
+    g_bad_lookup = 1;
+    *cell = 0;
+    return 0;
+}
+
+static cplx stencil3_links(const lat3 *L, int comp, int64_t X, int64_t Y, int64_t Z, const double r[3],
+                           const cplx *const U[24]) {
+    cplx s = 0.0;
+    int64_t cx;
+    int ax = locate3(L, comp, X, Y, Z, &cx);
+    for (int t = 0; t < 6; ++t) {
+        const term *q = &ST3[comp][t];
+        int64_t QX = X + q->dx, QY = Y + q->dy, QZ = Z + q->dz;
+        cplx u;
+        if (comp == CA || comp == CB) {
+            u = U[6 * ax + t][cx];
+        } else {
+            int64_t cq;
+            int aq = locate3(L, q->comp, QX, QY, QZ, &cq);
+            int tb = -1;                        /* the term of S at Q that points back to X */
+            for (int t2 = 0; t2 < 6; ++t2) {
+                const term *b = &ST3[q->comp][t2];
+                if (b->dx == -q->dx && b->dy == -q->dy && b->dz == -q->dz) tb = t2;
+            }
+            if (tb < 0) {
+                g_bad_lookup = 1;
+                tb = 0;
+            }
+            u = conj(U[6 * aq + tb][cq]);
+        }
+        s += coef(q->cls, r) * u * get3(L, q->comp, QX, QY, QZ);
+    }
+    return s;
+}
+
 /* Cayley factors of the time average, from (1 + i th) X+ = (1 - i th) X- - S. */
 static void cayley(double th, cplx *alpha, cplx *beta) {
     double d = 1.0 + th * th;
@@ -177,7 +235,7 @@ static void cayley_c(double th, double thi, cplx *alpha, cplx *beta) {
  * components, so the update is done in place.
  */
 static void half3(const lat3 *L, int a_lo, const double r[3], const double *const th[8],
-                  const double *const thi[8], double tsgn, double sgn) {
+                  const double *const thi[8], double tsgn, double sgn, const cplx *const *U) {
     for (int a = a_lo; a < a_lo + 4; ++a) {
         int comp = a / 2;
 #pragma omp parallel for schedule(static)
@@ -188,7 +246,8 @@ static void half3(const lat3 *L, int a_lo, const double r[3], const double *cons
                     cplx al, be;
                     if (thi) cayley_c(tsgn * th[a][c], tsgn * thi[a][c], &al, &be);
                     else cayley(tsgn * th[a][c], &al, &be);
-                    cplx s = stencil3(L, comp, POS3(a, i, j, k), r);
+                    cplx s = U ? stencil3_links(L, comp, POS3(a, i, j, k), r, U)
+                               : stencil3(L, comp, POS3(a, i, j, k), r);
                     L->f[a][c] = al * L->f[a][c] - sgn * be * s;
                 }
     }
@@ -211,8 +270,8 @@ int oracle_step3(const int64_t n[3], const double r[3], void *const f[8], const 
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half3(&L, 0, r, th, NULL, 1.0, 1.0);
-    half3(&L, 4, r, th, NULL, 1.0, 1.0);
+    half3(&L, 0, r, th, NULL, 1.0, 1.0, NULL);
+    half3(&L, 4, r, th, NULL, 1.0, 1.0, NULL);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -223,8 +282,8 @@ int oracle_step3c(const int64_t n[3], const double r[3], void *const f[8], const
     lat3 L;
     if (mk3(&L, n, f) || !thi) return -1;
     g_bad_lookup = 0;
-    half3(&L, 0, r, th, thi, 1.0, 1.0);
-    half3(&L, 4, r, th, thi, 1.0, 1.0);
+    half3(&L, 0, r, th, thi, 1.0, 1.0, NULL);
+    half3(&L, 4, r, th, thi, 1.0, 1.0, NULL);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -234,8 +293,21 @@ int oracle_reverse3(const int64_t n[3], const double r[3], void *const f[8], con
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half3(&L, 4, r, th, NULL, -1.0, -1.0);
-    half3(&L, 0, r, th, NULL, -1.0, -1.0);
+    half3(&L, 4, r, th, NULL, -1.0, -1.0, NULL);
+    half3(&L, 0, r, th, NULL, -1.0, -1.0, NULL);
+    return g_bad_lookup ? -2 : 0;
+}
+
+/* One forward step with gauge links U[24] (see stencil3_links). */
+int oracle_step3_links(const int64_t n[3], const double r[3], void *const f[8], const double *const th[8],
+                       void *const U[24]) {
+    lat3 L;
+    if (mk3(&L, n, f)) return -1;
+    for (int q = 0; q < 24; ++q)
+        if (!U[q]) return -1;
+    g_bad_lookup = 0;
+    half3(&L, 0, r, th, NULL, 1.0, 1.0, (const cplx *const *)U);
+    half3(&L, 4, r, th, NULL, 1.0, 1.0, (const cplx *const *)U);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -303,6 +375,53 @@ int oracle_energy3(const int64_t n[3], const double r[3], void *const f[8], doub
                         cplx sx = stencil3(&L, comp, POS3(b, i, j, k), r);
                         kadd(&e2, creal(conj(x) * sx));
                     }
+                }
+            }
+        pl[3 * k + 0] = e1.s;
+        pl[3 * k + 1] = e2.s;
+        pl[3 * k + 2] = nv.s;
+    }
+    ksum t1 = {0, 0}, t2 = {0, 0}, t3 = {0, 0};
+    for (int64_t k = 0; k < nz; ++k) {
+        kadd(&t1, pl[3 * k]);
+        kadd(&t2, pl[3 * k + 1]);
+        kadd(&t3, pl[3 * k + 2]);
+    }
+    free(pl);
+    out[0] = t3.s + t1.s;
+    out[1] = t3.s + t2.s;
+    out[2] = t3.s;
+    return g_bad_lookup ? -2 : 0;
+}
+
+/*
+ * E_r with gauge links: out[0] = sum |psi|^2 - Re sum_{A,B} conj(X) S_X(C,D),
+ * out[1] = sum |psi|^2 + Re sum_{C,D} conj(Y) S_Y(A,B) (S with the links),
+ * out[2] = sum |psi|^2.
+ */
+int oracle_energy3_links(const int64_t n[3], const double r[3], void *const f[8], void *const U[24],
+                         double out[3]) {
+    lat3 L;
+    if (mk3(&L, n, f)) return -1;
+    for (int q = 0; q < 24; ++q)
+        if (!U[q]) return -1;
+    const cplx *const *u = (const cplx *const *)U;
+    g_bad_lookup = 0;
+    int64_t nz = L.nz;
+    double *pl = (double *)calloc((size_t)(3 * nz), sizeof(double));
+    if (!pl) return -3;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k) {
+        ksum e1 = {0, 0}, e2 = {0, 0}, nv = {0, 0};
+        for (int64_t j = 0; j < L.ny; ++j)
+            for (int64_t i = 0; i < L.nx; ++i) {
+                int64_t c = (k * L.ny + j) * L.nx + i;
+                for (int a = 0; a < 8; ++a) {
+                    double m2 = creal(L.f[a][c]) * creal(L.f[a][c]) + cimag(L.f[a][c]) * cimag(L.f[a][c]);
+                    kadd(&nv, m2);
+                    cplx sx = stencil3_links(&L, a / 2, POS3(a, i, j, k), r, u);
+                    if (a < 4) kadd(&e1, -creal(conj(L.f[a][c]) * sx));
+                    else kadd(&e2, creal(conj(L.f[a][c]) * sx));
                 }
             }
         pl[3 * k + 0] = e1.s;
@@ -472,8 +591,55 @@ static cplx stencil2(const lat2 *L, int comp, int64_t X, int64_t Y, const double
     return s;
 }
 
+/* Gauge links in 2D: as stencil3_links with U[4 a + t] at the u sites (term
+ * order of ST2: +x -x +y -y) and the conjugates at the v sites. */
+static int locate2(const lat2 *L, int comp, int64_t X, int64_t Y, int64_t *cell) {
+    X = wrap(X, 2 * L->nx);
+    Y = wrap(Y, 2 * L->ny);
+    for (int s = 0; s < 2; ++s) {
+        int a = 2 * comp + s;
+        if ((X & 1) == OFF2[a][0] && (Y & 1) == OFF2[a][1]) {
+            *cell = (Y >> 1) * L->nx + (X >> 1);
+            return a;
+        }
+    }
+    g_bad_lookup = 1;
+    *cell = 0;
+    return 0;
+}
+
+static cplx stencil2_links(const lat2 *L, int comp, int64_t X, int64_t Y, const double r[3],
+                           const cplx *const U[8]) {
+    cplx s = 0.0;
+    int64_t cx;
+    int ax = locate2(L, comp, X, Y, &cx);
+    for (int t = 0; t < 4; ++t) {
+        const term *q = &ST2[comp][t];
+        int64_t QX = X + q->dx, QY = Y + q->dy;
+        cplx u;
+        if (comp == CU) {
+            u = U[4 * ax + t][cx];
+        } else {
+            int64_t cq;
+            int aq = locate2(L, q->comp, QX, QY, &cq);
+            int tb = -1;
+            for (int t2 = 0; t2 < 4; ++t2) {
+                const term *b = &ST2[q->comp][t2];
+                if (b->dx == -q->dx && b->dy == -q->dy) tb = t2;
+            }
+            if (tb < 0) {
+                g_bad_lookup = 1;
+                tb = 0;
+            }
+            u = conj(U[4 * aq + tb][cq]);
+        }
+        s += coef(q->cls, r) * u * get2(L, q->comp, QX, QY);
+    }
+    return s;
+}
+
 static void half2(const lat2 *L, int a_lo, const double r[3], const double *const th[4],
-                  const double *const thi[4], double tsgn, double sgn) {
+                  const double *const thi[4], double tsgn, double sgn, const cplx *const *U) {
     for (int a = a_lo; a < a_lo + 2; ++a) {
         int comp = a / 2;
 #pragma omp parallel for schedule(static)
@@ -483,7 +649,8 @@ static void half2(const lat2 *L, int a_lo, const double r[3], const double *cons
                 cplx al, be;
                 if (thi) cayley_c(tsgn * th[a][c], tsgn * thi[a][c], &al, &be);
                 else cayley(tsgn * th[a][c], &al, &be);
-                cplx s = stencil2(L, comp, 2 * i + OFF2[a][0], 2 * j + OFF2[a][1], r);
+                cplx s = U ? stencil2_links(L, comp, 2 * i + OFF2[a][0], 2 * j + OFF2[a][1], r, U)
+                           : stencil2(L, comp, 2 * i + OFF2[a][0], 2 * j + OFF2[a][1], r);
                 L->f[a][c] = al * L->f[a][c] - sgn * be * s;
             }
     }
@@ -505,8 +672,8 @@ int oracle_step2(const int64_t n[2], const double r[3], void *const f[4], const 
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half2(&L, 0, r, th, NULL, 1.0, 1.0);
-    half2(&L, 2, r, th, NULL, 1.0, 1.0);
+    half2(&L, 0, r, th, NULL, 1.0, 1.0, NULL);
+    half2(&L, 2, r, th, NULL, 1.0, 1.0, NULL);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -516,8 +683,8 @@ int oracle_step2c(const int64_t n[2], const double r[3], void *const f[4], const
     lat2 L;
     if (mk2(&L, n, f) || !thi) return -1;
     g_bad_lookup = 0;
-    half2(&L, 0, r, th, thi, 1.0, 1.0);
-    half2(&L, 2, r, th, thi, 1.0, 1.0);
+    half2(&L, 0, r, th, thi, 1.0, 1.0, NULL);
+    half2(&L, 2, r, th, thi, 1.0, 1.0, NULL);
     return g_bad_lookup ? -2 : 0;
 }
 
@@ -525,8 +692,48 @@ int oracle_reverse2(const int64_t n[2], const double r[3], void *const f[4], con
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     g_bad_lookup = 0;
-    half2(&L, 2, r, th, NULL, -1.0, -1.0);
-    half2(&L, 0, r, th, NULL, -1.0, -1.0);
+    half2(&L, 2, r, th, NULL, -1.0, -1.0, NULL);
+    half2(&L, 0, r, th, NULL, -1.0, -1.0, NULL);
+    return g_bad_lookup ? -2 : 0;
+}
+
+/* One forward (2+1)D step with gauge links U[8] (see stencil2_links). */
+int oracle_step2_links(const int64_t n[2], const double r[3], void *const f[4], const double *const th[4],
+                       void *const U[8]) {
+    lat2 L;
+    if (mk2(&L, n, f)) return -1;
+    for (int q = 0; q < 8; ++q)
+        if (!U[q]) return -1;
+    g_bad_lookup = 0;
+    half2(&L, 0, r, th, NULL, 1.0, 1.0, (const cplx *const *)U);
+    half2(&L, 2, r, th, NULL, 1.0, 1.0, (const cplx *const *)U);
+    return g_bad_lookup ? -2 : 0;
+}
+
+/* (2+1)D functional with links (d_+ form): out[0] = sum |psi|^2 + Re sum_v conj(v) S_v(u),
+ * out[1] = sum |psi|^2 - Re sum_u conj(u) S_u(v), out[2] = sum |psi|^2. */
+int oracle_energy2_links(const int64_t n[2], const double r[3], void *const f[4], void *const U[8],
+                         double out[3]) {
+    lat2 L;
+    if (mk2(&L, n, f)) return -1;
+    for (int q = 0; q < 8; ++q)
+        if (!U[q]) return -1;
+    const cplx *const *u = (const cplx *const *)U;
+    g_bad_lookup = 0;
+    ksum ev = {0, 0}, eu = {0, 0}, nv = {0, 0};
+    for (int64_t j = 0; j < L.ny; ++j)
+        for (int64_t i = 0; i < L.nx; ++i) {
+            int64_t c = j * L.nx + i;
+            for (int a = 0; a < 4; ++a) {
+                kadd(&nv, creal(L.f[a][c]) * creal(L.f[a][c]) + cimag(L.f[a][c]) * cimag(L.f[a][c]));
+                cplx sx = stencil2_links(&L, a / 2, 2 * i + OFF2[a][0], 2 * j + OFF2[a][1], r, u);
+                if (a < 2) kadd(&eu, -creal(conj(L.f[a][c]) * sx));
+                else kadd(&ev, creal(conj(L.f[a][c]) * sx));
+            }
+        }
+    out[0] = nv.s + ev.s;
+    out[1] = nv.s + eu.s;
+    out[2] = nv.s;
     return g_bad_lookup ? -2 : 0;
 }
 

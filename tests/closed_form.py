@@ -104,3 +104,126 @@ def rel_l2(a_list, b_list):
     num = sum(float(np.sum(np.abs(np.asarray(a) - np.asarray(b)) ** 2)) for a, b in zip(a_list, b_list))
     den = sum(float(np.sum(np.abs(np.asarray(b)) ** 2)) for b in b_list)
     return np.sqrt(num / den)
+
+
+# --------------------------------------------------------------------------
+# Gauge links (vector potential): construction of link arrays from site data.
+# --------------------------------------------------------------------------
+#: neighbour displacements (cell units) of the link terms, in order
+LINK_DIRS3 = [(0, 0, 0.5), (0, 0, -0.5), (0.5, 0, 0), (-0.5, 0, 0), (0, 0.5, 0), (0, -0.5, 0)]
+LINK_DIRS2 = [(0.5, 0), (-0.5, 0), (0, 0.5), (0, -0.5)]
+
+
+def _site3(shape, pos):
+    """(array, k, j, i) of the 3D site at physical position pos (cell units)."""
+    nz, ny, nx = shape
+    x, y, z = pos
+    fr = (x % 1.0, y % 1.0, z % 1.0)
+    for a, o in enumerate(OFF3):
+        if all(abs(f - oo) < 1e-9 for f, oo in zip(fr, o)):
+            return a, int(np.floor(z)) % nz, int(np.floor(y)) % ny, int(np.floor(x)) % nx
+    raise ValueError("not a site")
+
+
+def _site2(shape, pos):
+    ny, nx = shape
+    x, y = pos
+    fr = (x % 1.0, y % 1.0)
+    for a, o in enumerate(OFF2):
+        if all(abs(f - oo) < 1e-9 for f, oo in zip(fr, o)):
+            return a, int(np.floor(y)) % ny, int(np.floor(x)) % nx
+    raise ValueError("not a site")
+
+
+def links_from_site_phase3(shape, chi):
+    """Pure-gauge links U[6 a + t] = exp(i (chi(Y) - chi(X))) for the A,B site X
+    of array a and its term-t neighbour Y; chi: 8 real arrays (one per array)."""
+    nz, ny, nx = shape
+    out = []
+    for a in range(4):
+        for d in LINK_DIRS3:
+            U = np.empty(shape, np.complex128)
+            for k in range(nz):
+                for j in range(ny):
+                    for i in range(nx):
+                        pos = (i + OFF3[a][0] + d[0], j + OFF3[a][1] + d[1], k + OFF3[a][2] + d[2])
+                        b, kk, jj, ii = _site3(shape, pos)
+                        U[k, j, i] = np.exp(1j * (chi[b][kk, jj, ii] - chi[a][k, j, i]))
+            out.append(U)
+    return out
+
+
+def links_from_site_phase2(shape, chi):
+    ny, nx = shape
+    out = []
+    for a in range(2):
+        for d in LINK_DIRS2:
+            U = np.empty(shape, np.complex128)
+            for j in range(ny):
+                for i in range(nx):
+                    pos = (i + OFF2[a][0] + d[0], j + OFF2[a][1] + d[1])
+                    b, jj, ii = _site2(shape, pos)
+                    U[j, i] = np.exp(1j * (chi[b][jj, ii] - chi[a][j, i]))
+            out.append(U)
+    return out
+
+
+def links_uniform_field2(shape, flux):
+    """Links of a static, non-pure-gauge field in 2D: every half-link along x at
+    height y (cell units) carries the phase exp(-i flux y dx) (a Landau-gauge
+    vector potential A_x = -B y; dx = +-1/2 the link's signed length), y links
+    carry 1.  The phase around a cell is not 1: no gauge transformation removes
+    it."""
+    ny, nx = shape
+    out = []
+    for a in range(2):
+        for d in LINK_DIRS2:
+            jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+            y = jj + OFF2[a][1] + 0.5 * d[1]
+            out.append(np.ascontiguousarray(np.exp(-1j * flux * y * d[0]) * np.ones(shape)))
+    return out
+
+
+def links_from_potential3(shape, a_fn):
+    """Peierls links of a vector potential: U(X -> Y) = exp(-i a_j(M) d_j) with
+    a = q A/(hbar c) (per cell length) evaluated at the half-link midpoint M and
+    d = Y - X = +-1/2 along axis j (midpoint rule for the line integral).
+    a_fn(x, y, z) -> (ax, ay, az) on arrays of physical coordinates."""
+    nz, ny, nx = shape
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for a in range(4):
+        for d in LINK_DIRS3:
+            mx = ii + OFF3[a][0] + 0.5 * d[0]
+            my = jj + OFF3[a][1] + 0.5 * d[1]
+            mz = kk + OFF3[a][2] + 0.5 * d[2]
+            ax, ay, az = a_fn(mx, my, mz)
+            out.append(np.ascontiguousarray(np.exp(-1j * (ax * d[0] + ay * d[1] + az * d[2]))))
+    return out
+
+
+def links_from_potential2(shape, a_fn):
+    """2D version of links_from_potential3; a_fn(x, y) -> (ax, ay)."""
+    ny, nx = shape
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for a in range(2):
+        for d in LINK_DIRS2:
+            mx = ii + OFF2[a][0] + 0.5 * d[0]
+            my = jj + OFF2[a][1] + 0.5 * d[1]
+            ax, ay = a_fn(mx, my)
+            out.append(np.ascontiguousarray(np.exp(-1j * (ax * d[0] + ay * d[1]))))
+    return out
+
+
+def smooth_potential3(shape, amp, seed):
+    """A smooth periodic vector potential with nonzero curl: a few low Fourier
+    modes per component with random phases."""
+    nz, ny, nx = shape
+    g = np.random.default_rng(seed)
+    ph = g.uniform(0, 2 * np.pi, (3, 3))
+    def fn(x, y, z):
+        return (amp * np.sin(2 * np.pi * y / ny + ph[0, 0]) * np.cos(2 * np.pi * z / nz + ph[0, 1]),
+                amp * np.sin(2 * np.pi * z / nz + ph[1, 0]) * np.cos(2 * np.pi * x / nx + ph[1, 1]),
+                amp * np.sin(2 * np.pi * x / nx + ph[2, 0]) * np.cos(2 * np.pi * y / ny + ph[2, 1]))
+    return fn

@@ -10,6 +10,8 @@ import pytest
 
 import oracle
 from oracle.dense import Dense2, Dense3
+from closed_form import (links_from_potential2, links_from_potential3, links_from_site_phase2,
+                         links_from_site_phase3, links_uniform_field2, smooth_potential3)
 from closed_form import (eigenket2, eigenket3, growth_factor, lattice_momentum, omega,
                          plane_wave2, plane_wave3, rel_l2)
 
@@ -606,3 +608,69 @@ def test_complex_potential_plane_wave_2d(V):
         steps = 20
         lat.step(f, th, steps, thi=thi)
         assert rel_l2(f, [lam[q] ** steps * a for a in f0]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Vector potential by gauge links (Sect. 4, Peierls substitution).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_links_pure_gauge_is_a_phase(dim):
+    """Links built from a site function chi, U(X -> Y) = exp(i(chi(Y) - chi(X))),
+    are a pure gauge: the evolved state is exp(-i chi) times the free evolution
+    of exp(i chi) psi0, exactly.  A wrong orientation or a missing conjugate on
+    either sheet breaks this."""
+    g = rng(301)
+    if dim == 3:
+        lat, cnt = oracle.Lattice3(5, 4, 6, DT3), 8
+        make = links_from_site_phase3
+    else:
+        lat, cnt = oracle.Lattice2(7, 6, DT2), 4
+        make = links_from_site_phase2
+    chi = [g.uniform(-np.pi, np.pi, lat.shape) for _ in range(cnt)]
+    U = make(lat.shape, chi)
+    f0 = rand_state(lat.shape, cnt, g)
+    th = rand_theta(lat.shape, cnt, g)
+    f = [a.copy() for a in f0]
+    lat.step(f, th, 6, links=U)
+    h = [np.exp(1j * chi[a]) * f0[a] for a in range(cnt)]
+    lat.step(h, th, 6)
+    assert rel_l2(f, [np.exp(-1j * chi[a]) * h[a] for a in range(cnt)]) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_links_unit_and_conservation(dim):
+    """Unit links give the plain scheme; a static link field that is not a pure
+    gauge (random phases; a uniform magnetic flux in 2D) keeps E_r, with the
+    links in S_X, exactly conserved, and its two forms agree."""
+    g = rng(302)
+    if dim == 3:
+        lat, cnt, nl = oracle.Lattice3(6, 5, 7, DT3), 8, 24
+    else:
+        lat, cnt, nl = oracle.Lattice2(9, 8, DT2), 4, 8
+    f0 = rand_state(lat.shape, cnt, g)
+    th = rand_theta(lat.shape, cnt, g)
+    ones = [np.ones(lat.shape, np.complex128) for _ in range(nl)]
+    f1, f2 = [a.copy() for a in f0], [a.copy() for a in f0]
+    lat.step(f1, th, 3, links=ones)
+    lat.step(f2, th, 3)
+    assert rel_l2(f1, f2) < 1e-15
+    # smooth fields with curl (a physical vector potential varies slowly on the
+    # grid; uniformly random link phases would make E_r indefinite, and the
+    # state then grows although E_r is still an exact invariant)
+    if dim == 3:
+        fields = [links_from_potential3(lat.shape, smooth_potential3(lat.shape, 0.5, 7))]
+    else:
+        fields = [links_uniform_field2(lat.shape, 0.05),
+                  links_from_potential2(lat.shape, lambda x, y: (0.4 * np.sin(2 * np.pi * y / 8.0),
+                                                                 0.3 * np.cos(2 * np.pi * x / 9.0)))]
+    for U in fields:
+        f = [a.copy() for a in f0]
+        e0 = lat.energy_links(f, U)
+        assert abs(e0[0] - e0[1]) < 1e-13 * e0[2]
+        lat.step(f, th, 50, links=U)
+        e1 = lat.energy_links(f, U)
+        assert e1[2] < 10 * e0[2]                     # bounded: E_r is definite here
+        assert abs(e1[0] - e0[0]) < 1e-13 * 50 * e0[2]
+        assert abs(e1[0] - e1[1]) < 1e-13 * e0[2]
+        # without the links in S_X the functional is not the conserved one
+        assert abs(lat.energy(f)[0] - e0[0]) > 1e-6 * e0[2]
