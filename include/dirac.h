@@ -183,6 +183,30 @@ int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream
  */
 int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im, int64_t n, void *stream);
 
+/*
+ * Vector potential by gauge links (Sect. 4: the Peierls substitution applied
+ * to each neighbour coupling of Eqs. ss1-ss4 / scheme2Deq-scheme4thline).
+ * links: 24 (3D) or 8 (2D) caller-owned device arrays, one complex per cell in
+ * the lattice's storage type (complex64 for DIRAC_C64, complex128 for
+ * DIRAC_C128), laid out like the state arrays.  links[6 a + t] (3D) /
+ * links[4 a + t] (2D) belongs to state array a of the A,B group (A0, A1, B0,
+ * B1) / u group (u0, u1) and neighbour term t in the order +z, -z, +x, -x, +y,
+ * -y (2D: +x, -x, +y, -y): in S_X of that array at cell c, the neighbour
+ * value reached in direction t is multiplied by links[6 a + t][c].  The C,D /
+ * v rows use the complex conjugate of the factor of the same half-link, taken
+ * at its A,B / u end.  For U = exp(-i a_j(mid) d_j) (a_j the Peierls phase per
+ * unit length at the half-link midpoint, d_j the signed displacement) the
+ * coupling is gauge covariant: with U = exp(i (chi(Y) - chi(X))) a step maps
+ * exp(-i chi) psi to exp(-i chi) times the free step of psi.  Unit-modulus
+ * links keep E_r (dirac_norm, evaluated with the links) exactly conserved.
+ * While links are bound, the step, the reversed step and the reductions use
+ * the split kernels (FUSED requests are ignored); dirac_adjoint_vz is
+ * refused.  links == NULL unbinds them.  The arrays must stay valid while
+ * bound.  DIRAC_E_ARG for a null link array (nothing is bound then),
+ * DIRAC_E_STATE for a batch context.  Makes no HIP call.
+ */
+int dirac_set_links(dirac_ctx *ctx, void *const links[]);
+
 /* Choose the step kernel and its tiling; 0 = library default for a knob.
  *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8
  *           (default 8); its tile is 64 cells in x (128 for complex64 with nx even)

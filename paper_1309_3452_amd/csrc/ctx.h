@@ -35,6 +35,10 @@ struct dirac_ctx {
     void *theta[8] = {};
     bool site_mode = false;
 
+    // gauge links (vector potential), caller-owned; links_on when bound
+    void *links[24] = {};
+    bool links_on = false;
+
     // kernel choice
     int kernel = 0, tile_y = 0, zchunk = 0;
 

@@ -257,6 +257,7 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
 
 int kernel_choice(const dirac_ctx *c) {
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
+    if (c->links_on) return DIRAC_KERNEL_SPLIT;    // only the split kernels carry links
     // the fused kernels address a plane with 32-bit byte offsets
     const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
     if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
@@ -270,6 +271,12 @@ int kernel_choice(const dirac_ctx *c) {
         (c->kernel == DIRAC_KERNEL_FUSED2 || c->nx * c->ny >= (int64_t)1 << 20))
         return DIRAC_KERNEL_FUSED2;
     return DIRAC_KERNEL_FUSED;
+}
+
+LinkPtrs link_ptrs(const dirac_ctx *c) {
+    LinkPtrs L;
+    for (int q = 0; q < 24; ++q) L.u[q] = c->links[q];
+    return L;
 }
 
 template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipStream_t s) {
@@ -296,7 +303,11 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
         } else {
             HalfArgs<R> a = half_args<R>(c, reverse);
             int first = reverse ? 1 : 0;
-            if (c->ndim == 3) {
+            if (c->links_on) {
+                const LinkPtrs L = link_ptrs(c);
+                HIPCHK(c, launch_half_links<R>(a, L, c->ndim, first, site, s));
+                HIPCHK(c, launch_half_links<R>(a, L, c->ndim, 1 - first, site, s));
+            } else if (c->ndim == 3) {
                 HIPCHK(c, launch_half3<R>(a, first, site, s));
                 HIPCHK(c, launch_half3<R>(a, 1 - first, site, s));
             } else {
@@ -495,6 +506,20 @@ int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
     return DIRAC_OK;
 }
 
+int dirac_set_links(dirac_ctx *c, void *const links[]) {
+    if (!c) return DIRAC_E_ARG;
+    if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    for (int q = 0; q < 24; ++q) c->links[q] = nullptr;
+    c->links_on = false;
+    if (!links) return DIRAC_OK;
+    const int nl = c->ndim == 3 ? 24 : 8;
+    for (int q = 0; q < nl; ++q)
+        if (!links[q]) return fail(c, DIRAC_E_ARG, "null link array %d", q);
+    for (int q = 0; q < nl; ++q) c->links[q] = links[q];
+    c->links_on = true;
+    return DIRAC_OK;
+}
+
 int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream) {
     return dirac_coef_from_theta_c(coef, theta, nullptr, n, stream);
 }
@@ -628,7 +653,11 @@ int dirac_norm_device(dirac_ctx *c, void *dev_out, void *stream) {
     if (!dev_out) return fail(c, DIRAC_E_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     double *part = (double *)scratch_at(c, off_partial(c));
-    if (c->dtype == DIRAC_C64) {
+    if (c->links_on) {
+        const LinkPtrs L = link_ptrs(c);
+        if (c->dtype == DIRAC_C64) HIPCHK(c, launch_norm_links<float>(reduce_args<float>(c, 0.0), L, c->ndim, s));
+        else HIPCHK(c, launch_norm_links<double>(reduce_args<double>(c, 0.0), L, c->ndim, s));
+    } else if (c->dtype == DIRAC_C64) {
         ReduceArgs<float> a = reduce_args<float>(c, 0.0);
         HIPCHK(c, c->ndim == 3 ? launch_norm3<float>(a, s) : launch_norm2<float>(a, s));
     } else {
@@ -704,6 +733,7 @@ int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int,
     if (c->site_mode) return fail(c, DIRAC_E_STATE, "needs a V(z) profile (dirac_set_mass_potential_z)");
     if (!c->w_int.empty())
         return fail(c, DIRAC_E_STATE, "the reversal-based adjoint needs a real potential (no absorbing layers)");
+    if (c->links_on) return fail(c, DIRAC_E_STATE, "the V(z) gradient kernels carry no gauge links");
     if (n < 0 || !lam || !dLdV_int || !dLdV_half) return fail(c, DIRAC_E_ARG, "bad arguments");
     for (int q = 0; q < 8; ++q)
         if (!lam[q]) return fail(c, DIRAC_E_ARG, "null lam array %d", q);

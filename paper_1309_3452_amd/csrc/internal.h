@@ -46,6 +46,13 @@ template <typename R> struct ReduceArgs {
     double *partial;      // [nblocks][nv]
 };
 
+// Gauge-link arrays (vector potential, Sect. 4): u[6 a + t] (3D) or u[4 a + t]
+// (2D) for A,B (u) array a and neighbour term t, one unit complex per cell in
+// the lattice's storage type.
+struct LinkPtrs {
+    const void *u[24];
+};
+
 // Adjoint sweep launch (V(z) profile mode).
 template <typename R> struct AdjArgs {
     void *f[8];           // state, rebuilt in place
@@ -89,6 +96,13 @@ template <typename R> hipError_t launch_fused2(const FusedArgs<R> &a, bool site,
 template <typename R> hipError_t launch_norm2(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_obs2(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_seed2(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);
+
+// Split half-step (which: 0 A,B / u, 1 C,D / v) and E_r reduction with gauge
+// links (gauge.hip); ndim 3 or 2.
+template <typename R> hipError_t launch_half_links(const HalfArgs<R> &a, const LinkPtrs &L, int ndim, int which,
+                                                   bool site, hipStream_t s);
+template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const LinkPtrs &L, int ndim,
+                                                   hipStream_t s);
 
 // Adjoint (adjoint.hip)
 template <typename R> hipError_t launch_adj3(const AdjArgs<R> &a, int sweep, hipStream_t s);

@@ -163,6 +163,26 @@ class Lattice:
             self._ctx, float(m), ptr_array([v.data_ptr() for v in vs]) if vs is not None else None,
             ptr_array([t.data_ptr() for t in self.theta]), _stream_handle()), self._ctx)
 
+    def set_links(self, links=None):
+        """Gauge links of a vector potential (Sect. 4): 24 (3D) or 8 (2D) tensors
+        of the state's shape and dtype, links[6 a + t] / links[4 a + t] for A,B /
+        u array a and neighbour term t in the order +z, -z, +x, -x, +y, -y (2D:
+        +x, -x, +y, -y); the C,D / v rows use the conjugates (see
+        dirac_set_links).  None unbinds them."""
+        if links is None:
+            check(lib().dirac_set_links(self._ctx, None), self._ctx)
+            self._links = None
+            return
+        nl = 24 if self.ndim == 3 else 8
+        if len(links) != nl:
+            raise ValueError("expected %d link arrays" % nl)
+        lk = [torch.as_tensor(u).to(device=self.device, dtype=self.dtype).contiguous() for u in links]
+        for u in lk:
+            if tuple(u.shape) != self.tshape:
+                raise ValueError("link shape %s != %s" % (tuple(u.shape), self.tshape))
+        check(lib().dirac_set_links(self._ctx, ptr_array([u.data_ptr() for u in lk])), self._ctx)
+        self._links = lk
+
     def set_kernel(self, kind: str = "auto", tile_y: int = 0, zchunk: int = 0):
         """kind: "auto", "split", "fused" (one step per launch) or "fused2" (two)."""
         code = {"auto": _abi.DIRAC_KERNEL_AUTO, "split": _abi.DIRAC_KERNEL_SPLIT,

@@ -88,6 +88,12 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_set_potential_im_z(c3, w, w, nz) == 0
     assert L.dirac_set_potential_im_z(c3, None, None, nz) == 0
     assert L.dirac_coef_from_theta_c(None, None, None, 1, None) == -1
+    # gauge links: 24 non-null arrays in 3D (pointers only recorded, never dereferenced here)
+    from paper_1309_3452_amd._abi import ptr_array
+    assert L.dirac_set_links(c3, ptr_array([256] * 23 + [0])) == -1
+    assert b"null link array 23" in L.dirac_last_error(c3)
+    assert L.dirac_set_links(c3, ptr_array([256] * 24)) == 0
+    assert L.dirac_set_links(c3, None) == 0
     L.dirac_destroy(c3)
     L.dirac_destroy(c)
     L.dirac_destroy(None)

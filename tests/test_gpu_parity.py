@@ -581,3 +581,198 @@ def test_absorbing_dissipation_identity_gpu(P):
         e1 = lat.norm()[0]
         rhs = sum(float(np.sum((0.5 * DT3 * zs[a])[:, None, None] * np.abs(post[a] + pre[a]) ** 2)) for a in range(8))
         assert abs((e1 - e0) - rhs) <= 1e-12 * abs(e0)
+
+
+# --------------------------------------------------------------------------
+# Vector potential by gauge links (Sect. 4, Peierls substitution)
+# --------------------------------------------------------------------------
+def _links_t(U):
+    return [torch.from_numpy(np.ascontiguousarray(u)) for u in U]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 25e-6)])
+@pytest.mark.parametrize("site", [False, True])
+def test_3d_links_vs_oracle(P, dtype, tol, site):
+    from closed_form import links_from_potential3, smooth_potential3
+    nx, ny, nz = 70, 20, 22
+    print("3d links %s site=%s" % (dtype, site), flush=True)
+    shape = (nz, ny, nx)
+    U = links_from_potential3(shape, smooth_potential3(shape, 0.5, 171))
+    f0 = rand_state(shape, 8, 172)
+    m = 0.5
+    lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+    lat.set_kernel("fused2")          # links force the split kernels regardless
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    if site:
+        g = np.random.default_rng(173)
+        V = [np.ascontiguousarray(0.4 * g.standard_normal(shape)) for _ in range(8)]
+        if dtype == torch.complex64:
+            V = [v.astype(np.float32).astype(np.float64) for v in V]
+        lat.set_fields(m, [torch.from_numpy(v) for v in V])
+        th = [np.ascontiguousarray(0.5 * DT3 * ((1.0 if a < 4 else -1.0) * m + V[a])) for a in range(8)]
+    else:
+        v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+        lat.set_potential_z(m, v_int, v_half)
+        th = ol.theta_vz(m, v_int, v_half)
+    lat.set_links(_links_t(U))
+    lat.load(f0)
+    f0 = np_state(lat.state())
+    Uc = [u.astype(np.complex64).astype(np.complex128) for u in U] if dtype == torch.complex64 else U
+    e0 = lat.norm()
+    steps = 20
+    lat.step(steps)
+    f = [a.copy() for a in f0]
+    ol.step(f, th, steps, links=Uc)
+    assert rel_l2(np_state(lat.state()), f) <= tol
+    e1 = lat.norm()
+    eo = ol.energy_links(f, Uc)
+    rtol = 1e-12 if dtype == torch.complex128 else 1e-5
+    assert abs(e1[0] - eo[0]) <= rtol * abs(eo[0])
+    assert abs(e1[1] - eo[1]) <= rtol * abs(eo[0])
+    assert abs(e1[2] - eo[2]) <= rtol * eo[2]
+    # conserved by the GPU steps: FP64 to rounding, FP32 within its drift bound
+    assert abs(e1[0] - e0[0]) <= (1e-13 if dtype == torch.complex128 else 1e-6) * steps * abs(e0[0])
+    assert e1[2] <= 20.0 * e0[2]      # bounded: E_r stays positive for this field
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 25e-6)])
+@pytest.mark.parametrize("site", [False, True])
+@pytest.mark.parametrize("shape", [(96, 70), (130, 33)])
+def test_2d_links_vs_oracle(P, dtype, tol, site, shape):
+    from closed_form import links_from_potential2, links_uniform_field2
+    nx, ny = shape
+    print("2d links %s %s site=%s" % (shape, dtype, site), flush=True)
+    tsh = (ny, nx)
+    a_fn = lambda x, y: (0.3 * np.sin(2 * np.pi * y / ny) + 0.1, 0.25 * np.cos(2 * np.pi * x / nx))
+    U = links_from_potential2(tsh, a_fn)
+    # uniform field with a Landau gauge periodic across the y wrap (flux 4 pi / ny
+    # per cell); stronger fields near the step bound make E_r indefinite
+    U2 = links_uniform_field2(tsh, 4 * np.pi / ny)
+    U = [u * w for u, w in zip(U, U2)]
+    f0 = rand_state(tsh, 4, 181)
+    m = 0.4
+    lat = P.Lattice2D(nx, ny, dtype=dtype, dt=DT2)
+    ol = oracle.Lattice2(nx, ny, DT2)
+    if site:
+        g = np.random.default_rng(182)
+        V = [np.ascontiguousarray(0.5 * g.standard_normal(tsh)) for _ in range(4)]
+        if dtype == torch.complex64:
+            V = [v.astype(np.float32).astype(np.float64) for v in V]
+        lat.set_fields(m, [torch.from_numpy(v) for v in V])
+        th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * m + V[a])) for a in range(4)]
+    else:
+        lat.set_potential_z(m)
+        th = ol.theta(m)
+    lat.set_links(_links_t(U))
+    lat.load(f0)
+    f0 = np_state(lat.state())
+    Uc = [u.astype(np.complex64).astype(np.complex128) for u in U] if dtype == torch.complex64 else U
+    steps = 25
+    e0 = lat.norm()
+    lat.step(steps)
+    f = [a.copy() for a in f0]
+    ol.step(f, th, steps, links=Uc)
+    assert rel_l2(np_state(lat.state()), f) <= tol
+    e1 = lat.norm()
+    eo = ol.energy_links(f, Uc)
+    rtol = 1e-12 if dtype == torch.complex128 else 1e-5
+    # GPU (u-site form, v-site form) vs oracle (v-site form, u-site form): equal up to rounding
+    assert abs(e1[0] - eo[1]) <= rtol * abs(eo[0])
+    assert abs(e1[1] - eo[0]) <= rtol * abs(eo[0])
+    assert abs(e1[2] - eo[2]) <= rtol * eo[2]
+    assert abs(e1[0] - e0[0]) <= (1e-13 if dtype == torch.complex128 else 1e-6) * steps * abs(e0[0])
+    assert e1[2] <= 20.0 * e0[2]      # bounded: E_r stays positive for this field
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_unit_links_bitwise_equal_split(P, dim, dtype):
+    """Unit links multiply every neighbour by exactly 1: the link kernels then
+    give the bits of the plain split kernels."""
+    print("unit links dim=%d %s" % (dim, dtype), flush=True)
+    if dim == 3:
+        nx, ny, nz = 40, 9, 13
+        shape, nl, mk = (nz, ny, nx), 24, (lambda: P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3))
+        v_int, v_half = workloads.step_potential(nz, 1.0, nz / 2.0, 2.0)
+    else:
+        nx, ny = 70, 33
+        shape, nl, mk = (ny, nx), 8, (lambda: P.Lattice2D(nx, ny, dtype=dtype, dt=DT2))
+        v_int = v_half = None
+    f0 = rand_state(shape, 8 if dim == 3 else 4, 191)
+    out = []
+    for use_links in (False, True):
+        lat = mk()
+        lat.set_kernel("split")
+        lat.set_potential_z(0.3, v_int, v_half) if dim == 3 else lat.set_potential_z(0.3)
+        if use_links:
+            lat.set_links([torch.ones(shape, dtype=dtype) for _ in range(nl)])
+        lat.load(f0)
+        lat.step(9)
+        out.append([t.clone() for t in lat.state()] + [torch.tensor(lat.norm())])
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+
+
+def test_3d_links_pure_gauge_vs_oracle(P):
+    """Pure-gauge links U = exp(i (chi(Y) - chi(X))) acting on exp(-i chi) psi0
+    give exp(-i chi) times the free evolution of psi0 (GPU against GPU), and
+    agree with the oracle's link step."""
+    from closed_form import links_from_site_phase3
+    nx, ny, nz = 18, 10, 12
+    shape = (nz, ny, nx)
+    print("3d pure gauge", flush=True)
+    g = np.random.default_rng(201)
+    chi = [np.ascontiguousarray(g.uniform(-np.pi, np.pi, shape)) for _ in range(8)]
+    U = links_from_site_phase3(shape, chi)
+    f0 = rand_state(shape, 8, 202)
+    v_int, v_half = workloads.step_potential(nz, 1.0, nz / 2.0, 2.0)
+    lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat.set_potential_z(0.5, v_int, v_half)
+    lat.load(f0)
+    lat.step(8)
+    free = np_state(lat.state())
+    lat2 = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    lat2.set_potential_z(0.5, v_int, v_half)
+    lat2.set_links(_links_t(U))
+    lat2.load([np.exp(-1j * chi[a]) * f0[a] for a in range(8)])
+    lat2.step(8)
+    gauged = np_state(lat2.state())
+    assert rel_l2(gauged, [np.exp(-1j * chi[a]) * free[a] for a in range(8)]) <= 1e-13
+    ol = oracle.Lattice3(nx, ny, nz, DT3)
+    f = [np.exp(-1j * chi[a]) * f0[a] for a in range(8)]
+    ol.step(f, ol.theta_vz(0.5, v_int, v_half), 8, links=U)
+    assert rel_l2(gauged, f) <= 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_links_reverse_and_step_norm(P, dim):
+    """The reversed step undoes the link step; step_norm reports the link E_r."""
+    from closed_form import links_from_potential2, links_from_potential3, smooth_potential3
+    print("links reverse dim=%d" % dim, flush=True)
+    if dim == 3:
+        nx, ny, nz = 34, 12, 10
+        shape = (nz, ny, nx)
+        U = links_from_potential3(shape, smooth_potential3(shape, 0.6, 211))
+        lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+        narr = 8
+    else:
+        nx, ny = 50, 42
+        shape = (ny, nx)
+        U = links_from_potential2(shape, lambda x, y: (0.5 * np.sin(2 * np.pi * y / ny), 0.2))
+        lat = P.Lattice2D(nx, ny, dtype=torch.complex128, dt=DT2)
+        narr = 4
+    lat.set_potential_z(0.7)
+    lat.set_links(_links_t(U))
+    f0 = rand_state(shape, narr, 212)
+    lat.load(f0)
+    out = lat.step_norm(12)
+    torch.cuda.synchronize()
+    e = lat.norm()
+    assert abs(float(out[0]) - e[0]) <= 1e-13 * abs(e[0]) and float(out[1]) == e[2]
+    lat.reverse(12)
+    assert rel_l2(np_state(lat.state()), f0) <= 1e-12
+    if dim == 3:
+        with pytest.raises(P.DiracError):
+            lat.adjoint_vz(1, lat.seed_region(nz / 2.0))
+    lat.set_links(None)
+    lat.step(1)          # plain kernels again
