@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
                     help="auto = fused2 (two steps per launch) where it applies")
-    ap.add_argument("--workload", default="step3d", choices=["step3d", "batched2d", "adjoint3d", "plane2d"],
+    ap.add_argument("--workload", default="step3d",
+                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -262,6 +263,45 @@ def bench_adjoint(steps, dtype_name):
             "grad_norm": float(p.grad.norm()), "rebuilt_initial_state_rel_l2": err}
 
 
+def bench_links3d(n, steps, dtype_name):
+    """(3+1)D n^3 step with a vector potential as gauge links (split kernels with links)."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    dtype = torch.complex64 if dtype_name == "f32" else torch.complex128
+    cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    lat.set_links(workloads.peierls_links3d(n, n, n, 0.05, 31, dtype=dtype, device="cuda"))
+    torch.cuda.empty_cache()
+    e0 = lat.norm()
+    lat.step(2)
+    ms = _timed(lambda: lat.step(steps))
+    e1 = lat.norm()
+    cells = n ** 3
+    b = 8 if dtype_name == "f32" else 16
+    # per half-step launch and cell: 4 own amplitudes read + written, 4 partner amplitudes
+    # read, 24 link factors read (each byte once)
+    alg_launch = (12 + 24) * b * cells
+    launch_ms = ms / steps / 2
+    achieved = alg_launch / (launch_ms * 1e-3) / 1e9
+    return {"metric": "site-updates/s, (3+1)D %d^3 with gauge links (vector potential)" % n,
+            "value": cells * steps / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
+            "warmup": 2, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
+            "config": {"workload": "(3+1)D %d^3 Klein-step lattice of the headline workload plus Peierls links of "
+                                   "a smooth periodic vector potential (amplitude 0.05 rad/cell), split kernels "
+                                   "with links" % n, "cells": cells},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k3_half_links (two launches per step)", "avg_launch_ms": launch_ms,
+                         "alg_bytes_per_launch": alg_launch},
+            "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]), "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
+
+
 def bench_plane2d(steps):
     """(2+1)D 128^2, complex128, 200 steps: launch-bound; plain launches vs one captured graph."""
     import torch
@@ -309,6 +349,10 @@ def main():
         return
     if args.workload == "plane2d":
         print(json.dumps(bench_plane2d(200)), flush=True)
+        return
+    if args.workload == "links3d":
+        for d in ("f32", "f64"):
+            print(json.dumps(bench_links3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
         return
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3

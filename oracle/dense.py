@@ -7,6 +7,16 @@ Used to pin the C oracle (M^n x against stepping), the conserved functional
 (M^H G M = G, Lemma of Sect. 2 / Sect. 3) and the spectrum against the
 closed-form dispersion (Sect. 2.1, Eq. pwdsip).
 
+A vector potential (Sect. 4) enters through a_fn(x, y[, z]) -> per-axis phase
+per cell length (a = q A Delta / (hbar c)), positions in cell units:
+  rule="exact":  the neighbour at displacement d (+-1/2 cell along axis j)
+                 is multiplied by exp(-i a_j(M) d), M the half-link midpoint
+                 (the Peierls substitution with the line integral by the
+                 midpoint rule);
+  rule="linear": the paper's simplified rule for smooth potentials, the
+                 difference psi(+) - psi(-) replaced by psi(+) - psi(-)
+                 - i a_j (psi(+) + psi(-))/2 with a_j taken at the row's site.
+
 State vector order: the arrays of the oracle's convention concatenated,
 3D: A0 A1 B0 B1 | C0 C1 D0 D1, 2D: u0 u1 | v0 v1, each flattened [k][j][i].
 """
@@ -34,8 +44,22 @@ _RULES2 = {
 }
 
 
+def _factors(a_fn, rule, pos2, axis, e2):
+    """(factor of the + neighbour, factor of the - neighbour) for the row at
+    doubled position pos2 along axis (index), e2 the unit step in doubled units."""
+    if a_fn is None:
+        return 1.0, 1.0
+    if rule == "linear":
+        aj = a_fn(*[p / 2.0 for p in pos2])[axis]
+        return 1.0 - 0.5j * aj, 1.0 + 0.5j * aj
+    mp = [(p + 0.5 * e) / 2.0 for p, e in zip(pos2, e2)]
+    mm = [(p - 0.5 * e) / 2.0 for p, e in zip(pos2, e2)]
+    return np.exp(-0.5j * a_fn(*mp)[axis]), np.exp(0.5j * a_fn(*mm)[axis])
+
+
 class Dense3:
-    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0):
+    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0, a_fn=None, rule="exact"):
+        self.a_fn, self.rule = a_fn, rule
         self.nx, self.ny, self.nz = nx, ny, nz
         self.dt = dt
         self.r = {"x": dt / dx, "y": dt / dy, "z": dt / dz}
@@ -61,13 +85,15 @@ class Dense3:
         """K with (K psi)_s = S_X(s) for every site s (both sheets)."""
         K = np.zeros((self.dim, self.dim), np.complex128)
         unit = {"x": (1, 0, 0), "y": (0, 1, 0), "z": (0, 0, 1)}
+        axis = {"x": 0, "y": 1, "z": 2}
         for s, (comp, pos) in enumerate(self.sites):
             for d, c, src in _RULES3[comp]:
                 e = unit[d]
                 plus = (pos[0] + e[0], pos[1] + e[1], pos[2] + e[2])
                 minus = (pos[0] - e[0], pos[1] - e[1], pos[2] - e[2])
-                K[s, self._find(src, plus)] += c * self.r[d]
-                K[s, self._find(src, minus)] -= c * self.r[d]
+                fp, fm = _factors(self.a_fn, self.rule, pos, axis[d], e)
+                K[s, self._find(src, plus)] += c * self.r[d] * fp
+                K[s, self._find(src, minus)] -= c * self.r[d] * fm
         return K
 
     def step_matrix(self, theta):
@@ -106,7 +132,8 @@ class Dense3:
 
 
 class Dense2:
-    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0):
+    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0, a_fn=None, rule="exact"):
+        self.a_fn, self.rule = a_fn, rule
         self.nx, self.ny = nx, ny
         self.dt = dt
         self.r = {"x": dt / dx, "y": dt / dy}
@@ -129,11 +156,13 @@ class Dense2:
     def _difference_operator(self):
         K = np.zeros((self.dim, self.dim), np.complex128)
         unit = {"x": (1, 0), "y": (0, 1)}
+        axis = {"x": 0, "y": 1}
         for s, (comp, pos) in enumerate(self.sites):
             for d, c, src in _RULES2[comp]:
                 e = unit[d]
-                K[s, self._find(src, (pos[0] + e[0], pos[1] + e[1]))] += c * self.r[d]
-                K[s, self._find(src, (pos[0] - e[0], pos[1] - e[1]))] -= c * self.r[d]
+                fp, fm = _factors(self.a_fn, self.rule, pos, axis[d], e)
+                K[s, self._find(src, (pos[0] + e[0], pos[1] + e[1]))] += c * self.r[d] * fp
+                K[s, self._find(src, (pos[0] - e[0], pos[1] - e[1]))] -= c * self.r[d] * fm
         return K
 
     def step_matrix(self, theta):

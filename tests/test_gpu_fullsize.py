@@ -172,6 +172,58 @@ def test_sampled_oracle_parity_256_fp64(P):
             assert abs(box[a][R, R, R] - got[a][k, j, i]) <= 1e-13 * scale, (i, j, k, a)
 
 
+def test_sampled_oracle_parity_links_512_fp32(P):
+    """The gauge-link workload bench.py times (512^3, complex64, Peierls links of a
+    smooth vector potential): after 3 steps, sampled cells against the FP64 oracle
+    with the same (complex64-rounded) links on periodic sub-boxes; E_r with the
+    links conserved at full size."""
+    n, steps, R = 512, 3, 7
+    cfg = workloads.config_step3d(n, dtype=torch.complex64, device="cuda")
+    print("sampled links parity 512^3 fp32", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex64, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    f0 = [t.clone() for t in lat.state()]
+    del cfg["state"]
+    U = workloads.peierls_links3d(n, n, n, 0.05, 31, dtype=torch.complex64, device="cuda")
+    lat.set_links(U)
+    e0 = lat.norm()
+    lat.step(steps)
+    e1 = lat.norm()
+    assert abs(e1[0] - e0[0]) <= 1e-6 * steps * abs(e0[0])
+    got = lat.state()
+    g = np.random.default_rng(19)
+    samples = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(16)]
+    samples += [(n // 2, n // 2, n // 4), (0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 0, n // 2)]
+    B = 2 * R + 1
+    ol = oracle.Lattice3(B, B, B, cfg["dt"])
+    scale = max(float(t.abs().max()) for t in got)
+    vz = lambda z: 1.5 * (1.0 + np.tanh((z - n / 2.0) / 4.0)) / 2.0
+
+    def box_of(t, iz, iy, ix):
+        idx = lambda v: torch.from_numpy(v).to("cuda")
+        sub = t.index_select(0, idx(iz)).index_select(1, idx(iy)).index_select(2, idx(ix))
+        return np.ascontiguousarray(sub.cpu().numpy().astype(np.complex128))
+
+    for (i, j, k) in samples:
+        ix = (np.arange(i - R, i + R + 1)) % n
+        iy = (np.arange(j - R, j + R + 1)) % n
+        iz = (np.arange(k - R, k + R + 1)) % n
+        box = [box_of(a, iz, iy, ix) for a in f0]
+        ubox = [box_of(u, iz, iy, ix) for u in U]
+        th = []
+        for a in range(8):
+            z = (iz + workloads.OFF3[a][2])[:, None, None] * np.ones((1, B, B))
+            sgn = 1.0 if a < 4 else -1.0
+            th.append(np.ascontiguousarray(0.5 * cfg["dt"] * (sgn * cfg["m"] + vz(z))))
+        ol.step(box, th, steps, links=ubox)
+        for a in range(8):
+            gv = complex(got[a][k, j, i].item())
+            assert abs(box[a][R, R, R] - gv) <= 3e-6 * scale, (i, j, k, a)
+    del lat, f0, U
+    free()
+
+
 def test_adjoint_fd_128_fp64(P):
     """The reversible adjoint's dL/dp against central finite differences (h = 1e-6)
     on the 128^3 adjoint workload (400 steps), FP64."""

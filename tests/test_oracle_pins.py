@@ -674,3 +674,73 @@ def test_links_unit_and_conservation(dim):
         assert abs(e1[0] - e1[1]) < 1e-13 * e0[2]
         # without the links in S_X the functional is not the conserved one
         assert abs(lat.energy(f)[0] - e0[0]) > 1e-6 * e0[2]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_links_match_dense_from_potential(dim):
+    """The oracle's link step (C,D / v rows find their link by displacement) equals
+    the dense one-step matrix assembled from the vector potential itself, each
+    coupling carrying exp(-i a_j(M) d) for its own midpoint M and displacement d
+    (Sect. 4); the link functional equals psi^H G psi of that operator, and
+    M^H G M = G."""
+    g = rng(303)
+    if dim == 3:
+        nx, ny, nz = 4, 3, 5
+        lat, cnt = oracle.Lattice3(nx, ny, nz, DT3), 8
+        a_fn = smooth_potential3(lat.shape, 0.7, 11)
+        D = Dense3(nx, ny, nz, DT3, a_fn=a_fn)
+        U = links_from_potential3(lat.shape, a_fn)
+    else:
+        nx, ny = 5, 4
+        lat, cnt = oracle.Lattice2(nx, ny, DT2), 4
+        a_fn = lambda x, y: (0.6 * np.sin(2 * np.pi * y / ny + 0.3) + 0.2,
+                             0.5 * np.cos(2 * np.pi * x / nx - 0.4) * np.cos(2 * np.pi * y / ny))
+        D = Dense2(nx, ny, DT2, a_fn=a_fn)
+        U = links_from_potential2(lat.shape, a_fn)
+    f = rand_state(lat.shape, cnt, g)
+    x0 = D.pack(f)
+    x = x0.copy()
+    for _ in range(3):
+        th = rand_theta(lat.shape, cnt, g)
+        lat.step(f, th, links=U)
+        x = D.step_matrix(D.pack(th).real) @ x
+    assert rel_l2([D.pack(f)], [x]) < 1e-13
+    G = D.gram()
+    e = lat.energy_links(f, U)
+    xf = D.pack(f)
+    assert abs(np.vdot(xf, G @ xf).real - e[0]) < 1e-12 * e[2]
+    M = D.step_matrix(D.pack(rand_theta(lat.shape, cnt, g)).real)
+    assert np.abs(M.conj().T @ G @ M - G).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linearised_rule_is_second_order(dim):
+    """Sect. 4's simplified rule for smooth potentials (a difference psi(+) -
+    psi(-) becomes psi(+) - psi(-) - i a_j (psi(+) + psi(-))/2) agrees with the
+    exact Peierls links to second order in a: for a uniform potential the
+    one-step difference shrinks fourfold when a is halved."""
+    g = rng(304)
+    if dim == 3:
+        nx, ny, nz = 3, 4, 4
+        f = rand_state((nz, ny, nx), 8, g)
+        mk = lambda fn, rule: Dense3(nx, ny, nz, DT3, a_fn=fn, rule=rule)
+        n_arr = 8
+        shape = (nz, ny, nx)
+    else:
+        nx, ny = 5, 4
+        f = rand_state((ny, nx), 4, g)
+        mk = lambda fn, rule: Dense2(nx, ny, DT2, a_fn=fn, rule=rule)
+        n_arr = 4
+        shape = (ny, nx)
+    th = rand_theta(shape, n_arr, g)
+    diffs = []
+    for eps in (0.2, 0.1, 0.05):
+        fn = (lambda x, y, z: (0.7 * eps, -0.4 * eps, 0.5 * eps)) if dim == 3 else \
+             (lambda x, y: (0.7 * eps, -0.4 * eps))
+        De, Dl = mk(fn, "exact"), mk(fn, "linear")
+        x = De.pack(f)
+        t = De.pack(th).real
+        diffs.append(np.linalg.norm(De.step_matrix(t) @ x - Dl.step_matrix(t) @ x) / np.linalg.norm(x))
+    assert diffs[1] > 1e-5
+    for q in range(2):
+        assert 3.6 < diffs[q] / diffs[q + 1] < 4.4, diffs

@@ -136,6 +136,37 @@ def hat_basis(nz, nodes=32):
     return H(k), H(k + 0.5)
 
 
+# neighbour directions of the A,B link terms, in link-array order: +z, -z, +x, -x, +y, -y
+LINK_DIRS3 = [(0.0, 0.0, 0.5), (0.0, 0.0, -0.5), (0.5, 0.0, 0.0), (-0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, -0.5, 0.0)]
+
+
+def peierls_links3d(nx, ny, nz, amp, seed, dtype=torch.complex64, device="cpu"):
+    """Gauge links of a smooth periodic vector potential with nonzero curl,
+    a(x,y,z) = amp (sin(2 pi y/ny + p0) cos(2 pi z/nz + p1), sin(2 pi z/nz + p2)
+    cos(2 pi x/nx + p3), sin(2 pi x/nx + p4) cos(2 pi y/ny + p5)) in radians per
+    cell, phases p from the seeded generator: for A,B array a and direction t the
+    factor exp(-i a_j(M) d_j), d the displacement (+-1/2 along axis j) to the
+    neighbour and M the half-link midpoint.  Returns 24 tensors (nz, ny, nx),
+    index 6 a + t."""
+    ph = np.random.default_rng(SEED_BASE + seed).uniform(0.0, 2.0 * math.pi, 6)
+    f64 = dict(dtype=torch.float64, device=device)
+    out = []
+    for a in range(4):
+        for d in LINK_DIRS3:
+            x = (torch.arange(nx, **f64) + OFF3[a][0] + 0.5 * d[0]).view(1, 1, nx)
+            y = (torch.arange(ny, **f64) + OFF3[a][1] + 0.5 * d[1]).view(1, ny, 1)
+            z = (torch.arange(nz, **f64) + OFF3[a][2] + 0.5 * d[2]).view(nz, 1, 1)
+            if d[0] != 0.0:
+                aj = amp * torch.sin(2 * math.pi * y / ny + ph[0]) * torch.cos(2 * math.pi * z / nz + ph[1]) * d[0]
+            elif d[1] != 0.0:
+                aj = amp * torch.sin(2 * math.pi * z / nz + ph[2]) * torch.cos(2 * math.pi * x / nx + ph[3]) * d[1]
+            else:
+                aj = amp * torch.sin(2 * math.pi * x / nx + ph[4]) * torch.cos(2 * math.pi * y / ny + ph[5]) * d[2]
+            u = torch.polar(torch.ones((), **f64), -aj).to(dtype)
+            out.append(u.expand(nz, ny, nx).contiguous())
+    return out
+
+
 # --------------------------------------------------------------------------
 # Configurations
 # --------------------------------------------------------------------------
