@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
-                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d"],
+                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "klein2d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -302,6 +302,80 @@ def bench_links3d(n, steps, dtype_name):
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]), "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
 
 
+def bench_klein2d(phi_deg):
+    """(2+1)D Klein-step scattering (m = 0, step height twice the packet energy,
+    absorbing frame), complex64: steps timed; the transmitted probability and
+    refraction angle of the run are reported beside the rate."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    cfg = workloads.config_klein2d(phi_deg, dtype=torch.complex64, device="cuda", absorbing=True)
+    nx, ny = cfg["nx"], cfg["ny"]
+    lat = P.Lattice2D(nx, ny, dtype=torch.complex64, dt=cfg["dt"])
+    lat.set_fields(0.0, [torch.from_numpy(v) for v in cfg["v_site"]], [torch.from_numpy(w) for w in cfg["w_site"]])
+    # warm-up on a copy of the initial state, then the measured run from it
+    lat.load(cfg["state"])
+    lat.step(4)
+    lat.load(cfg["state"])
+    seg = [int(round(250.0 / cfg["dt"])), int(round(100.0 / cfg["dt"]))]
+    ms, meas = 0.0, []
+    xs = [(torch.arange(nx, dtype=torch.float64, device="cuda") + workloads.OFF2[a][0]) for a in range(4)]
+    ys = [(torch.arange(ny, dtype=torch.float64, device="cuda") + workloads.OFF2[a][1]) for a in range(4)]
+    for n in seg:
+        ms += _timed(lambda: lat.step(n))
+        obs = lat.observables(cfg["xc"])
+        pm = sx = sy = 0.0
+        for a, t in enumerate(lat.state()):
+            d = (t.to(torch.complex128).abs() ** 2) * (xs[a] > cfg["xc"] + 40.0)[None, :]
+            pm += float(d.sum())
+            sx += float((d * xs[a][None, :]).sum())
+            sy += float((d * ys[a][:, None]).sum())
+        meas.append((obs[0], sx / pm, sy / pm))
+    steps = sum(seg)
+    cells = nx * ny
+    angle = math.degrees(math.atan2(meas[1][2] - meas[0][2], meas[1][1] - meas[0][1]))
+    # launch variants of the same steps (every kernel gives the same bits): one step per
+    # launch, two steps per launch, and two-step launches replayed from a captured graph
+    # (an even launch count, so the replay starts from the buffers it was captured on)
+    variants = {"auto": ms / steps}
+    for kind in ("fused", "fused2"):
+        lat.set_kernel(kind)
+        lat.load(cfg["state"])
+        lat.step(2)
+        variants[kind] = _timed(lambda: lat.step(steps)) / steps
+    gsteps = 4 * (steps // 4)
+    lat.set_kernel("fused2")
+    lat.load(cfg["state"])
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        lat.step(2)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=st):
+            lat.step(gsteps)
+    torch.cuda.current_stream().wait_stream(st)
+    graph.replay()
+    variants["fused2_graph"] = _timed(lambda: graph.replay(), reps=3) / gsteps
+    best = min(variants, key=variants.get)
+    ms_step = variants[best]
+    alg = 96.0 * cells          # 4 complex64 amplitudes read + written, 4 complex64 coefficient records read
+    return {"metric": "site-updates/s, (2+1)D Klein-step scattering %dx%d complex64" % (nx, ny),
+            "value": cells / (ms_step * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
+            "warmup": 4, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "(2+1)D %dx%d, m=0, smoothed step V0=0.4 (width 3) at x=400, packet E=0.2 "
+                                   "sigma=30 at %g deg from the step normal, absorbing frame of width 32, "
+                                   "per-site complex coefficient records" % (nx, ny, phi_deg), "cells": cells},
+            "variants_ms_per_step": variants, "best": best,
+            "roofline": {"bound": "hbm", "achieved": alg / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "alg_bytes_per_step": alg},
+            "physics": {"transmitted_probability_t250": meas[0][0], "transmitted_probability_t350": meas[1][0],
+                        "refraction_angle_deg": angle}}
+
+
 def bench_plane2d(steps):
     """(2+1)D 128^2, complex128, 200 steps: launch-bound; plain launches vs one captured graph."""
     import torch
@@ -349,6 +423,10 @@ def main():
         return
     if args.workload == "plane2d":
         print(json.dumps(bench_plane2d(200)), flush=True)
+        return
+    if args.workload == "klein2d":
+        for phi in (0.0, 37.0):
+            print(json.dumps(bench_klein2d(phi)), flush=True)
         return
     if args.workload == "links3d":
         for d in ("f32", "f64"):

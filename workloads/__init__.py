@@ -188,6 +188,35 @@ def config_step3d(n, dtype=torch.complex128, device="cpu"):
     return dict(nx=n, ny=n, nz=n, dt=DT3, m=0.5, v_int=v_int, v_half=v_half, state=state, z0=n / 2.0)
 
 
+def config_klein2d(phi_deg, nx=1024, ny=512, dtype=torch.complex128, device="cpu", absorbing=False):
+    """(2+1)D Klein-step scattering (Sect. 5): m = 0, a smoothed step V(x) =
+    V0 (1 + tanh((x - xc)/w))/2 with V0 = 2 E0 (the step height is twice the
+    packet energy in both of the paper's figures), E0 = 0.2 per cell, w = 3
+    cells, xc = 400; a packet of width sigma = 30 whose centre line meets the
+    step at (xc, ny/2 + 100) at angle phi_deg from the step normal (+x),
+    starting 100 cells before it.  Optional absorbing frame (imaginary
+    potential) of width 32 at the x boundaries (where the periodic wrap puts
+    the step back down).  Returns the state, per-array V at the sites, per-array
+    W (zeros without absorber) and the parameters."""
+    E0, w, xc, sigma = 0.2, 3.0, 400.0, 30.0
+    V0 = 2.0 * E0
+    phi = math.radians(phi_deg)
+    k0 = (E0 * math.cos(phi), E0 * math.sin(phi))
+    c = (xc - 100.0 * math.cos(phi), ny / 2.0 + 100.0 - 100.0 * math.sin(phi))
+    state = packet2d(nx, ny, c, sigma, k0, 0.0, DT2, dtype=dtype, device=device)
+    v_site, w_site = [], []
+    wx = absorber(nx, 32.0, 0.5, offsets=(0.0, 0.5)) if absorbing else None
+    for a in range(4):
+        x = np.arange(nx, dtype=np.float64) + OFF2[a][0]
+        v = V0 * (1.0 + np.tanh((x - xc) / w)) / 2.0
+        v_site.append(np.ascontiguousarray(np.broadcast_to(v[None, :], (ny, nx))))
+        wa = wx[1 if OFF2[a][0] else 0] if absorbing else np.zeros(nx)
+        w_site.append(np.ascontiguousarray(np.broadcast_to(wa[None, :], (ny, nx))))
+    return dict(nx=nx, ny=ny, dt=DT2, m=0.0, E0=E0, V0=V0, w=w, xc=xc, sigma=sigma, phi=phi, k0=k0,
+                state=state, v_site=v_site, w_site=w_site,
+                v_of_x=lambda x: V0 * (1.0 + math.tanh((x - xc) / w)) / 2.0)
+
+
 def config_adjoint(n=128, nodes=32):
     """3D adjoint workload: V(z) = sum_i p_i h_i(z) with p_i = step(z_i) + 0.05 xi_i."""
     g = rng(5)
