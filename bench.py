@@ -278,27 +278,33 @@ def bench_links3d(n, steps, dtype_name):
     lat.set_links(workloads.peierls_links3d(n, n, n, 0.05, 31, dtype=dtype, device="cuda"))
     torch.cuda.empty_cache()
     e0 = lat.norm()
+    # the split link kernels (two launches per step) for comparison, then the z-march
+    # link kernel (one launch per step, the default); the state keeps evolving
+    lat.set_kernel("split")
+    lat.step(2)
+    split_ms = _timed(lambda: lat.step(steps // 2)) / (steps // 2)
+    lat.set_kernel("auto")
     lat.step(2)
     ms = _timed(lambda: lat.step(steps))
     e1 = lat.norm()
     cells = n ** 3
     b = 8 if dtype_name == "f32" else 16
-    # per half-step launch and cell: 4 own amplitudes read + written, 4 partner amplitudes
-    # read, 24 link factors read (each byte once)
-    alg_launch = (12 + 24) * b * cells
-    launch_ms = ms / steps / 2
+    # per step and cell: 16 amplitudes read or written once and 24 link factors read once
+    alg_launch = (16 + 24) * b * cells
+    launch_ms = ms / steps
     achieved = alg_launch / (launch_ms * 1e-3) / 1e9
     return {"metric": "site-updates/s, (3+1)D %d^3 with gauge links (vector potential)" % n,
             "value": cells * steps / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
             "warmup": 2, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
             "config": {"workload": "(3+1)D %d^3 Klein-step lattice of the headline workload plus Peierls links of "
-                                   "a smooth periodic vector potential (amplitude 0.05 rad/cell), split kernels "
-                                   "with links" % n, "cells": cells},
+                                   "a smooth periodic vector potential (amplitude 0.05 rad/cell), z-march "
+                                   "link kernel" % n, "cells": cells},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k3_half_links (two launches per step)", "avg_launch_ms": launch_ms,
+                         "kernel": "k3_fused_links (one launch per step)", "avg_launch_ms": launch_ms,
                          "alg_bytes_per_launch": alg_launch},
+            "split_kernels_ms_per_step": split_ms,
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]), "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
 
 
@@ -414,6 +420,14 @@ def main():
               "(z-slab sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     if args.workload == "batched2d":
         print(json.dumps(bench_batched(500)), flush=True)
         return
@@ -431,17 +445,10 @@ def main():
     if args.workload == "links3d":
         for d in ("f32", "f64"):
             print(json.dumps(bench_links3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
+            torch.cuda.empty_cache()
         return
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3
-    if args.calibrate_copy:
-        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        torch.cuda.empty_cache()
     r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel)
     r64 = None
     if not args.no_fp64:

@@ -257,7 +257,8 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
 
 int kernel_choice(const dirac_ctx *c) {
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
-    if (c->links_on) return DIRAC_KERNEL_SPLIT;    // only the split kernels carry links
+    // links: the 3D z-march link kernel (one step per launch), else the split ones
+    if (c->links_on) return c->ndim == 3 ? DIRAC_KERNEL_FUSED : DIRAC_KERNEL_SPLIT;
     // the fused kernels address a plane with 32-bit byte offsets
     const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
     if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
@@ -295,7 +296,11 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
         }
     }
     for (; t < n; ++t) {
-        if (fused) {
+        if (fused && c->links_on) {
+            FusedArgs<R> a = fused_args<R>(c);
+            HIPCHK(c, launch_fused_links<R>(a, link_ptrs(c), site, s));
+            c->cur = 1 - c->cur;
+        } else if (fused) {
             FusedArgs<R> a = fused_args<R>(c);
             if (c->ndim == 3) HIPCHK(c, launch_fused3<R>(a, site, c->tile_y, s));
             else HIPCHK(c, launch_fused2<R>(a, site, s));
@@ -587,7 +592,7 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
     double *part = (double *)scratch_at(c, off_partial(c));
     const int cap = (kReduceBlocks * kObsVals) / 2;
     const int kc = kernel_choice(c);
-    if (c->ndim == 3 && kc == DIRAC_KERNEL_FUSED2 && n >= 2) {
+    if (c->ndim == 3 && kc == DIRAC_KERNEL_FUSED2 && n >= 2 && !c->links_on) {
         rc = dirac_step(c, n - 2, stream);
         if (rc) return rc;
         rc = upload_tables(c, s);
@@ -617,7 +622,7 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
         rc = dirac_step(c, n - 1, stream);
         if (rc) return rc;
     }
-    if (c->ndim == 3 && (kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2)) {
+    if (c->ndim == 3 && (kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2) && !c->links_on) {
         int nb = 0;
         hipError_t e;
         if (c->dtype == DIRAC_C64) {

@@ -11,11 +11,14 @@
 //   S_D0: +z B0 t-z, -z B0(zm) t+z, +x A0(xp) t-x, -x A0 t+x, +y A1 t-y, -y A1(ym) t+y
 //   S_D1: +z B1 t-z, -z B1(zm) t+z, +x A1 t-x, -x A1(xm) t+x, +y A0(yp) t-y, -y A0 t+y
 // The coupling stays anti-Hermitian, so E_r with the links in S_X is conserved
-// for a static potential.  These are cell-parallel kernels (split half-steps,
-// in place, and the E_r reduction); the fused kernels carry no links.
+// for a static potential.  Kernels: cell-parallel split half-steps (in place;
+// the reversed step, (2+1)D) and the E_r reductions, and a (3+1)D z-march that
+// does the whole step in one launch, reading every link factor once.  Both
+// build each C,D coupling through the same helpers: the same bits.
 #include "device.h"
 #include "internal.h"
 #include "stencil3.h"
+#include "march2.h"
 
 namespace dirac {
 
@@ -69,51 +72,82 @@ __device__ __forceinline__ Nb3 nb3(int i, int j, int k, int nx, int ny, int nz) 
     return n;
 }
 
-// S_X with links at cell n.c for the A,B arrays (from C,D) or C,D arrays (from A,B).
+// ---- (3+1)D ----
+// A,B rows with links, one row per array (u: that array's six link factors at
+// the cell, term order +z, -z, +x, -x, +y, -y; the C,D values as in stencil_ab).
+template <typename C, typename R>
+__device__ __forceinline__ C ab_row0(const C *u, C c0, C c0zm, C d0, C d0xm, C d1, C d1ym, R rx, R ry, R rz) {
+    return sterm3(rz, csub(cmul(u[TZP], c0), cmul(u[TZM], c0zm)), rx, csub(cmul(u[TXP], d0), cmul(u[TXM], d0xm)),
+                  -ry, csub(cmul(u[TYP], d1), cmul(u[TYM], d1ym)));
+}
+template <typename C, typename R>
+__device__ __forceinline__ C ab_row1(const C *u, C c1, C c1zm, C d1xp, C d1, C d0yp, C d0, R rx, R ry, R rz) {
+    return sterm3(rz, csub(cmul(u[TZP], c1), cmul(u[TZM], c1zm)), rx, csub(cmul(u[TXP], d1xp), cmul(u[TXM], d1)),
+                  -ry, csub(cmul(u[TYP], d0yp), cmul(u[TYM], d0)));
+}
+template <typename C, typename R>
+__device__ __forceinline__ C ab_row2(const C *u, C d0zp, C d0, C c0xp, C c0, C c1, C c1ym, R rx, R ry, R rz) {
+    return sterm3(-rz, csub(cmul(u[TZP], d0zp), cmul(u[TZM], d0)), rx, csub(cmul(u[TXP], c0xp), cmul(u[TXM], c0)),
+                  ry, csub(cmul(u[TYP], c1), cmul(u[TYM], c1ym)));
+}
+template <typename C, typename R>
+__device__ __forceinline__ C ab_row3(const C *u, C d1zp, C d1, C c1, C c1xm, C c0yp, C c0, R rx, R ry, R rz) {
+    return sterm3(-rz, csub(cmul(u[TZP], d1zp), cmul(u[TZM], d1)), rx, csub(cmul(u[TXP], c1), cmul(u[TXM], c1xm)),
+                  ry, csub(cmul(u[TYP], c0yp), cmul(u[TYM], c0)));
+}
+
+// One C,D coupling: the new A,B value x times the conjugate of its link factor u.
+template <typename C> __device__ __forceinline__ C pr(C u, C x) { return cmul(cconj(u), x); }
+
+// C,D rows from their 24 couplings T[6 q + term] (q = C0, C1, D0, D1; term
+// order +z, -z, +x, -x, +y, -y), each conj(U) times the new A,B value at the
+// neighbour (the table in the header comment):
+//   C0: A0(zp).-z  A0.+z  B0.-x  B0(xm).+x  B1.-y  B1(ym).+y
+//   C1: A1(zp).-z  A1.+z  B1(xp).-x  B1.+x  B0(yp).-y  B0.+y
+//   D0: B0.-z  B0(zm).+z  A0(xp).-x  A0.+x  A1.-y  A1(ym).+y
+//   D1: B1.-z  B1(zm).+z  A1.-x  A1(xm).+x  A0(yp).-y  A0.+y
+template <typename C, typename R> __device__ __forceinline__ St3<C> cd_rows(const C (&T)[24], R rx, R ry, R rz) {
+    St3<C> s;
+    s.s0 = sterm3(rz, csub(T[0], T[1]), rx, csub(T[2], T[3]), -ry, csub(T[4], T[5]));
+    s.s1 = sterm3(rz, csub(T[6], T[7]), rx, csub(T[8], T[9]), -ry, csub(T[10], T[11]));
+    s.s2 = sterm3(-rz, csub(T[12], T[13]), rx, csub(T[14], T[15]), ry, csub(T[16], T[17]));
+    s.s3 = sterm3(-rz, csub(T[18], T[19]), rx, csub(T[20], T[21]), ry, csub(T[22], T[23]));
+    return s;
+}
+
+// Cell-parallel forms (split half-steps, reductions): values loaded in the
+// compute type D (FV, LK above).
 template <typename D, typename RD, typename CS>
 __device__ __forceinline__ St3<D> links_ab(const CS *const f[8], const LinkPtrs &L, const Nb3 &n, RD rx, RD ry, RD rz) {
     constexpr int NT = 6;
+    D u[24];
+#pragma unroll
+    for (int q = 0; q < 24; ++q) u[q] = LK(q / 6, q % 6, n.c);
     St3<D> s;
-    // A0: +z C0, -z C0[k-1], +x D0, -x D0[i-1], +y D1, -y D1[j-1]
-    s.s0 = sterm3(rz, csub(cmul(LK(0, TZP, n.c), FV(4, n.c)), cmul(LK(0, TZM, n.c), FV(4, n.zm))),
-                  rx, csub(cmul(LK(0, TXP, n.c), FV(6, n.c)), cmul(LK(0, TXM, n.c), FV(6, n.xm))),
-                  -ry, csub(cmul(LK(0, TYP, n.c), FV(7, n.c)), cmul(LK(0, TYM, n.c), FV(7, n.ym))));
-    // A1: +z C1, -z C1[k-1], +x D1[i+1], -x D1, +y D0[j+1], -y D0
-    s.s1 = sterm3(rz, csub(cmul(LK(1, TZP, n.c), FV(5, n.c)), cmul(LK(1, TZM, n.c), FV(5, n.zm))),
-                  rx, csub(cmul(LK(1, TXP, n.c), FV(7, n.xp)), cmul(LK(1, TXM, n.c), FV(7, n.c))),
-                  -ry, csub(cmul(LK(1, TYP, n.c), FV(6, n.yp)), cmul(LK(1, TYM, n.c), FV(6, n.c))));
-    // B0: +z D0[k+1], -z D0, +x C0[i+1], -x C0, +y C1, -y C1[j-1]
-    s.s2 = sterm3(-rz, csub(cmul(LK(2, TZP, n.c), FV(6, n.zp)), cmul(LK(2, TZM, n.c), FV(6, n.c))),
-                  rx, csub(cmul(LK(2, TXP, n.c), FV(4, n.xp)), cmul(LK(2, TXM, n.c), FV(4, n.c))),
-                  ry, csub(cmul(LK(2, TYP, n.c), FV(5, n.c)), cmul(LK(2, TYM, n.c), FV(5, n.ym))));
-    // B1: +z D1[k+1], -z D1, +x C1, -x C1[i-1], +y C0[j+1], -y C0
-    s.s3 = sterm3(-rz, csub(cmul(LK(3, TZP, n.c), FV(7, n.zp)), cmul(LK(3, TZM, n.c), FV(7, n.c))),
-                  rx, csub(cmul(LK(3, TXP, n.c), FV(5, n.c)), cmul(LK(3, TXM, n.c), FV(5, n.xm))),
-                  ry, csub(cmul(LK(3, TYP, n.c), FV(4, n.yp)), cmul(LK(3, TYM, n.c), FV(4, n.c))));
+    s.s0 = ab_row0(u, FV(4, n.c), FV(4, n.zm), FV(6, n.c), FV(6, n.xm), FV(7, n.c), FV(7, n.ym), rx, ry, rz);
+    s.s1 = ab_row1(u + 6, FV(5, n.c), FV(5, n.zm), FV(7, n.xp), FV(7, n.c), FV(6, n.yp), FV(6, n.c), rx, ry, rz);
+    s.s2 = ab_row2(u + 12, FV(6, n.zp), FV(6, n.c), FV(4, n.xp), FV(4, n.c), FV(5, n.c), FV(5, n.ym), rx, ry, rz);
+    s.s3 = ab_row3(u + 18, FV(7, n.zp), FV(7, n.c), FV(5, n.c), FV(5, n.xm), FV(4, n.yp), FV(4, n.c), rx, ry, rz);
     return s;
 }
 
 template <typename D, typename RD, typename CS>
 __device__ __forceinline__ St3<D> links_cd(const CS *const f[8], const LinkPtrs &L, const Nb3 &n, RD rx, RD ry, RD rz) {
     constexpr int NT = 6;
-    St3<D> s;
-    // C0: +z A0[k+1], -z A0, +x B0, -x B0[i-1], +y B1, -y B1[j-1]
-    s.s0 = sterm3(rz, csub(cmul(LKC(0, TZM, n.zp), FV(0, n.zp)), cmul(LKC(0, TZP, n.c), FV(0, n.c))),
-                  rx, csub(cmul(LKC(2, TXM, n.c), FV(2, n.c)), cmul(LKC(2, TXP, n.xm), FV(2, n.xm))),
-                  -ry, csub(cmul(LKC(3, TYM, n.c), FV(3, n.c)), cmul(LKC(3, TYP, n.ym), FV(3, n.ym))));
-    // C1: +z A1[k+1], -z A1, +x B1[i+1], -x B1, +y B0[j+1], -y B0
-    s.s1 = sterm3(rz, csub(cmul(LKC(1, TZM, n.zp), FV(1, n.zp)), cmul(LKC(1, TZP, n.c), FV(1, n.c))),
-                  rx, csub(cmul(LKC(3, TXM, n.xp), FV(3, n.xp)), cmul(LKC(3, TXP, n.c), FV(3, n.c))),
-                  -ry, csub(cmul(LKC(2, TYM, n.yp), FV(2, n.yp)), cmul(LKC(2, TYP, n.c), FV(2, n.c))));
-    // D0: +z B0, -z B0[k-1], +x A0[i+1], -x A0, +y A1, -y A1[j-1]
-    s.s2 = sterm3(-rz, csub(cmul(LKC(2, TZM, n.c), FV(2, n.c)), cmul(LKC(2, TZP, n.zm), FV(2, n.zm))),
-                  rx, csub(cmul(LKC(0, TXM, n.xp), FV(0, n.xp)), cmul(LKC(0, TXP, n.c), FV(0, n.c))),
-                  ry, csub(cmul(LKC(1, TYM, n.c), FV(1, n.c)), cmul(LKC(1, TYP, n.ym), FV(1, n.ym))));
-    // D1: +z B1, -z B1[k-1], +x A1, -x A1[i-1], +y A0[j+1], -y A0
-    s.s3 = sterm3(-rz, csub(cmul(LKC(3, TZM, n.c), FV(3, n.c)), cmul(LKC(3, TZP, n.zm), FV(3, n.zm))),
-                  rx, csub(cmul(LKC(1, TXM, n.c), FV(1, n.c)), cmul(LKC(1, TXP, n.xm), FV(1, n.xm))),
-                  ry, csub(cmul(LKC(0, TYM, n.yp), FV(0, n.yp)), cmul(LKC(0, TYP, n.c), FV(0, n.c))));
-    return s;
+    const D T[24] = {
+        pr(LK(0, TZM, n.zp), FV(0, n.zp)), pr(LK(0, TZP, n.c), FV(0, n.c)),
+        pr(LK(2, TXM, n.c), FV(2, n.c)), pr(LK(2, TXP, n.xm), FV(2, n.xm)),
+        pr(LK(3, TYM, n.c), FV(3, n.c)), pr(LK(3, TYP, n.ym), FV(3, n.ym)),
+        pr(LK(1, TZM, n.zp), FV(1, n.zp)), pr(LK(1, TZP, n.c), FV(1, n.c)),
+        pr(LK(3, TXM, n.xp), FV(3, n.xp)), pr(LK(3, TXP, n.c), FV(3, n.c)),
+        pr(LK(2, TYM, n.yp), FV(2, n.yp)), pr(LK(2, TYP, n.c), FV(2, n.c)),
+        pr(LK(2, TZM, n.c), FV(2, n.c)), pr(LK(2, TZP, n.zm), FV(2, n.zm)),
+        pr(LK(0, TXM, n.xp), FV(0, n.xp)), pr(LK(0, TXP, n.c), FV(0, n.c)),
+        pr(LK(1, TYM, n.c), FV(1, n.c)), pr(LK(1, TYP, n.ym), FV(1, n.ym)),
+        pr(LK(3, TZM, n.c), FV(3, n.c)), pr(LK(3, TZP, n.zm), FV(3, n.zm)),
+        pr(LK(1, TXM, n.c), FV(1, n.c)), pr(LK(1, TXP, n.xm), FV(1, n.xm)),
+        pr(LK(0, TYM, n.yp), FV(0, n.yp)), pr(LK(0, TYP, n.c), FV(0, n.c))};
+    return cd_rows(T, rx, ry, rz);
 }
 
 // which == 0: A,B from C,D (Eqs. ss1, ss2); 1: C,D from A,B (ss3, ss4); in place.
@@ -146,6 +180,238 @@ __global__ __launch_bounds__(256) void k3_half_links(HalfArgs<R> a, LinkPtrs L) 
         f[5][n.c] = update(f[5][n.c], s.s1, gcoef<R, SITE>(a, 5, 2, k, n.c));
         f[6][n.c] = update(f[6][n.c], s.s2, gcoef<R, SITE>(a, 6, 3, k, n.c));
         f[7][n.c] = update(f[7][n.c], s.s3, gcoef<R, SITE>(a, 7, 3, k, n.c));
+    }
+}
+
+// One step per launch with links, marching along z (ping-pong in -> out).
+// A workgroup owns a 64 x TY tile and a chunk [z0, z1) of planes; at plane p it
+// computes the new A,B(p) on the tile and on the one-cell ring around it (not
+// the corners), then the new C,D(p-1) on the tile.  Each of a cell's 24 C,D
+// couplings pr(U, new A,B) is formed once, by the thread that updated the A,B
+// end, right after that update, with the link factors it has just loaded for
+// it: 12 serve the cell's own C,D rows (kept in registers one plane), 2 the
+// C,D rows one plane below (this plane's C,D(p-1)), 2 the rows one plane above
+// (kept two planes), and 8 the x-y neighbours' rows, through LDS.  So every
+// link factor and every amplitude is read once per step (the ring's recompute
+// and cache-served neighbour reads aside), where the split form reads the
+// links twice.  Same helpers and operation order as the split kernels: the
+// same bits.  Thread layout: 64 TY tile threads (wave y = tile row y), then
+// the ring (left and right columns, bottom and top rows), the rest idle.
+template <int TW, int TY> constexpr int fl_threads() { return TW * TY + 64 * ((2 * TW + 2 * TY + 63) / 64); }
+
+template <typename R, bool SITE, int TW, int TY, int WPE>
+__global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(FusedArgs<R> a, LinkPtrs L) {
+    using C = cx<R>;
+    constexpr int LW = TW + 2, LN = LW * (TY + 2);
+    __shared__ C sE[2][8][LN];      // exports of A,B(p), slot p & 1
+
+    int lb = blockIdx.x;
+    if ((gridDim.x & 7) == 0) lb = (lb & 7) * (gridDim.x >> 3) + (lb >> 3);   // one run of tiles per XCD
+    const int tx = lb % a.ntx;
+    lb /= a.ntx;
+    const int ty = lb % a.nty;
+    const int zc = lb / a.nty;
+    const int x0 = tx * TW, y0 = ty * TY;
+    const int w = min(TW, a.nx - x0), h = min(TY, a.ny - y0);
+    const int z0 = zc * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
+    const int t = threadIdx.x;
+    // rows this cell updates: all four on the tile; on the ring only the two
+    // whose couplings point into the tile (left: A1, B0; right: A0, B1; bottom:
+    // A1, B1; top: A0, B0)
+    int x = 0, y = 0;
+    bool tile = false, act = false, nA0 = false, nA1 = false, nB0 = false, nB1 = false;
+    if (t < TW * TY) {
+        x = t % TW;
+        y = t / TW;
+        tile = act = nA0 = nA1 = nB0 = nB1 = x < w && y < h;
+    } else {
+        const int r = t - TW * TY;
+        act = true;
+        if (r < h) { x = -1; y = r; nA1 = nB0 = true; }
+        else if (r < 2 * h) { x = w; y = r - h; nA0 = nB1 = true; }
+        else if (r < 2 * h + w) { x = r - 2 * h; y = -1; nA1 = nB1 = true; }
+        else if (r < 2 * h + 2 * w) { x = r - 2 * h - w; y = h; nA0 = nB0 = true; }
+        else { act = false; }
+    }
+    const int gx = wrapn(x0 + x, a.nx), gy = wrapn(y0 + y, a.ny);
+    const size_t row = (size_t)gy * a.nx;
+    const size_t c2 = row + gx;
+    const size_t xm2 = row + wrap_dec(gx, a.nx), xp2 = row + wrap_inc(gx, a.nx);
+    const size_t ym2 = (size_t)wrap_dec(gy, a.ny) * a.nx + gx, yp2 = (size_t)wrap_inc(gy, a.ny) * a.nx + gx;
+    const int li = act ? (y + 1) * LW + (x + 1) : 0;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const C *in[8];
+    C *out[8];
+    const C *lk[24];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        in[q] = (const C *)a.in[q];
+        out[q] = (C *)a.out[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 24; ++q) lk[q] = (const C *)L.u[q];
+    const R rx = a.rx, ry = a.ry, rz = a.rz;
+    const C zero = mk2((R)0, (R)0);
+    auto coef = [&](int arr, int cls, int pk, size_t idx) -> Coef<R> {
+        if constexpr (SITE) {
+            return coef_site_at<R>(a.th[arr], idx, (R)1);
+        } else {
+            const R *e = a.tab + ((size_t)cls * a.nz + pk) * 4;
+            Coef<R> k;
+            k.c1 = mk2(e[0], e[1]);
+            k.c2 = mk2(e[2], e[3]);
+            return k;
+        }
+    };
+
+    // carried along the march: old C(p-1), D(p), D(p-1) at the cell; the own
+    // couplings of A,B(p-1); the upward couplings of A,B(p-1) and A,B(p-2)
+    C cm0 = zero, cm1 = zero, dc0 = zero, dc1 = zero, dm0 = zero, dm1 = zero;
+    C Q[12], zm1[2] = {zero, zero}, zm2[2] = {zero, zero};
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Q[q] = zero;
+    if (act) {
+        const size_t Pc = (size_t)wrapn(z0 - 2, a.nz) * plane, Pd = (size_t)wrapn(z0 - 1, a.nz) * plane;
+        cm0 = in[4][Pc + c2];
+        cm1 = in[5][Pc + c2];
+        dc0 = in[6][Pd + c2];
+        dc1 = in[7][Pd + c2];
+    }
+
+    for (int p = z0 - 1; p <= z1; ++p) {
+        const int pk = wrapn(p, a.nz);
+        const size_t P = (size_t)pk * plane, Pn = (size_t)wrapn(p + 1, a.nz) * plane;
+        C E[8], Qn[12], zpn[2], zmn[2], cc0 = zero, cc1 = zero, dn0 = zero, dn1 = zero;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) E[q] = zero;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) Qn[q] = zero;
+        zpn[0] = zpn[1] = zmn[0] = zmn[1] = zero;
+        if (act) {
+            const size_t ci = P + c2;
+            const bool store = tile && p >= z0 && p < z1;
+            C u[24], xo[4], nb[8];
+#pragma unroll
+            for (int q = 0; q < 24; ++q) u[q] = zero;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) nb[q] = zero;
+            xo[0] = xo[1] = xo[2] = xo[3] = zero;
+            cc0 = in[4][ci];
+            cc1 = in[5][ci];
+            dn0 = in[6][Pn + c2];
+            dn1 = in[7][Pn + c2];
+            auto ld0 = [&]() {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[q] = lk[q][ci];
+                xo[0] = in[0][ci];
+                nb[0] = in[6][P + xm2];
+                nb[1] = in[7][P + ym2];
+            };
+            auto ld1 = [&]() {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[6 + q] = lk[6 + q][ci];
+                xo[1] = in[1][ci];
+                nb[2] = in[7][P + xp2];
+                nb[3] = in[6][P + yp2];
+            };
+            auto ld2 = [&]() {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[12 + q] = lk[12 + q][ci];
+                xo[2] = in[2][ci];
+                nb[4] = in[4][P + xp2];
+                nb[5] = in[5][P + ym2];
+            };
+            auto ld3 = [&]() {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[18 + q] = lk[18 + q][ci];
+                xo[3] = in[3][ci];
+                nb[6] = in[5][P + xm2];
+                nb[7] = in[4][P + yp2];
+            };
+            if (nA0) {
+                ld0();
+                const C na0 = update(xo[0], ab_row0(u, cc0, cm0, dc0, nb[0], dc1, nb[1], rx, ry, rz), coef(0, 0, pk, ci));
+                if (store) out[0][ci] = na0;
+                E[3] = pr(u[TXM], na0);
+                E[7] = pr(u[TYM], na0);
+                Qn[0] = pr(u[TZP], na0);
+                Qn[7] = pr(u[TXP], na0);
+                Qn[11] = pr(u[TYP], na0);
+                zpn[0] = pr(u[TZM], na0);
+            }
+            if (nA1) {
+                ld1();
+                const C *v = u + 6;
+                const C na1 = update(xo[1], ab_row1(v, cc1, cm1, nb[2], dc1, nb[3], dc0, rx, ry, rz), coef(1, 0, pk, ci));
+                if (store) out[1][ci] = na1;
+                E[1] = pr(v[TXP], na1);
+                E[5] = pr(v[TYP], na1);
+                Qn[3] = pr(v[TZP], na1);
+                Qn[8] = pr(v[TYM], na1);
+                Qn[10] = pr(v[TXM], na1);
+                zpn[1] = pr(v[TZM], na1);
+            }
+            if (nB0) {
+                ld2();
+                const C *v = u + 12;
+                const C nb0 = update(xo[2], ab_row2(v, dn0, dc0, nb[4], cc0, cc1, nb[5], rx, ry, rz), coef(2, 1, pk, ci));
+                if (store) out[2][ci] = nb0;
+                E[0] = pr(v[TXP], nb0);
+                E[6] = pr(v[TYM], nb0);
+                Qn[1] = pr(v[TXM], nb0);
+                Qn[5] = pr(v[TYP], nb0);
+                Qn[6] = pr(v[TZM], nb0);
+                zmn[0] = pr(v[TZP], nb0);
+            }
+            if (nB1) {
+                ld3();
+                const C *v = u + 18;
+                const C nb1 = update(xo[3], ab_row3(v, dn1, dc1, cc1, nb[6], nb[7], cc0, rx, ry, rz), coef(3, 1, pk, ci));
+                if (store) out[3][ci] = nb1;
+                E[2] = pr(v[TXM], nb1);
+                E[4] = pr(v[TYP], nb1);
+                Qn[2] = pr(v[TYM], nb1);
+                Qn[4] = pr(v[TXP], nb1);
+                Qn[9] = pr(v[TZM], nb1);
+                zmn[1] = pr(v[TZP], nb1);
+            }
+        }
+        // C,D of plane p-1 on the tile, from the couplings of A,B(p-1) (LDS and
+        // registers), A,B(p) (this plane) and A,B(p-2)
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sE[p & 1][q][li] = E[q];
+        }
+        if (tile && p - 1 >= z0 && p - 1 < z1) {
+            const int pm = wrapn(p - 1, a.nz);
+            const size_t cm = (size_t)pm * plane + c2;
+            const C(*e)[LN] = sE[(p - 1) & 1];
+            const C T[24] = {zpn[0], Q[0], Q[1], e[0][li - 1], Q[2], e[4][li - LW],
+                             zpn[1], Q[3], e[2][li + 1], Q[4], e[6][li + LW], Q[5],
+                             Q[6], zm2[0], e[3][li + 1], Q[7], Q[8], e[5][li - LW],
+                             Q[9], zm2[1], Q[10], e[1][li - 1], e[7][li + LW], Q[11]};
+            const St3<C> s = cd_rows(T, rx, ry, rz);
+            out[4][cm] = update(cm0, s.s0, coef(4, 2, pm, cm));
+            out[5][cm] = update(cm1, s.s1, coef(5, 2, pm, cm));
+            out[6][cm] = update(dm0, s.s2, coef(6, 3, pm, cm));
+            out[7][cm] = update(dm1, s.s3, coef(7, 3, pm, cm));
+        }
+        // one barrier per plane: the exports of A,B(p) (slot p & 1) are visible to
+        // the next plane's C,D, and this plane's reads of slot (p - 1) & 1 are done
+        // before the next plane overwrites it
+        __syncthreads();
+        cm0 = cc0;
+        cm1 = cc1;
+        dm0 = dc0;
+        dm1 = dc1;
+        dc0 = dn0;
+        dc1 = dn1;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) Q[q] = Qn[q];
+        zm2[0] = zm1[0];
+        zm2[1] = zm1[1];
+        zm1[0] = zmn[0];
+        zm1[1] = zmn[1];
     }
 }
 
@@ -321,6 +587,31 @@ hipError_t launch_half_links(const HalfArgs<R> &a, const LinkPtrs &L, int ndim, 
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_fused_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool site, hipStream_t s) {
+    FusedArgs<R> a = a0;
+    // tiles 32 x 16 (complex64, 640 threads) or 32 x 8 (complex128, 384 threads:
+    // registers without spilling); tall tiles keep the recomputed ring small
+    constexpr int TW = 32, TY = sizeof(R) == 4 ? 16 : 8;
+    a.ntx = (a.nx + TW - 1) / TW;
+    a.nty = (a.ny + TY - 1) / TY;
+    const int64_t tiles = (int64_t)a.ntx * a.nty;
+    if (a.zchunk <= 0) {
+        int64_t nzc = (1024 + tiles - 1) / tiles;
+        if (nzc < 1) nzc = 1;
+        if (nzc > a.nz) nzc = a.nz;
+        a.zchunk = (int)((a.nz + nzc - 1) / nzc);
+    }
+    a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
+    const int64_t nblk = tiles * a.nzc;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g((unsigned)nblk), b(fl_threads<TW, TY>());
+    constexpr int WPE = sizeof(R) == 4 ? 3 : 2;
+    if (site) hipLaunchKernelGGL((k3_fused_links<R, true, TW, TY, WPE>), g, b, 0, s, a, L);
+    else hipLaunchKernelGGL((k3_fused_links<R, false, TW, TY, WPE>), g, b, 0, s, a, L);
+    return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const LinkPtrs &L, int ndim, hipStream_t s) {
     if (ndim == 3) hipLaunchKernelGGL((k3_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
     else hipLaunchKernelGGL((k2_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
@@ -329,6 +620,8 @@ template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const
 
 template hipError_t launch_half_links<float>(const HalfArgs<float> &, const LinkPtrs &, int, int, bool, hipStream_t);
 template hipError_t launch_half_links<double>(const HalfArgs<double> &, const LinkPtrs &, int, int, bool, hipStream_t);
+template hipError_t launch_fused_links<float>(const FusedArgs<float> &, const LinkPtrs &, bool, hipStream_t);
+template hipError_t launch_fused_links<double>(const FusedArgs<double> &, const LinkPtrs &, bool, hipStream_t);
 template hipError_t launch_norm_links<float>(const ReduceArgs<float> &, const LinkPtrs &, int, hipStream_t);
 template hipError_t launch_norm_links<double>(const ReduceArgs<double> &, const LinkPtrs &, int, hipStream_t);
 

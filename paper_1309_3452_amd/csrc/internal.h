@@ -103,6 +103,9 @@ template <typename R> hipError_t launch_half_links(const HalfArgs<R> &a, const L
                                                    bool site, hipStream_t s);
 template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const LinkPtrs &L, int ndim,
                                                    hipStream_t s);
+// 3D one step per launch with links, z-march, ping-pong in -> out (gauge.hip).
+template <typename R> hipError_t launch_fused_links(const FusedArgs<R> &a, const LinkPtrs &L, bool site,
+                                                    hipStream_t s);
 
 // Adjoint (adjoint.hip)
 template <typename R> hipError_t launch_adj3(const AdjArgs<R> &a, int sweep, hipStream_t s);

@@ -776,3 +776,35 @@ def test_links_reverse_and_step_norm(P, dim):
             lat.adjoint_vz(1, lat.seed_region(nz / 2.0))
     lat.set_links(None)
     lat.step(1)          # plain kernels again
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("site", [False, True])
+@pytest.mark.parametrize("shape,zchunk,steps", [((70, 20, 22), 0, 5), ((130, 9, 5), 2, 4), ((3, 2, 4), 0, 3),
+                                                 ((64, 8, 16), 5, 4), ((1, 1, 3), 0, 2), ((65, 9, 7), 3, 3)])
+def test_fused_links_bitwise_equals_split(P, dtype, site, shape, zchunk, steps):
+    """The z-march link kernel (one launch per step) gives the bits of the split
+    link kernels: ragged tiles, chunk boundaries, lattices smaller than the ring."""
+    from closed_form import links_from_potential3, smooth_potential3
+    nx, ny, nz = shape
+    print("fused links %s %s site=%s zchunk=%d" % (shape, dtype, site, zchunk), flush=True)
+    tsh = (nz, ny, nx)
+    U = _links_t(links_from_potential3(tsh, smooth_potential3(tsh, 0.6, 221)))
+    f0 = rand_state(tsh, 8, 222)
+    g = np.random.default_rng(223)
+    V = [torch.from_numpy(np.ascontiguousarray(0.4 * g.standard_normal(tsh))) for _ in range(8)]
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    out = []
+    for kind in ("split", "fused"):
+        lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+        lat.set_kernel(kind, 0, zchunk)
+        if site:
+            lat.set_fields(0.3, V)
+        else:
+            lat.set_potential_z(0.3, v_int, v_half)
+        lat.set_links(U)
+        lat.load(f0)
+        lat.step(steps)
+        out.append([t.clone() for t in lat.state()])
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
