@@ -590,9 +590,10 @@ hipError_t launch_half_links(const HalfArgs<R> &a, const LinkPtrs &L, int ndim, 
 template <typename R>
 hipError_t launch_fused_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool site, hipStream_t s) {
     FusedArgs<R> a = a0;
-    // tiles 32 x 16 (complex64, 640 threads) or 32 x 8 (complex128, 384 threads:
-    // registers without spilling); tall tiles keep the recomputed ring small
-    constexpr int TW = 32, TY = sizeof(R) == 4 ? 16 : 8;
+    // tiles 64 x 8 (complex64, 704 threads) or 32 x 8 (complex128, 384 threads:
+    // registers without spilling); measured best of 64x8, 32x16 (complex64) and
+    // 64x4, 32x8 (complex128) at 512^3
+    constexpr int TW = sizeof(R) == 4 ? 64 : 32, TY = 8;
     a.ntx = (a.nx + TW - 1) / TW;
     a.nty = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)a.ntx * a.nty;
