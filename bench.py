@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
-                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "klein2d"],
+                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "klein2d", "slab3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -133,6 +133,29 @@ def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel):
     return out
 
 
+def copy_ceiling_gbs(nbytes=4 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) of a plain copy of
+    nbytes, the practical HBM ceiling the stencil kernels are compared with."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = _timed(lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline():
     import numpy as np
 
@@ -148,6 +171,7 @@ def cpu_baseline():
     ol.step(f, th, nsteps)
     dt = time.perf_counter() - t0
     return {"value": n ** 3 * nsteps / dt, "unit": "site-updates/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "FP64 C oracle, same physics on a %d^3 lattice, %d steps (%.1f s); "
                       "site-updates/s is per cell-step, independent of lattice size" % (n, nsteps, dt)}
 
@@ -382,6 +406,59 @@ def bench_klein2d(phi_deg):
                         "refraction_angle_deg": angle}}
 
 
+def bench_slab3d(steps):
+    """One device's share of the 512^3 headline lattice split into 8 z-slabs: a
+    512 x 512 x 64 slab (complex64) with two halo planes per side, stepped by the
+    one-step kernel, halos filled before every step (here from the slab's own
+    opposite boundary: a one-slab decomposition, the same bytes a device would
+    receive from its neighbours)."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    n, nzs = 512, 64
+    v_int, v_half = workloads.step_potential(nzs, 1.5, nzs / 2.0, 4.0)
+    st = workloads.packet3d(n, n, nzs, (n / 2.0, n / 2.0, nzs / 2.0), 12.0, (0.0, 0.0, 0.56), 0.5, workloads.DT3,
+                            dtype=torch.complex64, device="cuda")
+    sl = P.SlabDecomposition(n, n, nzs, 1, dtype=torch.complex64, dt=workloads.DT3)
+    sl.set_potential_z(0.5, v_int, v_half)
+    sl.load(st)
+    del st
+    torch.cuda.empty_cache()
+    e0 = sl.norm()
+    sl.step(2)
+    lat = sl.parts[0]
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for q in range(steps):
+        ev[q][0].record(stream)
+        lat.step(1)
+        ev[q][1].record(stream)
+        sl.exchange()
+        ev[q][2].record(stream)
+    torch.cuda.synchronize()
+    k_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    x_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    e1 = sl.norm()
+    cells = n * n * nzs
+    plane = n * n * 8
+    alg = 128.0 * cells
+    return {"metric": "site-updates/s of one device's z-slab (512x512x64 of a 512^3 lattice over 8 devices), complex64",
+            "value": cells / ((k_ms + x_ms) * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
+            "warmup": 2, "ms_per_step": k_ms + x_ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "(3+1)D z-slab 512x512x64 + 2 halo planes per side, headline physics, "
+                                   "one-step kernel, halo fill on the device", "cells": cells},
+            "slab_kernel_ms_per_step": k_ms, "halo_fill_ms_per_step": x_ms,
+            "roofline": {"bound": "hbm", "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k3_fused<float> in z-slab mode"},
+            "halo": {"bytes_per_face_filled": 8 * 2 * plane, "bytes_per_face_read_by_kernel": 10 * plane,
+                     "xgmi_link_GBs": 153.0, "modeled_link_ms_per_face": 10 * plane / 153e9 * 1e3},
+            "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
+
+
 def bench_plane2d(steps):
     """(2+1)D 128^2, complex128, 200 steps: launch-bound; plain launches vs one captured graph."""
     import torch
@@ -438,6 +515,9 @@ def main():
     if args.workload == "plane2d":
         print(json.dumps(bench_plane2d(200)), flush=True)
         return
+    if args.workload == "slab3d":
+        print(json.dumps(bench_slab3d(200)), flush=True)
+        return
     if args.workload == "klein2d":
         for phi in (0.0, 37.0):
             print(json.dumps(bench_klein2d(phi)), flush=True)
@@ -460,6 +540,7 @@ def main():
     alg_bytes = 128.0 * cells * G
     achieved = alg_bytes / (r32["launch_ms"] * 1e-3) / 1e9
     traffic = profiled_traffic("fp32", n, G)
+    copy_gbs = copy_ceiling_gbs()
     kname = "k3_fused2<float> (two steps per launch" if G == 2 else "k3_fused<float> (one step per launch"
     line = {
         "metric": "site-updates/s & HBM-roofline %, FP32 vs FP64 3+1D 512^3 at stated norm error",
@@ -486,7 +567,8 @@ def main():
                      "steps_per_launch": G,
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": r32["launch_ms"],
-                     "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None},
+                     "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "copy_ceiling_GBs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs},
         "norm_error": {"E_r_rel_drift_fp32": r32["drift"], "E_r_rel_drift_fp32_max_every10": r32["drift_max"],
                        "steps_total": r32["steps_total"], "plain_norm_rel_change": r32["plain_norm_change"]},
         "amplitude_updates_per_s": 8 * value,

@@ -59,6 +59,21 @@ enum dirac_status {
 
 /* dirac_create flags */
 #define DIRAC_ALLOW_UNSTABLE 1u
+/*
+ * z-slab mode (3D): the context is one z-slab of a larger lattice, the unit a
+ * multi-GPU run gives each device (the paper's closing remark on splitting
+ * space into sub-domains that trade boundary values).  Every bound array
+ * (state, per-site fields) holds nz + 4 planes: two halo planes below, the nz
+ * interior planes, two halo planes above; V(z) tables take nz + 4 entries, one
+ * per stored plane.  z is not periodic: a step reads the halo planes and writes
+ * the interior only, so before each step the caller fills the halos of the
+ * current buffer set with the neighbouring slabs' outermost two interior planes
+ * (all 8 arrays).  Steps use the one-step fused kernel (the state moves to the
+ * other buffer set each step); dirac_step_norm and dirac_norm sum the interior
+ * (slab sums add up to the whole lattice's).  dirac_reverse, dirac_observables,
+ * dirac_seed_region, dirac_adjoint_vz and links are refused (DIRAC_E_STATE).
+ */
+#define DIRAC_SLAB_Z 2u
 
 /* step kernels (dirac_set_kernel) */
 enum dirac_kernel {
@@ -81,7 +96,8 @@ const char *dirac_status_string(int status);
  *          or DIRAC_C128 (FP64 throughout).
  *   dt     time step (Delta_o = dt); dx, dy, dz > 0 grid spacings.
  *   flags  DIRAC_ALLOW_UNSTABLE to accept sum r_j^2 > 1 (the scheme then
- *          grows, Sect. 2.2 and Sect. 3 "reality condition").
+ *          grows, Sect. 2.2 and Sect. 3 "reality condition"); DIRAC_SLAB_Z
+ *          (ndim == 3) for z-slab mode, nz then counting interior planes.
  * Validates the stability bound sum_j r_j^2 <= 1 of Sect. 2.2 (3D) / Sect. 3
  * (2D).  The context starts with m = 0, V = 0.  Makes no HIP call.
  */

@@ -10,6 +10,7 @@ from ._abi import DiracError, lib  # noqa: F401
 from .lattice import Lattice, Lattice2D, Lattice3D  # noqa: F401
 from .batch import BatchedLattices  # noqa: F401
 from .autograd import DiracLoss, potential_gradient  # noqa: F401
+from .slabs import SlabDecomposition  # noqa: F401
 
 __all__ = ["Lattice", "Lattice2D", "Lattice3D", "BatchedLattices", "DiracLoss", "potential_gradient",
-           "DiracError", "lib"]
+           "SlabDecomposition", "DiracError", "lib"]

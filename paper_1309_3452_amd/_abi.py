@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libdirac.so")
 DIRAC_C64 = 1
 DIRAC_C128 = 2
 DIRAC_ALLOW_UNSTABLE = 1
+DIRAC_SLAB_Z = 2
 DIRAC_KERNEL_AUTO, DIRAC_KERNEL_SPLIT, DIRAC_KERNEL_FUSED, DIRAC_KERNEL_FUSED2 = 0, 1, 2, 3
 STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SHAPE", -3: "DIRAC_E_UNSTABLE",
           -4: "DIRAC_E_NONFINITE", -5: "DIRAC_E_HIP", -6: "DIRAC_E_STATE"}

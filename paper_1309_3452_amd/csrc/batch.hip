@@ -127,6 +127,9 @@ __device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity,
     a.nzc = 0;
     a.ntx = 0;
     a.nty = 1;
+    a.npart = nullptr;
+    a.npart_cap = 0;
+    a.zh = 0;
     return a;
 }
 

@@ -14,6 +14,7 @@ struct dirac_ctx {
     int dtype = 2;
     double dt = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
     unsigned flags = 0;
+    int zh = 0;               // z-slab mode: halo planes per side (arrays hold nz + 2 zh planes)
     std::string err;
 
     // state: two caller-owned buffer sets; cur says which holds the state

@@ -144,6 +144,10 @@ void cayley32c(double th, double thi, float out[4]) {
     out[3] = (float)c[3];
 }
 
+// Planes of the V(z) tables and per-site fields: the interior plus, in z-slab
+// mode, the halo planes on both sides.
+int64_t planes_of(const dirac_ctx *c) { return c->nz + 2 * c->zh; }
+
 // theta of class q (A, B, C, D) at plane k: (dt/2)(+-m + V at the class's z).
 double theta_of(const dirac_ctx *c, int q, int64_t k) {
     double h = 0.5 * c->dt;
@@ -158,7 +162,7 @@ double theta_im_of(const dirac_ctx *c, int q, int64_t k) {
     return 0.5 * c->dt * ((q == 0 || q == 3) ? c->w_int[k] : c->w_half[k]);
 }
 
-template <typename R> size_t tab_bytes(const dirac_ctx *c) { return (size_t)4 * c->nz * 4 * sizeof(R); }
+template <typename R> size_t tab_bytes(const dirac_ctx *c) { return (size_t)4 * planes_of(c) * 4 * sizeof(R); }
 
 size_t tab_bytes_of(const dirac_ctx *c) {
     return c->dtype == DIRAC_C64 ? tab_bytes<float>(c) : tab_bytes<double>(c);
@@ -180,7 +184,7 @@ char *scratch_at(const dirac_ctx *c, size_t off) { return (char *)c->scratch + o
 int upload_tables(dirac_ctx *c, hipStream_t s) {
     if (!c->tab_dirty) return DIRAC_OK;
     if (!c->scratch) return fail(c, DIRAC_E_STATE, "scratch must be bound before stepping");
-    const int64_t nz = c->nz;
+    const int64_t nz = planes_of(c);
     if (c->dtype == DIRAC_C128) {
         c->tab_host64.assign((size_t)2 * 4 * nz * 4, 0.0);
         for (int dir = 0; dir < 2; ++dir)
@@ -252,10 +256,12 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
     a.ny = (int)c->ny;
     a.nz = (int)c->nz;
     a.zchunk = c->zchunk;
+    a.zh = c->zh;
     return a;
 }
 
 int kernel_choice(const dirac_ctx *c) {
+    if (c->zh) return DIRAC_KERNEL_FUSED;          // z-slab mode: the one-step march only
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
     // links: the 3D z-march link kernel (one step per launch), else the split ones
     if (c->links_on) return c->ndim == 3 ? DIRAC_KERNEL_FUSED : DIRAC_KERNEL_SPLIT;
@@ -337,6 +343,7 @@ template <typename R> ReduceArgs<R> reduce_args(dirac_ctx *c, double z0) {
     a.nz = (int)c->nz;
     a.z0 = z0;
     a.partial = (double *)scratch_at(c, off_partial(c));
+    a.zh = c->zh;
     return a;
 }
 
@@ -374,7 +381,8 @@ int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, 
     *out = nullptr;
     if (ndim != 2 && ndim != 3) return DIRAC_E_ARG;
     if (dtype != DIRAC_C64 && dtype != DIRAC_C128) return DIRAC_E_ARG;
-    if ((flags & ~DIRAC_ALLOW_UNSTABLE) != 0) return DIRAC_E_ARG;
+    if ((flags & ~(DIRAC_ALLOW_UNSTABLE | DIRAC_SLAB_Z)) != 0) return DIRAC_E_ARG;
+    if ((flags & DIRAC_SLAB_Z) && ndim != 3) return DIRAC_E_ARG;
     if (nx < 1 || ny < 1 || nz < 1) return DIRAC_E_SHAPE;
     if (ndim == 2 && nz != 1) return DIRAC_E_SHAPE;
     if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return DIRAC_E_SHAPE;
@@ -395,6 +403,7 @@ int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, 
     c->ry = ry;
     c->rz = rz;
     c->flags = flags;
+    c->zh = (flags & DIRAC_SLAB_Z) ? 2 : 0;
     *out = c;
     return DIRAC_OK;
 }
@@ -455,7 +464,8 @@ int dirac_bind_scratch(dirac_ctx *c, void *dev, size_t bytes) {
 int dirac_set_potential_im_z(dirac_ctx *c, const double *w_int, const double *w_half, int64_t nz) {
     if (!c) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
-    if (nz != c->nz) return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice nz %lld", (long long)nz, (long long)c->nz);
+    if (nz != planes_of(c))
+        return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice planes %lld", (long long)nz, (long long)planes_of(c));
     if ((w_int == nullptr) != (w_half == nullptr)) return fail(c, DIRAC_E_ARG, "w_int and w_half: both or neither");
     std::vector<double> wi, wh;
     if (w_int) {
@@ -481,7 +491,8 @@ int dirac_set_potential_im_z(dirac_ctx *c, const double *w_int, const double *w_
 int dirac_set_mass_potential_z(dirac_ctx *c, double m, const double *v_int, const double *v_half, int64_t nz) {
     if (!c || !isfinite(m)) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
-    if (nz != c->nz) return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice nz %lld", (long long)nz, (long long)c->nz);
+    if (nz != planes_of(c))
+        return fail(c, DIRAC_E_SHAPE, "nz %lld != lattice planes %lld", (long long)nz, (long long)planes_of(c));
     if ((v_int == nullptr) != (v_half == nullptr)) return fail(c, DIRAC_E_ARG, "v_int and v_half: both or neither");
     if (v_int && c->ndim == 2) return fail(c, DIRAC_E_ARG, "2D: use dirac_theta_from_fields for V(x, y)");
     std::vector<double> vi, vh;
@@ -514,6 +525,7 @@ int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
 int dirac_set_links(dirac_ctx *c, void *const links[]) {
     if (!c) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
+    if (c->zh && links) return fail(c, DIRAC_E_STATE, "links are not available in z-slab mode");
     for (int q = 0; q < 24; ++q) c->links[q] = nullptr;
     c->links_on = false;
     if (!links) return DIRAC_OK;
@@ -550,7 +562,7 @@ int dirac_theta_from_fields(dirac_ctx *c, double m, void *const v_site[], void *
         v8[q] = v_site ? v_site[q] : nullptr;
     }
     hipStream_t s = (hipStream_t)stream;
-    int64_t ncell = c->nx * c->ny * c->nz;
+    int64_t ncell = c->nx * c->ny * planes_of(c);
     if (c->dtype == DIRAC_C64) HIPCHK(c, launch_theta_fields<float>(th8, v8, narr, ncell, 0.5 * c->dt, m, s));
     else HIPCHK(c, launch_theta_fields<double>(th8, v8, narr, ncell, 0.5 * c->dt, m, s));
     c->m = m;
@@ -579,6 +591,7 @@ int dirac_step(dirac_ctx *c, int64_t n, void *stream) {
 int dirac_reverse(dirac_ctx *c, int64_t n, void *stream) {
     int rc = check_ready(c, !c || !c->site_mode);
     if (rc) return rc;
+    if (c->zh) return fail(c, DIRAC_E_STATE, "z-slab contexts step forward only");
     if (n < 0) return fail(c, DIRAC_E_ARG, "n must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     return c->dtype == DIRAC_C64 ? run_steps<float>(c, n, true, s) : run_steps<double>(c, n, true, s);
@@ -691,6 +704,7 @@ int dirac_norm(dirac_ctx *c, double out[3], void *stream) {
 int dirac_observables(dirac_ctx *c, double z0, double out[9], void *stream) {
     int rc = check_ready(c, true);
     if (rc) return rc;
+    if (c->zh) return fail(c, DIRAC_E_STATE, "not available in z-slab mode (dirac_norm is)");
     if (!out || !isfinite(z0)) return fail(c, DIRAC_E_ARG, "bad output or z0");
     hipStream_t s = (hipStream_t)stream;
     double *part = (double *)scratch_at(c, off_partial(c));
@@ -713,6 +727,7 @@ int dirac_observables(dirac_ctx *c, double z0, double out[9], void *stream) {
 int dirac_seed_region(dirac_ctx *c, double z0, void *const lam[], void *stream) {
     int rc = check_ready(c, false);
     if (rc) return rc;
+    if (c->zh) return fail(c, DIRAC_E_STATE, "not available in z-slab mode");
     if (!lam || !isfinite(z0)) return fail(c, DIRAC_E_ARG, "bad lam or z0");
     int narr = c->ndim == 3 ? 8 : 4;
     void *l8[8] = {0};
@@ -735,6 +750,7 @@ int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int,
     int rc = check_ready(c, true);
     if (rc) return rc;
     if (c->ndim != 3) return fail(c, DIRAC_E_STATE, "the V(z) gradient is defined for 3D lattices");
+    if (c->zh) return fail(c, DIRAC_E_STATE, "not available in z-slab mode");
     if (c->site_mode) return fail(c, DIRAC_E_STATE, "needs a V(z) profile (dirac_set_mass_potential_z)");
     if (!c->w_int.empty())
         return fail(c, DIRAC_E_STATE, "the reversal-based adjoint needs a real potential (no absorbing layers)");

@@ -38,12 +38,19 @@ __device__ __forceinline__ int logical_block() {
     return b;
 }
 
+// Storage plane of plane index pl: periodic wrap, or in z-slab mode the plane
+// counted from the first halo plane (reads reach at most zh planes beyond the
+// interior).
+template <typename R> __device__ __forceinline__ int zplane(const FusedArgs<R> &a, int pl) {
+    return a.zh ? pl + a.zh : wrapn(pl, a.nz);
+}
+
 template <typename R, bool SITE>
 __device__ __forceinline__ Coef<R> fcoef(const FusedArgs<R> &a, int arr, int cls, int pk, size_t idx) {
     if constexpr (SITE) {
         return coef_site_at<R>(a.th[arr], idx, (R)1);
     } else {
-        const R *e = a.tab + ((size_t)cls * a.nz + pk) * 4;
+        const R *e = a.tab + ((size_t)cls * (a.nz + 2 * a.zh) + pk) * 4;
         Coef<R> k;
         k.c1 = mk2(e[0], e[1]);
         k.c2 = mk2(e[2], e[3]);
@@ -236,7 +243,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
     // Global -> LDS copies of the interior rows of C(pl) (slot pl & 1) and
     // D(pl+1) (slot (pl+1) mod 3); wave y takes rows y, y + TY, ...
     auto copy_rows = [&](int pl) {
-        const size_t Pc = (size_t)wrapn(pl, a.nz) * plane, Pd = (size_t)wrapn(pl + 1, a.nz) * plane;
+        const size_t Pc = (size_t)zplane(a, pl) * plane, Pd = (size_t)zplane(a, pl + 1) * plane;
         const int cs = pl & 1, ds = wrapn(pl + 1, 3);
         for (int item = y; item < NROW; item += TY) {
             const int arr = item / (TY + 2), ry0 = item % (TY + 2) - 1;
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
     };
     // register loads for plane pl: halo columns of C(pl), D(pl+1); own and ring A,B(pl)
     auto load_regs = [&](int pl) {
-        const size_t P = (size_t)wrapn(pl, a.nz) * plane, Pp = (size_t)wrapn(pl + 1, a.nz) * plane;
+        const size_t P = (size_t)zplane(a, pl) * plane, Pp = (size_t)zplane(a, pl + 1) * plane;
         if (sv) {
             psc[0] = ldo(in[4] + P, so);
             psc[1] = ldo(in[5] + P, so);
@@ -292,7 +299,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
     {
         // D(z0-1) region (slot (z0-1) mod 3), C(z0-2) at the own and ring cells
         const int dsl = wrapn(z0 - 1, 3);
-        const size_t Pd = (size_t)wrapn(z0 - 1, a.nz) * plane, Pc = (size_t)wrapn(z0 - 2, a.nz) * plane;
+        const size_t Pd = (size_t)zplane(a, z0 - 1) * plane, Pc = (size_t)zplane(a, z0 - 2) * plane;
         for (int item = y; item < 2 * (TY + 2); item += TY) {
             const int arr = item / (TY + 2), ry0 = item % (TY + 2) - 1;
             if (ry0 > h) continue;
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
     for (int p = z0 - 1; p <= z1; ++p) {
         const int cs = p & 1;
         const int ds = wrapn(p, 3), dsn = wrapn(p + 1, 3);
-        const int pk = wrapn(p, a.nz);
+        const int pk = zplane(a, p);
         const size_t P = (size_t)pk * plane;
         const V a0 = pa[0], a1 = pa[1], b0 = pa[2], b1 = pa[3], ra = pra, rb = prb;
         if (p < z1) {
@@ -378,7 +385,7 @@ __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fuse
         }
         if (own && p >= z0 + 1) {
             // C,D of plane k = p-1 from the new A,B of planes p-1 (LDS), p and p-2 (registers)
-            const int kq = wrapn(p - 1, a.nz);
+            const int kq = zplane(a, p - 1);
             const size_t Pm = (size_t)kq * plane;
             const C *A0 = sAB[0], *A1 = sAB[1], *B0 = sAB[2], *B1 = sAB[3];
             V o4, o5, o6, o7;

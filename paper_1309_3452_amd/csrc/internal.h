@@ -35,6 +35,8 @@ template <typename R> struct FusedArgs {
     int ntx, nty;         // tiles in x, y
     double *npart;        // if set: per-workgroup (E_r, plain norm) of the new state, FP64
     int npart_cap;        // capacity of npart in workgroups
+    int zh;               // z-slab mode: halo planes per side (arrays hold nz + 2 zh planes,
+                          // interior planes zh .. zh + nz - 1, no wrap in z); 0 = periodic
 };
 
 // Reduction launch over a single lattice.
@@ -44,6 +46,7 @@ template <typename R> struct ReduceArgs {
     int nx, ny, nz;
     double z0;
     double *partial;      // [nblocks][nv]
+    int zh;               // z-slab mode (as in FusedArgs); 0 = periodic
 };
 
 // Gauge-link arrays (vector potential, Sect. 4): u[6 a + t] (3D) or u[4 a + t]

@@ -150,13 +150,15 @@ __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
         const uint32_t c = (uint32_t)j * a.nx + i;
         const uint32_t xm = (uint32_t)j * a.nx + wrap_dec(i, a.nx), xp = (uint32_t)j * a.nx + wrap_inc(i, a.nx);
         const uint32_t ym = (uint32_t)wrap_dec(j, a.ny) * a.nx + i, yp = (uint32_t)wrap_inc(j, a.ny) * a.nx + i;
-        const size_t Pb = (size_t)wrap_dec(z0, a.nz) * plane, P0 = (size_t)z0 * plane;
+        // storage planes: periodic wrap, or in z-slab mode the interior offset by the halo
+        auto zpl = [&](int pl) { return a.zh ? pl + a.zh : (pl < 0 ? pl + a.nz : pl >= a.nz ? pl - a.nz : pl); };
+        const size_t Pb = (size_t)zpl(z0 - 1) * plane, P0 = (size_t)zpl(z0) * plane;
         double2 cm0 = to_d(f[4][Pb + c]), cm1 = to_d(f[5][Pb + c]);      // C(k-1)
         double2 bm0 = to_d(f[2][Pb + c]), bm1 = to_d(f[3][Pb + c]);      // B(k-1)
         double2 a0 = to_d(f[0][P0 + c]), a1 = to_d(f[1][P0 + c]), d0 = to_d(f[6][P0 + c]), d1 = to_d(f[7][P0 + c]);
         for (int k = z0; k < z1; ++k) {
-            const size_t Pk = (size_t)k * plane;
-            const size_t Pn = (size_t)wrap_inc(k, a.nz) * plane;
+            const size_t Pk = (size_t)zpl(k) * plane;
+            const size_t Pn = (size_t)zpl(k + 1) * plane;
             const double2 an0 = to_d(f[0][Pn + c]), an1 = to_d(f[1][Pn + c]);
             const double2 dn0 = to_d(f[6][Pn + c]), dn1 = to_d(f[7][Pn + c]);
             const double2 b0 = to_d(f[2][Pk + c]), b1 = to_d(f[3][Pk + c]);

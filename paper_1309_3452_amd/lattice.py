@@ -33,10 +33,13 @@ class Lattice:
     """A periodic (2+1)D or (3+1)D lattice of the staggered leap-frog scheme.
 
     shape: (nx, ny) or (nx, ny, nz) cells; dt: time step; d: grid spacings.
+    slab: (3D) a z-slab of a larger lattice (DIRAC_SLAB_Z): nz interior planes,
+    arrays of nz + 4 planes with two halo planes on each side that the caller
+    fills before every step (see SlabDecomposition).
     """
 
     def __init__(self, shape: Sequence[int], dtype=torch.complex128, dt: float = 0.5, d=None,
-                 allow_unstable: bool = False, device="cuda"):
+                 allow_unstable: bool = False, device="cuda", slab: bool = False):
         if len(shape) not in (2, 3):
             raise ValueError("shape must have 2 or 3 entries")
         self.ndim = len(shape)
@@ -48,10 +51,12 @@ class Lattice:
         d = tuple(d) if d is not None else (1.0,) * self.ndim
         self.device = torch.device(device)
         self.narr = 8 if self.ndim == 3 else 4
-        self.tshape = (self.nz, self.ny, self.nx) if self.ndim == 3 else (self.ny, self.nx)
+        self.zh = 2 if slab else 0
+        self.nplanes = self.nz + 2 * self.zh            # stored planes (V(z) table entries)
+        self.tshape = (self.nplanes, self.ny, self.nx) if self.ndim == 3 else (self.ny, self.nx)
         ctx = ctypes.c_void_p()
         dz = d[2] if self.ndim == 3 else 1.0
-        flags = _abi.DIRAC_ALLOW_UNSTABLE if allow_unstable else 0
+        flags = (_abi.DIRAC_ALLOW_UNSTABLE if allow_unstable else 0) | (_abi.DIRAC_SLAB_Z if slab else 0)
         check(lib().dirac_create(ctypes.byref(ctx), self.ndim, self.nx, self.ny, self.nz, _dtype_code(dtype),
                                  self.dt, float(d[0]), float(d[1]), float(dz), flags))
         self._ctx = ctx
@@ -103,30 +108,30 @@ class Lattice:
     def set_potential_z(self, m: float, v_int=None, v_half=None):
         """Mass m and V(z) sampled at integer (v_int) and half-integer (v_half) z."""
         if v_int is None:
-            check(lib().dirac_set_mass_potential_z(self._ctx, float(m), None, None, self.nz), self._ctx)
+            check(lib().dirac_set_mass_potential_z(self._ctx, float(m), None, None, self.nplanes), self._ctx)
             return
         import numpy as np
         vi = np.ascontiguousarray(v_int, dtype=np.float64)
         vh = np.ascontiguousarray(v_half, dtype=np.float64)
-        if vi.shape != (self.nz,) or vh.shape != (self.nz,):
-            raise ValueError("v_int and v_half need nz entries")
+        if vi.shape != (self.nplanes,) or vh.shape != (self.nplanes,):
+            raise ValueError("v_int and v_half need one entry per stored plane (%d)" % self.nplanes)
         check(lib().dirac_set_mass_potential_z(self._ctx, float(m), vi.ctypes.data_as(ctypes.c_void_p),
-                                               vh.ctypes.data_as(ctypes.c_void_p), self.nz), self._ctx)
+                                               vh.ctypes.data_as(ctypes.c_void_p), self.nplanes), self._ctx)
         self._pin = (vi, vh)
 
     def set_absorber_z(self, w_int=None, w_half=None):
         """Imaginary part W(z) of the potential (absorbing layers where W < 0),
         sampled like V(z); None clears it (see dirac_set_potential_im_z)."""
         if w_int is None:
-            check(lib().dirac_set_potential_im_z(self._ctx, None, None, self.nz), self._ctx)
+            check(lib().dirac_set_potential_im_z(self._ctx, None, None, self.nplanes), self._ctx)
             return
         import numpy as np
         wi = np.ascontiguousarray(w_int, dtype=np.float64)
         wh = np.ascontiguousarray(w_half, dtype=np.float64)
-        if wi.shape != (self.nz,) or wh.shape != (self.nz,):
-            raise ValueError("w_int and w_half need nz entries")
+        if wi.shape != (self.nplanes,) or wh.shape != (self.nplanes,):
+            raise ValueError("w_int and w_half need one entry per stored plane (%d)" % self.nplanes)
         check(lib().dirac_set_potential_im_z(self._ctx, wi.ctypes.data_as(ctypes.c_void_p),
-                                             wh.ctypes.data_as(ctypes.c_void_p), self.nz), self._ctx)
+                                             wh.ctypes.data_as(ctypes.c_void_p), self.nplanes), self._ctx)
         self._pin_w = (wi, wh)
 
     def set_fields(self, m: float, v_site=None, w_site=None):

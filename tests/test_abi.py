@@ -95,6 +95,22 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_set_links(c3, ptr_array([256] * 24)) == 0
     assert L.dirac_set_links(c3, None) == 0
     L.dirac_destroy(c3)
+    # z-slab mode: 3D only; tables and fields span nz + 4 planes; forward steps only
+    cs = ctypes.c_void_p()
+    assert L.dirac_create(ctypes.byref(cs), 2, 4, 4, 1, 2, 0.5, 1.0, 1.0, 1.0, 2) == -1
+    assert L.dirac_create(ctypes.byref(cs), 3, 4, 4, nz, 2, 0.5, 1.0, 1.0, 1.0, 2) == 0
+    v4 = (ctypes.c_double * (nz + 4))(*([0.1] * (nz + 4)))
+    assert L.dirac_set_mass_potential_z(cs, 0.5, w, w, nz) == -2
+    assert L.dirac_set_mass_potential_z(cs, 0.5, v4, v4, nz + 4) == 0
+    assert L.dirac_set_potential_im_z(cs, v4, v4, nz + 4) == 0
+    fake = ptr_array([256] * 8)
+    assert L.dirac_bind_state(cs, fake, fake) == 0
+    assert L.dirac_scratch_bytes(cs, ctypes.byref(nb)) == 0
+    assert L.dirac_bind_scratch(cs, ctypes.c_void_p(256), nb.value) == 0
+    assert L.dirac_reverse(cs, 1, None) == -6
+    assert L.dirac_observables(cs, 0.0, (ctypes.c_double * 9)(), None) == -6
+    assert L.dirac_set_links(cs, ptr_array([256] * 24)) == -6
+    L.dirac_destroy(cs)
     L.dirac_destroy(c)
     L.dirac_destroy(None)
 

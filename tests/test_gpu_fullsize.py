@@ -224,6 +224,33 @@ def test_sampled_oracle_parity_links_512_fp32(P):
     free()
 
 
+def test_slabs_at_device_shape_512(P):
+    """One device's share of a 512^3 lattice split over 8 devices is a 512 x 512 x 64
+    slab: two such slabs (a 512 x 512 x 128 periodic lattice) with halos exchanged
+    every step give the bits of the whole lattice, complex64, headline workload."""
+    n, nz, steps = 512, 128, 3
+    print("slabs at 512x512x64", flush=True)
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 4.0)
+    st = workloads.packet3d(n, n, nz, (n / 2.0, n / 2.0, nz / 4.0), 12.0, (0.0, 0.0, 0.56), 0.5, DT3,
+                            dtype=torch.complex64, device="cuda")
+    parts = P.SlabDecomposition(n, n, nz, 2, dtype=torch.complex64, dt=DT3)
+    parts.set_potential_z(0.5, v_int, v_half)
+    parts.load(st)
+    parts.step(steps)
+    got = parts.state()
+    del parts
+    free()
+    whole = P.Lattice3D(n, n, nz, dtype=torch.complex64, dt=DT3)
+    whole.set_kernel("fused")
+    whole.set_potential_z(0.5, v_int, v_half)
+    whole.load(st)
+    whole.step(steps)
+    for a, b in zip(whole.state(), got):
+        assert torch.equal(a, b)
+    del whole, got, st
+    free()
+
+
 def test_adjoint_fd_128_fp64(P):
     """The reversible adjoint's dL/dp against central finite differences (h = 1e-6)
     on the 128^3 adjoint workload (400 steps), FP64."""

@@ -1,0 +1,82 @@
+"""z-slab mode (the per-device unit of a z-decomposed multi-GPU run) on one GPU:
+a periodic lattice split into slabs whose halo planes are filled from their
+neighbours before every step gives the bits of the whole lattice stepped by the
+one-step fused kernel; the slabs' functional sums add up to the whole."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DT3 = workloads.DT3
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1309_3452_amd as P
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.lib()
+    return P
+
+
+def rand_state(shape, count, seed):
+    g = np.random.default_rng(seed)
+    return [torch.from_numpy(np.ascontiguousarray(g.standard_normal(shape) + 1j * g.standard_normal(shape)))
+            for _ in range(count)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("mode", ["vz", "site"])
+@pytest.mark.parametrize("shape,slabs", [((40, 12, 16), 1), ((40, 12, 16), 2), ((40, 12, 16), 4),
+                                         ((70, 9, 16), 8), ((130, 20, 12), 3)])
+def test_slabs_bitwise_equal_periodic(P, dtype, mode, shape, slabs):
+    nx, ny, nz = shape
+    print("slabs %s x%d %s %s" % (shape, slabs, mode, dtype), flush=True)
+    f0 = [t.to(dtype) for t in rand_state((nz, ny, nx), 8, 301)]
+    whole = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+    whole.set_kernel("fused")
+    parts = P.SlabDecomposition(nx, ny, nz, slabs, dtype=dtype, dt=DT3)
+    if mode == "vz":
+        v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+        whole.set_potential_z(0.5, v_int, v_half)
+        parts.set_potential_z(0.5, v_int, v_half)
+    else:
+        g = np.random.default_rng(302)
+        V = [torch.from_numpy(np.ascontiguousarray(0.4 * g.standard_normal((nz, ny, nx)))) for _ in range(8)]
+        whole.set_fields(0.3, V)
+        parts.set_fields(0.3, V)
+    whole.load(f0)
+    parts.load(f0)
+    e_whole, e_parts = whole.norm(), parts.norm()
+    for q in range(3):
+        assert abs(e_parts[q] - e_whole[q]) <= 1e-12 * abs(e_whole[2])
+    whole.step(6)
+    parts.step(6)
+    for a, b in zip(whole.state(), parts.state()):
+        assert torch.equal(a, b)
+    e_whole, e_parts = whole.norm(), parts.norm()
+    for q in range(3):
+        assert abs(e_parts[q] - e_whole[q]) <= 1e-12 * abs(e_whole[2])
+
+
+def test_slab_step_norm_sums(P):
+    """The in-step functional of each slab (interior only) adds up to the whole's."""
+    nx, ny, nz, slabs = 64, 16, 24, 3
+    f0 = rand_state((nz, ny, nx), 8, 311)
+    whole = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    whole.set_kernel("fused")
+    whole.set_potential_z(0.5)
+    whole.load(f0)
+    parts = P.SlabDecomposition(nx, ny, nz, slabs, dtype=torch.complex128, dt=DT3)
+    parts.set_potential_z(0.5)
+    parts.load(f0)
+    ew = whole.step_norm(1)
+    es = sum(lat.step_norm(1) for lat in parts.parts)
+    parts.exchange()
+    torch.cuda.synchronize()
+    assert abs(float(es[0]) - float(ew[0])) <= 1e-12 * float(ew[1])
+    assert abs(float(es[1]) - float(ew[1])) <= 1e-12 * float(ew[1])
+    for a, b in zip(whole.state(), parts.state()):
+        assert torch.equal(a, b)
