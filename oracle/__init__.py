@@ -33,12 +33,18 @@ OFFSETS3 = [(0.0, 0.0, 0.0), (0.5, 0.5, 0.0), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5),
 OFFSETS2 = [(0.0, 0.0), (0.5, 0.5), (0.5, 0.0), (0.0, 0.5)]
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc, FP64, no FMA contraction, OpenMP: src (a C file) -> shared library out."""
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-std=c11", src, "-o", out, "-lm"])
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the C oracle (gcc, FP64, no FMA contraction, OpenMP)."""
+    """Compile the C oracle."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-std=c11", _SRC, "-o", tmp, "-lm"])
+        compile_source(_SRC, tmp)
         os.replace(tmp, _SO)
     return _SO
 
@@ -46,25 +52,29 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def load(path: str):
+    """A ctypes handle to an oracle library at path, with the signatures set."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    for name in ("oracle_step3", "oracle_reverse3", "oracle_step2", "oracle_reverse2"):
+        getattr(L, name).argtypes = [P, P, P, P]
+    for name in ("oracle_step3c", "oracle_step2c", "oracle_step3_links", "oracle_step2_links",
+                 "oracle_energy3_links", "oracle_energy2_links"):
+        getattr(L, name).argtypes = [P, P, P, P, P]
+    for name in ("oracle_energy3", "oracle_energy2"):
+        getattr(L, name).argtypes = [P, P, P, P]
+    L.oracle_observe3.argtypes = [P, P, ctypes.c_double, P]
+    L.oracle_observe2.argtypes = [P, P, ctypes.c_double, P]
+    L.oracle_adjoint3.argtypes = [P] * 7
+    L.oracle_adjoint2.argtypes = [P] * 7
+    L.oracle_threads.restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_SO)
-        P = ctypes.c_void_p
-        for name in ("oracle_step3", "oracle_reverse3", "oracle_step2", "oracle_reverse2"):
-            getattr(L, name).argtypes = [P, P, P, P]
-        for name in ("oracle_step3c", "oracle_step2c", "oracle_step3_links", "oracle_step2_links",
-                     "oracle_energy3_links", "oracle_energy2_links"):
-            getattr(L, name).argtypes = [P, P, P, P, P]
-        for name in ("oracle_energy3", "oracle_energy2"):
-            getattr(L, name).argtypes = [P, P, P, P]
-        L.oracle_observe3.argtypes = [P, P, ctypes.c_double, P]
-        L.oracle_observe2.argtypes = [P, P, ctypes.c_double, P]
-        L.oracle_adjoint3.argtypes = [P] * 7
-        L.oracle_adjoint2.argtypes = [P] * 7
-        L.oracle_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = load(build())
     return _lib
 
 
