@@ -493,8 +493,8 @@ def bench_plane2d(steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(z-slab sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: a lattice is stepped on one device (a z-slab context is the "
+              "per-device unit of a multi-device run); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.calibrate_copy:
