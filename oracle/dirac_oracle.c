@@ -35,8 +35,7 @@
  *     alpha = (1 - i theta) beta    = (1 - theta^2 - 2 i theta)/(1 + theta^2).
  * The caller supplies theta per site (it folds m, V and dt).
  *
- * Readings taken where the paper is silent or garbled (each is listed in the
- * design notes): periodic boundaries; V and m sampled at the updated
+ * Readings taken where the paper is silent or garbled: periodic boundaries; V and m sampled at the updated
  * amplitude's own site and sheet; hbar = c = 1, so Delta_o = dt and
  * r_j = dt/Delta_j; in 2D the conserved functional carries delta_+ (the sign
  * that the printed update equations conserve), the printed delta_- form is
