@@ -133,6 +133,25 @@ def test_packet_512_fp32_vs_fp64(P):
     free()
 
 
+def test_full_oracle_parity_256_fp64(P):
+    """The 256^3 complex128 Klein-step workload, 20 steps through the default
+    (two steps per launch) kernel, against the oracle on every cell."""
+    n, steps = 256, 20
+    cfg = workloads.config_step3d(n, dtype=torch.complex128, device="cpu")
+    print("full parity 256^3, %d steps" % steps, flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    lat.step(steps)
+    got = [t.cpu().numpy() for t in lat.state()]
+    del lat
+    free()
+    ol = oracle.Lattice3(n, n, n, cfg["dt"])
+    f = [np.ascontiguousarray(t.numpy()) for t in cfg["state"]]
+    ol.step(f, ol.theta_vz(cfg["m"], cfg["v_int"], cfg["v_half"]), steps)
+    assert rel_l2(got, f) <= 1e-13
+
+
 def test_sampled_oracle_parity_256_fp64(P):
     """Klein-step workload at 256^3 (fused kernel, bench launch configuration): after
     3 steps, sampled cells against the oracle run on a periodic sub-box of half-width
