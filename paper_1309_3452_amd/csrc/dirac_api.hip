@@ -271,11 +271,11 @@ int kernel_choice(const dirac_ctx *c) {
     if (c->kernel == DIRAC_KERNEL_FUSED) return DIRAC_KERNEL_FUSED;
     if (c->ndim == 3 && fused3x2_supported((int)c->nx, c->dtype == DIRAC_C64, c->site_mode))
         return DIRAC_KERNEL_FUSED2;
-    // (2+1)D: two-step passes need long y chunks (a six-row pipeline per
-    // chunk), so small lattices keep the one-step march, which spreads them
-    // over more workgroups; an explicit FUSED2 request is honoured
+    // (2+1)D: a two-step pass recomputes a six-row pipeline per chunk, so small
+    // lattices (under 2^18 cells, cache-resident) keep the one-step march, which
+    // spreads them over more workgroups; an explicit FUSED2 request is honoured
     if (c->ndim == 2 && fused2x2_supported((int)c->nx, c->dtype == DIRAC_C64) &&
-        (c->kernel == DIRAC_KERNEL_FUSED2 || c->nx * c->ny >= (int64_t)1 << 20))
+        (c->kernel == DIRAC_KERNEL_FUSED2 || c->nx * c->ny >= (int64_t)1 << 18))
         return DIRAC_KERNEL_FUSED2;
     return DIRAC_KERNEL_FUSED;
 }

@@ -454,9 +454,11 @@ template <typename R> hipError_t launch_fused2x2(const FusedArgs<R> &a0, bool si
     a.ntx = (a.nx + TW - 1) / TW;
     a.nty = 1;
     if (a.zchunk <= 0) {
-        const int nc = chunks_for(a.ntx, a.ny, 2048);
+        // about 1024 workgroups of TW + 64 threads: 2^19-cell lattices march 4-row
+        // chunks, 2^21-cell ones 16 (the best of a sweep from 2 to 128 rows)
+        const int nc = chunks_for(a.ntx, a.ny, 1024);
         a.zchunk = (a.ny + nc - 1) / nc;
-        if (a.zchunk < 32 && a.ny >= 32) a.zchunk = 32;
+        if (a.zchunk < 4) a.zchunk = a.ny < 4 ? a.ny : 4;
     }
     a.nzc = (a.ny + a.zchunk - 1) / a.zchunk;
     const int64_t nblk = (int64_t)a.ntx * a.nzc;

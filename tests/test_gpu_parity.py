@@ -436,6 +436,28 @@ def test_fused2_2d_bitwise_equals_one_step(P, dtype, site, shape, steps):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("zchunk", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("shape,steps", [((130, 40), 5), ((256, 33), 6), ((64, 7), 4)])
+def test_fused2_2d_short_chunks_bitwise(P, dtype, zchunk, shape, steps):
+    """Two-step 2D passes over chunks of a few rows give the bits of one-step launches."""
+    nx, ny = shape
+    print("fused2 2d zchunk=%d %s %s" % (zchunk, shape, dtype), flush=True)
+    g = np.random.default_rng(111)
+    f0 = rand_state((ny, nx), 4, 112)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)]
+    res = []
+    for kernel, zc in (("fused2", zchunk), ("fused", 0)):
+        lat = P.Lattice2D(nx, ny, dtype=dtype, dt=DT2)
+        lat.set_kernel(kernel, 0, zc)
+        lat.set_fields(0.4, [torch.from_numpy(v) for v in V])
+        lat.load(f0)
+        lat.step(steps)
+        res.append([t.cpu() for t in lat.state()])
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
 def _batch_key(P, lats, dtype):
     props = torch.cuda.get_device_properties(0)
     arch = props.gcnArchName.split(":")[0]
