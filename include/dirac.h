@@ -225,6 +225,20 @@ int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im,
  */
 int dirac_set_links(dirac_ctx *ctx, void *const links[]);
 
+/*
+ * The per-site coefficient record of one state array from its fields (the
+ * time-averaged term of Eqs. ss1-ss4 / scheme2Deq-scheme4thline), for lattices
+ * and batches: theta[t] = (dt/2)(sgn_m + v[t]) + i (dt/2) w[t], formed in FP64
+ * and written in the record format of dtype (see dirac_theta_from_fields):
+ * DIRAC_C128 theta (double; w must be NULL), DIRAC_C64 gamma (complex64).
+ * sgn_m: the mass with the array's sign, +m for A,B / u arrays, -m for C,D / v.
+ * v, w: device arrays of n doubles (V and Im V at the array's sites), or NULL
+ * for zero.  coef: device array of n records.  Context-free, asynchronous on
+ * stream; DIRAC_E_ARG for bad arguments, DIRAC_E_HIP on launch failure.
+ */
+int dirac_coef_from_fields(void *coef, int dtype, double dt, double sgn_m, const void *v, const void *w,
+                           int64_t n, void *stream);
+
 /* Choose the step kernel and its tiling; 0 = library default for a knob.
  *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8
  *           (default 8); its tile is 64 cells in x (128 for complex64 with nx even)

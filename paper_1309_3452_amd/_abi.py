@@ -28,7 +28,7 @@ EXPORTS = (
     "dirac_step", "dirac_step_norm", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
-    "dirac_coef_from_theta_c", "dirac_set_links",
+    "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields",
 )
 
 
@@ -82,6 +82,7 @@ def lib():
         "dirac_coef_from_theta_c": ([P, P, P, I64, P], I),
         "dirac_set_potential_im_z": ([P, P, P, I64], I),
         "dirac_set_links": ([P, PP], I),
+        "dirac_coef_from_fields": ([P, I, D, D, P, P, I64, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

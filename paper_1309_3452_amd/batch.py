@@ -29,35 +29,31 @@ class BatchedLattices:
         self._ctx = ctx
         self.bufs = [[], []]
         self.theta = []
-        half = 0.5 * self.dt
+        self._fields = []
+        code = _dtype_code(dtype)
         for L, shp in zip(lattices, self.shapes):
             st = [torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous().clone() for a in L["state"]]
             self.bufs[0].append(st)
             self.bufs[1].append([torch.zeros(shp, dtype=dtype, device=self.device) for _ in range(4)])
             m = float(L["m"])
-            vs = L.get("v_site")
+            vs, ws = L.get("v_site"), L.get("w_site")
+            if ws is not None and dtype != torch.complex64:
+                raise ValueError("per-site complex potentials are supported for complex64 batches")
             th = []
             for a in range(4):
-                v = torch.zeros(shp, dtype=torch.float64, device=self.device) if vs is None else \
-                    torch.as_tensor(vs[a]).to(device=self.device, dtype=torch.float64)
+                # the library forms theta = (dt/2)(+-m + V) + i (dt/2) W per site (u: +m, v: -m)
+                # in FP64 and writes the record (complex64: gamma, complex128: theta)
                 sgn = 1.0 if a < 2 else -1.0
-                # theta = (dt/2)(+-m + V) per site (u: +m, v: -m), Eqs. scheme2Deq-scheme4thline,
-                # in FP64; complex64 batches bind the per-site gamma record made from it
-                theta = (half * (sgn * m + v)).contiguous()
-                ws = L.get("w_site")
-                if ws is not None and dtype != torch.complex64:
-                    raise ValueError("per-site complex potentials are supported for complex64 batches")
-                if dtype == torch.complex64:
-                    thi = None if ws is None else \
-                        (half * torch.as_tensor(ws[a]).to(device=self.device, dtype=torch.float64)).contiguous()
-                    coef = torch.empty(shp, dtype=torch.complex64, device=self.device)
-                    check(lib().dirac_coef_from_theta_c(ctypes.c_void_p(coef.data_ptr()),
-                                                        ctypes.c_void_p(theta.data_ptr()),
-                                                        ctypes.c_void_p(thi.data_ptr()) if thi is not None else None,
-                                                        theta.numel(), _stream_handle()))
-                    th.append(coef)
-                else:
-                    th.append(theta)
+                v = None if vs is None else torch.as_tensor(vs[a]).to(device=self.device, dtype=torch.float64).contiguous()
+                w = None if ws is None else torch.as_tensor(ws[a]).to(device=self.device, dtype=torch.float64).contiguous()
+                coef = torch.empty(shp, dtype=torch.complex64 if dtype == torch.complex64 else torch.float64,
+                                   device=self.device)
+                check(lib().dirac_coef_from_fields(ctypes.c_void_p(coef.data_ptr()), code, self.dt, sgn * m,
+                                                   ctypes.c_void_p(v.data_ptr()) if v is not None else None,
+                                                   ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                                                   coef.numel(), _stream_handle()))
+                th.append(coef)
+                self._fields.append((v, w))
             self.theta.append(th)
         nbytes = ctypes.c_size_t()
         check(lib().dirac_scratch_bytes(ctx, ctypes.byref(nbytes)), ctx)

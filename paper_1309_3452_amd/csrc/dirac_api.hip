@@ -550,6 +550,18 @@ int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im,
     return DIRAC_OK;
 }
 
+int dirac_coef_from_fields(void *coef, int dtype, double dt, double sgn_m, const void *v, const void *w, int64_t n,
+                           void *stream) {
+    if (!coef || n < 0 || !isfinite(dt) || !isfinite(sgn_m)) return DIRAC_E_ARG;
+    if (dtype != DIRAC_C64 && dtype != DIRAC_C128) return DIRAC_E_ARG;
+    if (dtype == DIRAC_C128 && w) return DIRAC_E_ARG;     // complex128 records hold a real theta
+    if (n == 0) return DIRAC_OK;
+    if (launch_coef_from_fields(coef, dtype == DIRAC_C64, 0.5 * dt, sgn_m, (const double *)v, (const double *)w, n,
+                                (hipStream_t)stream) != hipSuccess)
+        return DIRAC_E_HIP;
+    return DIRAC_OK;
+}
+
 int dirac_theta_from_fields(dirac_ctx *c, double m, void *const v_site[], void *const theta[], void *stream) {
     if (!c || !theta || !isfinite(m)) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");

@@ -90,6 +90,8 @@ template <typename R> hipError_t launch_theta_fields(void *const th[8], void *co
                                                      double half_dt, double m, hipStream_t s);
 hipError_t launch_coef_from_theta(void *coef, const double *theta, const double *theta_im, int64_t n,
                                   hipStream_t s);
+hipError_t launch_coef_from_fields(void *coef, bool c64, double half_dt, double sgn_m, const double *v,
+                                   const double *w, int64_t n, hipStream_t s);
 hipError_t launch_final_sum(const double *partial, int nblocks, int nv, double *out, hipStream_t s);
 
 // 2D split kernels (kernels2d.hip)

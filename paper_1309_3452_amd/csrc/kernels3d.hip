@@ -298,6 +298,22 @@ __global__ __launch_bounds__(256) void k_coef_from_theta(float2 *coef, const dou
         coef[t] = gamma32_complex(theta[t], theta_im ? theta_im[t] : 0.0);
 }
 
+// Per-site record from the fields of one state array: theta = half_dt (sgn_m +
+// V) + i half_dt W in FP64, then gamma (complex64 lattices) or theta itself.
+template <bool C64>
+__global__ __launch_bounds__(256) void k_coef_from_fields(void *coef, double half_dt, double sgn_m, const double *v,
+                                                          const double *w, int64_t n) {
+#pragma clang fp contract(off)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double th = half_dt * (sgn_m + (v ? v[t] : 0.0));
+        if constexpr (C64) {
+            ((float2 *)coef)[t] = gamma32_complex(th, w ? half_dt * w[t] : 0.0);
+        } else {
+            ((double *)coef)[t] = th;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_final_sum(const double *partial, int nblocks, int nv, double *out) {
     __shared__ double lds[16 * 16];
     // one value at a time, fixed order: thread t sums blocks t, t+256, ...
@@ -369,6 +385,17 @@ hipError_t launch_coef_from_theta(void *coef, const double *theta, const double 
                                   hipStream_t s) {
     hipLaunchKernelGGL(k_coef_from_theta, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (float2 *)coef, theta,
                        theta_im, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_from_fields(void *coef, bool c64, double half_dt, double sgn_m, const double *v,
+                                   const double *w, int64_t n, hipStream_t s) {
+    if (c64)
+        hipLaunchKernelGGL(k_coef_from_fields<true>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, coef, half_dt,
+                           sgn_m, v, w, n);
+    else
+        hipLaunchKernelGGL(k_coef_from_fields<false>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, coef,
+                           half_dt, sgn_m, v, w, n);
     return hipGetLastError();
 }
 

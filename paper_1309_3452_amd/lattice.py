@@ -143,20 +143,21 @@ class Lattice:
         if w_site is not None:
             if self.dtype != torch.complex64:
                 raise ValueError("per-site complex potentials are supported for complex64 lattices")
-            # theta = (dt/2)(+-m + V) + i (dt/2) W in FP64, then the library's records
-            half = 0.5 * self.dt
+            # the library forms theta = (dt/2)(+-m + V) + i (dt/2) W in FP64 and the records
             self.theta = []
+            self._fields = []
             for a in range(self.narr):
                 sgn = 1.0 if a < self.narr // 2 else -1.0
-                v = torch.zeros(self.tshape, dtype=torch.float64, device=self.device) if v_site is None else \
-                    torch.as_tensor(v_site[a]).to(device=self.device, dtype=torch.float64)
-                w = torch.as_tensor(w_site[a]).to(device=self.device, dtype=torch.float64)
-                th = (half * (sgn * float(m) + v)).contiguous()
-                thi = (half * w).contiguous()
+                v = None if v_site is None else \
+                    torch.as_tensor(v_site[a]).to(device=self.device, dtype=torch.float64).contiguous()
+                w = torch.as_tensor(w_site[a]).to(device=self.device, dtype=torch.float64).contiguous()
                 rec = torch.empty(self.tshape, dtype=torch.complex64, device=self.device)
-                check(lib().dirac_coef_from_theta_c(ctypes.c_void_p(rec.data_ptr()), ctypes.c_void_p(th.data_ptr()),
-                                                    ctypes.c_void_p(thi.data_ptr()), th.numel(), _stream_handle()))
+                check(lib().dirac_coef_from_fields(ctypes.c_void_p(rec.data_ptr()), _abi.DIRAC_C64, self.dt,
+                                                   sgn * float(m), ctypes.c_void_p(v.data_ptr()) if v is not None
+                                                   else None, ctypes.c_void_p(w.data_ptr()), rec.numel(),
+                                                   _stream_handle()))
                 self.theta.append(rec)
+                self._fields.append((v, w))
             check(lib().dirac_set_theta_field(self._ctx, ptr_array([t.data_ptr() for t in self.theta])), self._ctx)
             return
         self.theta = [torch.empty(self.tshape, dtype=cdt, device=self.device) for _ in range(self.narr)]
