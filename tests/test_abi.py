@@ -88,6 +88,12 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_set_potential_im_z(c3, w, w, nz) == 0
     assert L.dirac_set_potential_im_z(c3, None, None, nz) == 0
     assert L.dirac_coef_from_theta_c(None, None, None, 1, None) == -1
+    # records from fields: validated before any launch
+    assert L.dirac_coef_from_fields(None, 1, 0.5, 0.1, None, None, 4, None) == -1
+    assert L.dirac_coef_from_fields(ctypes.c_void_p(256), 3, 0.5, 0.1, None, None, 4, None) == -1
+    assert L.dirac_coef_from_fields(ctypes.c_void_p(256), 2, 0.5, 0.1, None, ctypes.c_void_p(256), 4, None) == -1
+    assert L.dirac_coef_from_fields(ctypes.c_void_p(256), 1, float("nan"), 0.1, None, None, 4, None) == -1
+    assert L.dirac_coef_from_fields(ctypes.c_void_p(256), 1, 0.5, 0.1, None, None, 0, None) == 0
     # gauge links: 24 non-null arrays in 3D (pointers only recorded, never dereferenced here)
     from paper_1309_3452_amd._abi import ptr_array
     assert L.dirac_set_links(c3, ptr_array([256] * 23 + [0])) == -1
