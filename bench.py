@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP per FMA x 2.4 GHz (packed FP32, which would double it, is not used)
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# per amplitude update: S (3 differences, 2 products, 4 FMA) 16 FLOP + update (2 products, 6 FMA, 2 differences)
+# 16 FLOP; 16 amplitude updates per cell-step
+ALU_FLOP_PER_CELL_STEP = 16 * 32
 NORM_EVERY = 10
 
 
@@ -568,7 +573,14 @@ def main():
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": r32["launch_ms"],
                      "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "copy_ceiling_GBs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs},
+                     "copy_ceiling_GBs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs,
+                     # the two-step kernel moves about half the algorithmic bytes across the bus and is
+                     # limited by VALU issue: its useful FP32 arithmetic (32 FLOP per amplitude update,
+                     # 16 updates per cell-step) against the non-packed FP32 vector peak
+                     "alu": {"flop_per_cell_step": ALU_FLOP_PER_CELL_STEP,
+                             "achieved_TFLOPs": ALU_FLOP_PER_CELL_STEP * value / 1e12,
+                             "peak_TFLOPs": FP32_NONPACKED_TFLOPS,
+                             "frac": ALU_FLOP_PER_CELL_STEP * value / 1e12 / FP32_NONPACKED_TFLOPS}},
         "norm_error": {"E_r_rel_drift_fp32": r32["drift"], "E_r_rel_drift_fp32_max_every10": r32["drift_max"],
                        "steps_total": r32["steps_total"], "plain_norm_rel_change": r32["plain_norm_change"]},
         "amplitude_updates_per_s": 8 * value,
