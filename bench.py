@@ -573,6 +573,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": r32["launch_ms"],
                      "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "kernel_source_sha": kernel_source_hash(G),
                      "copy_ceiling_GBs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs,
                      # the two-step kernel moves about half the algorithmic bytes across the bus and is
                      # limited by VALU issue: its useful FP32 arithmetic (32 FLOP per amplitude update,
