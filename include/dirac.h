@@ -215,9 +215,9 @@ int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im,
  * coupling is gauge covariant: with U = exp(i (chi(Y) - chi(X))) a step maps
  * exp(-i chi) psi to exp(-i chi) times the free step of psi.  Unit-modulus
  * links keep E_r (dirac_norm, evaluated with the links) exactly conserved.
- * While links are bound, a (3+1)D step takes one z-march launch per step that
- * moves the state to the other buffer set (unless DIRAC_KERNEL_SPLIT is set);
- * (2+1)D steps, the reversed step and DIRAC_KERNEL_SPLIT use the in-place split
+ * While links are bound, a step takes one launch (a z-march in 3D, a y-march in
+ * 2D) that moves the state to the other buffer set, unless DIRAC_KERNEL_SPLIT
+ * is set; the reversed step and DIRAC_KERNEL_SPLIT use the in-place split
  * kernels; all give the same bits.  dirac_step_norm steps, then reduces.
  * dirac_adjoint_vz is refused.  links == NULL unbinds them.  The arrays must stay valid while
  * bound.  DIRAC_E_ARG for a null link array (nothing is bound then),

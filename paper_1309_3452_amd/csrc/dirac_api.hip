@@ -10,6 +10,7 @@
 
 #include "../../include/dirac.h"
 #include "ctx.h"
+#include "gauge.h"
 #include "internal.h"
 
 using namespace dirac;
@@ -263,8 +264,8 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
 int kernel_choice(const dirac_ctx *c) {
     if (c->zh) return DIRAC_KERNEL_FUSED;          // z-slab mode: the one-step march only
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
-    // links: the 3D z-march link kernel (one step per launch), else the split ones
-    if (c->links_on) return c->ndim == 3 ? DIRAC_KERNEL_FUSED : DIRAC_KERNEL_SPLIT;
+    // links: the link marches (one step per launch)
+    if (c->links_on) return DIRAC_KERNEL_FUSED;
     // the fused kernels address a plane with 32-bit byte offsets
     const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
     if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
@@ -304,7 +305,8 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
     for (; t < n; ++t) {
         if (fused && c->links_on) {
             FusedArgs<R> a = fused_args<R>(c);
-            HIPCHK(c, launch_fused_links<R>(a, link_ptrs(c), site, s));
+            if (c->ndim == 3) HIPCHK(c, launch_fused_links<R>(a, link_ptrs(c), site, s));
+            else HIPCHK(c, launch_fused2_links<R>(a, link_ptrs(c), site, s));
             c->cur = 1 - c->cur;
         } else if (fused) {
             FusedArgs<R> a = fused_args<R>(c);

@@ -19,6 +19,7 @@
 #include "internal.h"
 #include "stencil3.h"
 #include "march2.h"
+#include "gauge.h"
 
 namespace dirac {
 
@@ -475,29 +476,45 @@ __device__ __forceinline__ Nb2 nb2(int i, int j, int nx, int ny) {
 }
 enum { T2XP = 0, T2XM = 1, T2YP = 2, T2YM = 3 };
 
+// u rows with links, one row per array (u: the array's four link factors at
+// the cell, term order +x, -x, +y, -y):
+//   u0: +x v0, -x v0[i-1], +y v1, -y v1[j-1];  u1: +x v1[i+1], -x v1, +y v0[j+1], -y v0
+template <typename C, typename R>
+__device__ __forceinline__ C u_row0(const C *u, C v0, C v0xm, C v1, C v1ym, R rx, R ry) {
+    return sterm2(rx, csub(cmul(u[T2XP], v0), cmul(u[T2XM], v0xm)), -ry, csub(cmul(u[T2YP], v1), cmul(u[T2YM], v1ym)));
+}
+template <typename C, typename R>
+__device__ __forceinline__ C u_row1(const C *u, C v1xp, C v1, C v0yp, C v0, R rx, R ry) {
+    return sterm2(rx, csub(cmul(u[T2XP], v1xp), cmul(u[T2XM], v1)), -ry, csub(cmul(u[T2YP], v0yp), cmul(u[T2YM], v0)));
+}
+// v rows from their 8 couplings T[4 q + term] (q = v0, v1; term order +x, -x, +y, -y):
+//   v0: u0(xp).-x  u0.+x  u1.-y  u1(ym).+y;   v1: u1.-x  u1(xm).+x  u0(yp).-y  u0.+y
+template <typename C, typename R> __device__ __forceinline__ St2<C> v_rows(const C (&T)[8], R rx, R ry) {
+    St2<C> s;
+    s.s0 = sterm2(rx, csub(T[0], T[1]), ry, csub(T[2], T[3]));
+    s.s1 = sterm2(rx, csub(T[4], T[5]), ry, csub(T[6], T[7]));
+    return s;
+}
+
 template <typename D, typename RD, typename CS>
 __device__ __forceinline__ St2<D> links_u(const CS *const f[4], const LinkPtrs &L, const Nb2 &n, RD rx, RD ry) {
     constexpr int NT = 4;
+    D u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = LK(q / 4, q % 4, n.c);
     St2<D> s;
-    // u0: +x v0, -x v0[i-1], +y v1, -y v1[j-1]
-    s.s0 = sterm2(rx, csub(cmul(LK(0, T2XP, n.c), FV(2, n.c)), cmul(LK(0, T2XM, n.c), FV(2, n.xm))),
-                  -ry, csub(cmul(LK(0, T2YP, n.c), FV(3, n.c)), cmul(LK(0, T2YM, n.c), FV(3, n.ym))));
-    // u1: +x v1[i+1], -x v1, +y v0[j+1], -y v0
-    s.s1 = sterm2(rx, csub(cmul(LK(1, T2XP, n.c), FV(3, n.xp)), cmul(LK(1, T2XM, n.c), FV(3, n.c))),
-                  -ry, csub(cmul(LK(1, T2YP, n.c), FV(2, n.yp)), cmul(LK(1, T2YM, n.c), FV(2, n.c))));
+    s.s0 = u_row0(u, FV(2, n.c), FV(2, n.xm), FV(3, n.c), FV(3, n.ym), rx, ry);
+    s.s1 = u_row1(u + 4, FV(3, n.xp), FV(3, n.c), FV(2, n.yp), FV(2, n.c), rx, ry);
     return s;
 }
 template <typename D, typename RD, typename CS>
 __device__ __forceinline__ St2<D> links_v(const CS *const f[4], const LinkPtrs &L, const Nb2 &n, RD rx, RD ry) {
     constexpr int NT = 4;
-    St2<D> s;
-    // v0: +x u0[i+1] (its -x term), -x u0 (+x), +y u1 (-y), -y u1[j-1] (+y)
-    s.s0 = sterm2(rx, csub(cmul(LKC(0, T2XM, n.xp), FV(0, n.xp)), cmul(LKC(0, T2XP, n.c), FV(0, n.c))),
-                  ry, csub(cmul(LKC(1, T2YM, n.c), FV(1, n.c)), cmul(LKC(1, T2YP, n.ym), FV(1, n.ym))));
-    // v1: +x u1 (-x), -x u1[i-1] (+x), +y u0[j+1] (-y), -y u0 (+y)
-    s.s1 = sterm2(rx, csub(cmul(LKC(1, T2XM, n.c), FV(1, n.c)), cmul(LKC(1, T2XP, n.xm), FV(1, n.xm))),
-                  ry, csub(cmul(LKC(0, T2YM, n.yp), FV(0, n.yp)), cmul(LKC(0, T2YP, n.c), FV(0, n.c))));
-    return s;
+    const D T[8] = {pr(LK(0, T2XM, n.xp), FV(0, n.xp)), pr(LK(0, T2XP, n.c), FV(0, n.c)),
+                    pr(LK(1, T2YM, n.c), FV(1, n.c)), pr(LK(1, T2YP, n.ym), FV(1, n.ym)),
+                    pr(LK(1, T2XM, n.c), FV(1, n.c)), pr(LK(1, T2XP, n.xm), FV(1, n.xm)),
+                    pr(LK(0, T2YM, n.yp), FV(0, n.yp)), pr(LK(0, T2YP, n.c), FV(0, n.c))};
+    return v_rows(T, rx, ry);
 }
 
 template <typename R, bool SITE, int WHICH>
@@ -524,6 +541,122 @@ __global__ __launch_bounds__(256) void k2_half_links(HalfArgs<R> a, LinkPtrs L) 
         const St2<C> s = links_v<C, R, C>(fc, L, n, a.rx, a.ry);
         f[2][n.c] = update(f[2][n.c], s.s0, gcoef<R, SITE>(a, 2, 3, 0, n.c));
         f[3][n.c] = update(f[3][n.c], s.s1, gcoef<R, SITE>(a, 3, 3, 0, n.c));
+    }
+}
+
+// (2+1)D step with links in one launch: a workgroup owns an x strip of TW cells
+// and marches a chunk of rows; at row p it updates u(p) on the strip and on a
+// one-cell ring (left: u1, right: u0), then v(p-1) on the strip.  Each v
+// coupling pr(U, new u) is formed by the thread that updated the u end: four
+// serve the cell's own v rows (kept one row), u0's -y one the v1 row below
+// (used at once), u1's +y one the v0 row above (kept two rows), and u0's -x and
+// u1's +x ones the x neighbours (LDS).  Same helpers as the split kernels.
+template <typename R, bool SITE, int TW>
+__global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPtrs L) {
+    using C = cx<R>;
+    constexpr int LW = TW + 2;
+    __shared__ C sE[2][2][LW];     // slot p & 1: [0] u0's -x coupling, [1] u1's +x coupling
+    const int tx = blockIdx.x % a.ntx, yc = blockIdx.x / a.ntx;
+    const int x0 = tx * TW, w = min(TW, a.nx - x0);
+    const int y0 = yc * a.zchunk, y1 = min(a.ny, y0 + a.zchunk);
+    const int t = threadIdx.x;
+    int x = 0;
+    bool tile = false, n0 = false, n1 = false;
+    if (t < TW) {
+        x = t;
+        tile = n0 = n1 = x < w;
+    } else if (t == TW) {
+        x = -1;
+        n1 = true;                 // its u1 coupling reaches the strip's first v1
+    } else if (t == TW + 1) {
+        x = w;
+        n0 = true;                 // its u0 coupling reaches the strip's last v0
+    }
+    const bool act = n0 || n1;
+    const int gx = wrapn(x0 + x, a.nx);
+    const int gxm = wrap_dec(gx, a.nx), gxp = wrap_inc(gx, a.nx);
+    const int li = x + 1;
+    const size_t nx = (size_t)a.nx;
+    const C *in[4];
+    C *out[4];
+    const C *lk[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        in[q] = (const C *)a.in[q];
+        out[q] = (C *)a.out[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lk[q] = (const C *)L.u[q];
+    const R rx = a.rx, ry = a.ry;
+    const C zero = mk2((R)0, (R)0);
+    auto coef = [&](int arr, int cls, size_t idx) -> Coef<R> {
+        if constexpr (SITE) {
+            return coef_site_at<R>(a.th[arr], idx, (R)1);
+        } else {
+            const R *e = a.tab + (size_t)cls * a.nz * 4;      // plane 0 of class cls
+            Coef<R> k;
+            k.c1 = mk2(e[0], e[1]);
+            k.c2 = mk2(e[2], e[3]);
+            return k;
+        }
+    };
+    // carried: old v0 of rows p and p-1, old v1 of row p-1; own couplings of u(p-1);
+    // the u1 +y couplings of u(p-1) and u(p-2)
+    C v0c = zero, v0m = zero, v1m = zero, Q[4] = {zero, zero, zero, zero}, up1 = zero, up2 = zero;
+    if (act) {
+        v0c = in[2][(size_t)wrapn(y0 - 1, a.ny) * nx + gx];
+        v1m = in[3][(size_t)wrapn(y0 - 2, a.ny) * nx + gx];
+    }
+    for (int p = y0 - 1; p <= y1; ++p) {
+        const size_t row = (size_t)wrapn(p, a.ny) * nx, rown = (size_t)wrapn(p + 1, a.ny) * nx;
+        const size_t ci = row + gx;
+        C v1c = zero, v0n = zero, Qn[4] = {zero, zero, zero, zero}, dn = zero, upn = zero, eL = zero, eR = zero;
+        if (act) {
+            v1c = in[3][ci];
+            v0n = in[2][rown + gx];
+            const bool store = tile && p >= y0 && p < y1;
+            C u[4];
+            if (n0) {
+                const C v0xm = in[2][row + gxm];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = lk[q][ci];
+                const C nu0 = update(in[0][ci], u_row0(u, v0c, v0xm, v1c, v1m, rx, ry), coef(0, 0, ci));
+                if (store) out[0][ci] = nu0;
+                eL = pr(u[T2XM], nu0);
+                Qn[0] = pr(u[T2XP], nu0);
+                Qn[3] = pr(u[T2YP], nu0);
+                dn = pr(u[T2YM], nu0);
+            }
+            if (n1) {
+                const C v1xp = in[3][row + gxp];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = lk[4 + q][ci];
+                const C nu1 = update(in[1][ci], u_row1(u, v1xp, v1c, v0n, v0c, rx, ry), coef(1, 0, ci));
+                if (store) out[1][ci] = nu1;
+                eR = pr(u[T2XP], nu1);
+                Qn[1] = pr(u[T2YM], nu1);
+                Qn[2] = pr(u[T2XM], nu1);
+                upn = pr(u[T2YP], nu1);
+            }
+            sE[p & 1][0][li] = eL;
+            sE[p & 1][1][li] = eR;
+        }
+        if (tile && p - 1 >= y0 && p - 1 < y1) {
+            const size_t cm = (size_t)wrapn(p - 1, a.ny) * nx + gx;
+            const C(*e)[LW] = sE[(p - 1) & 1];
+            const C T[8] = {e[0][li + 1], Q[0], Q[1], up2, Q[2], e[1][li - 1], dn, Q[3]};
+            const St2<C> s = v_rows(T, rx, ry);
+            out[2][cm] = update(v0m, s.s0, coef(2, 3, cm));
+            out[3][cm] = update(v1m, s.s1, coef(3, 3, cm));
+        }
+        __syncthreads();
+        v0m = v0c;
+        v0c = v0n;
+        v1m = v1c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Q[q] = Qn[q];
+        up2 = up1;
+        up1 = upn;
     }
 }
 
@@ -613,6 +746,27 @@ hipError_t launch_fused_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool si
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_fused2_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool site, hipStream_t s) {
+    FusedArgs<R> a = a0;
+    constexpr int TW = 128;
+    a.ntx = (a.nx + TW - 1) / TW;
+    a.nty = 1;
+    if (a.zchunk <= 0) {
+        // about 1024 workgroups, chunks of at least 8 rows (each chunk recomputes two)
+        int64_t nc = (1024 + a.ntx - 1) / a.ntx;
+        if (nc > a.ny) nc = a.ny;
+        a.zchunk = (int)((a.ny + nc - 1) / nc);
+        if (a.zchunk < 8) a.zchunk = a.ny < 8 ? a.ny : 8;
+    }
+    a.nzc = (a.ny + a.zchunk - 1) / a.zchunk;
+    const int64_t nblk = (int64_t)a.ntx * a.nzc;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    if (site) hipLaunchKernelGGL((k2_fused_links<R, true, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L);
+    else hipLaunchKernelGGL((k2_fused_links<R, false, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L);
+    return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const LinkPtrs &L, int ndim, hipStream_t s) {
     if (ndim == 3) hipLaunchKernelGGL((k3_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
     else hipLaunchKernelGGL((k2_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
@@ -623,6 +777,8 @@ template hipError_t launch_half_links<float>(const HalfArgs<float> &, const Link
 template hipError_t launch_half_links<double>(const HalfArgs<double> &, const LinkPtrs &, int, int, bool, hipStream_t);
 template hipError_t launch_fused_links<float>(const FusedArgs<float> &, const LinkPtrs &, bool, hipStream_t);
 template hipError_t launch_fused_links<double>(const FusedArgs<double> &, const LinkPtrs &, bool, hipStream_t);
+template hipError_t launch_fused2_links<float>(const FusedArgs<float> &, const LinkPtrs &, bool, hipStream_t);
+template hipError_t launch_fused2_links<double>(const FusedArgs<double> &, const LinkPtrs &, bool, hipStream_t);
 template hipError_t launch_norm_links<float>(const ReduceArgs<float> &, const LinkPtrs &, int, hipStream_t);
 template hipError_t launch_norm_links<double>(const ReduceArgs<double> &, const LinkPtrs &, int, hipStream_t);
 

@@ -830,3 +830,35 @@ def test_fused_links_bitwise_equals_split(P, dtype, site, shape, zchunk, steps):
         out.append([t.clone() for t in lat.state()])
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("site", [False, True])
+@pytest.mark.parametrize("shape,zchunk,steps", [((130, 40), 0, 5), ((64, 7), 0, 4), ((1, 5), 0, 3),
+                                                 ((257, 33), 3, 4), ((96, 70), 8, 6), ((2, 2), 1, 3)])
+def test_fused_links_2d_bitwise_equals_split(P, dtype, site, shape, zchunk, steps):
+    """The (2+1)D link march (one launch per step) gives the bits of the split link
+    kernels: ragged strips, chunk boundaries, lattices smaller than the ring."""
+    from closed_form import links_from_potential2
+    nx, ny = shape
+    print("fused links 2d %s %s site=%s zchunk=%d" % (shape, dtype, site, zchunk), flush=True)
+    tsh = (ny, nx)
+    U = _links_t(links_from_potential2(tsh, lambda x, y: (0.4 * np.sin(2 * np.pi * y / max(ny, 2)) + 0.1,
+                                                          0.3 * np.cos(2 * np.pi * x / max(nx, 2)))))
+    f0 = rand_state(tsh, 4, 231)
+    g = np.random.default_rng(232)
+    V = [torch.from_numpy(np.ascontiguousarray(0.4 * g.standard_normal(tsh))) for _ in range(4)]
+    out = []
+    for kind in ("split", "fused"):
+        lat = P.Lattice2D(nx, ny, dtype=dtype, dt=DT2)
+        lat.set_kernel(kind, 0, zchunk)
+        if site:
+            lat.set_fields(0.3, V)
+        else:
+            lat.set_potential_z(0.3)
+        lat.set_links(U)
+        lat.load(f0)
+        lat.step(steps)
+        out.append([t.clone() for t in lat.state()])
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
