@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
-                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "klein2d", "slab3d"],
+                    choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "links2d", "klein2d",
+                             "slab3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -411,6 +412,41 @@ def bench_klein2d(phi_deg):
                         "refraction_angle_deg": angle}}
 
 
+def bench_links2d(n, steps):
+    """(2+1)D n^2 complex64 lattice in a uniform magnetic field (Landau-gauge links),
+    the link y-march against the split link kernels."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    st = workloads.packet2d(n, n, (n / 2.0, n / 2.0), n / 16.0, (0.3, 0.0), 0.3, workloads.DT2,
+                            dtype=torch.complex64, device="cuda")
+    lat = P.Lattice2D(n, n, dtype=torch.complex64, dt=workloads.DT2)
+    lat.set_potential_z(0.3)
+    lat.load(st)
+    lat.set_links(workloads.landau_links2d(n, n, 1, dtype=torch.complex64, device="cuda"))
+    e0 = lat.norm()
+    lat.set_kernel("split")
+    lat.step(2)
+    split_ms = _timed(lambda: lat.step(steps)) / steps
+    lat.set_kernel("auto")
+    lat.step(2)
+    ms = _timed(lambda: lat.step(steps)) / steps
+    e1 = lat.norm()
+    cells = n * n
+    alg = (8 + 8) * 8.0 * cells      # 4 amplitudes read + 4 written, 8 link factors read, per cell-step
+    return {"metric": "site-updates/s, (2+1)D %d^2 complex64 in a uniform magnetic field (gauge links)" % n,
+            "value": cells / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "(2+1)D %d^2, m=0.3, Landau-gauge links of one flux pair across the torus, "
+                                   "Gaussian packet, link y-march" % n, "cells": cells},
+            "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k2_fused_links (one launch per step)", "alg_bytes_per_step": alg},
+            "split_kernels_ms_per_step": split_ms, "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
+
+
 def bench_slab3d(steps):
     """One device's share of the 512^3 headline lattice split into 8 z-slabs: a
     512 x 512 x 64 slab (complex64) with two halo planes per side, stepped by the
@@ -519,6 +555,9 @@ def main():
         return
     if args.workload == "plane2d":
         print(json.dumps(bench_plane2d(200)), flush=True)
+        return
+    if args.workload == "links2d":
+        print(json.dumps(bench_links2d(2048, 200)), flush=True)
         return
     if args.workload == "slab3d":
         print(json.dumps(bench_slab3d(200)), flush=True)

@@ -167,6 +167,22 @@ def peierls_links3d(nx, ny, nz, amp, seed, dtype=torch.complex64, device="cpu"):
     return out
 
 
+def landau_links2d(nx, ny, nflux, dtype=torch.complex64, device="cpu"):
+    """Gauge links of a uniform magnetic field in 2D, Landau gauge a_x = b y with
+    b = 4 pi nflux / ny per cell (periodic across the y wrap): for u array a and
+    direction t (+x, -x, +y, -y) the factor exp(-i a_x(M) d_x), d_x = +-1/2 the
+    x displacement and M the half-link midpoint; y links are 1.  Returns 8 tensors
+    (ny, nx), index 4 a + t."""
+    b = 4.0 * math.pi * nflux / ny
+    out = []
+    for a in range(2):
+        for d in ((0.5, 0.0), (-0.5, 0.0), (0.0, 0.5), (0.0, -0.5)):
+            y = (torch.arange(ny, dtype=torch.float64, device=device) + OFF2[a][1] + 0.5 * d[1]).view(ny, 1)
+            u = torch.polar(torch.ones((), dtype=torch.float64, device=device), -(b * y) * d[0])
+            out.append(u.expand(ny, nx).to(dtype).contiguous())
+    return out
+
+
 # --------------------------------------------------------------------------
 # Configurations
 # --------------------------------------------------------------------------
