@@ -43,8 +43,10 @@ __device__ __forceinline__ int logical_block2() {
     return b;
 }
 
-template <typename R> __device__ __forceinline__ Coef<R> tcoef(const R *tab, int nz, int cls, int pk) {
-    const R *e = tab + ((size_t)cls * nz + pk) * 4;
+// coefficients of class cls (A, B, C, D) at wrapped plane pk; tstride is the
+// byte size of one class's table (nz entries of 4 reals)
+template <typename R> __device__ __forceinline__ Coef<R> tcoef(const R *tab, uint32_t tstride, int cls, int pk) {
+    const R *e = (const R *)((const char *)tab + (uint32_t)cls * tstride + (uint32_t)pk * (uint32_t)(4 * sizeof(R)));
     Coef<R> k;
     k.c1 = mk2(e[0], e[1]);
     k.c2 = mk2(e[2], e[3]);
@@ -54,14 +56,20 @@ template <typename R> __device__ __forceinline__ Coef<R> tcoef(const R *tab, int
 template <typename C> __device__ __forceinline__ C ld_at(const C *base, uint32_t boff) {
     return *(const C *)((const char *)base + boff);
 }
+// base + pb + boff: a plane's byte offset pb (wave-uniform) and a lane offset
+template <typename C> __device__ __forceinline__ C ld_pl(const C *base, size_t pb, uint32_t boff) {
+    return *(const C *)((const char *)base + pb + boff);
+}
 
 typedef float nt2f __attribute__((ext_vector_type(2)));
 typedef double nt2d __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_nt(float2 *p, float2 v) { __builtin_nontemporal_store(nt2f{v.x, v.y}, (nt2f *)p); }
 __device__ __forceinline__ void st_nt(double2 *p, double2 v) { __builtin_nontemporal_store(nt2d{v.x, v.y}, (nt2d *)p); }
-template <typename C> __device__ __forceinline__ void st_at(C *base, uint32_t boff, C v) {
-    st_nt((C *)((char *)base + boff), v);
+template <typename C> __device__ __forceinline__ void st_pl(C *base, size_t pb, uint32_t boff, C v) {
+    st_nt((C *)((char *)base + pb + boff), v);
 }
+// next plane index on the torus of nz planes (k in [0, nz))
+__device__ __forceinline__ int wrap_inc(int k, int nz) { return k + 1 == nz ? 0 : k + 1; }
 
 // Asynchronous global -> LDS copy: lane l's 16 bytes land at lds_wave_base + 16 l.
 __device__ __forceinline__ void g2lds16(const void *gsrc, void *lds_wave_base) {
@@ -132,10 +140,16 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     const int w = min(TW, a.nx - x0), h = min(TY, a.ny - y0);
     const int z0 = zc * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
     const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
-    const size_t plane = (size_t)a.nx * a.ny;
+    // the wave index is uniform: read it into a scalar register so that the
+    // per-wave copy bookkeeping below runs on the scalar unit
+    const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     constexpr uint32_t CS = sizeof(C);
+    // bytes of one plane (below 4 GiB, checked by the launcher) and of one
+    // class of the coefficient table
+    const uint32_t pbytes = (uint32_t)nx * (uint32_t)ny * CS;
+    const uint32_t tstride = (uint32_t)nz * (uint32_t)(4 * sizeof(R));
+    auto pofs = [&](int k) -> size_t { return (size_t)(uint32_t)k * (size_t)pbytes; };
 
     // the region cell of this thread: (xr, yr) relative to the tile origin
     int xr, yr;
@@ -157,20 +171,28 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     const C zero = mk2((R)0, (R)0);
 
     // whole region rows (ring columns included) of the old C (arrays 4, 5) of
-    // plane pc into C slot cs and of D (arrays 6, 7) of plane pd into D slot ds;
-    // lane j moves cells 2j, 2j+1 (complex64) or cell j (complex128) of the row,
-    // wrapped in x per 16-byte unit (nx is even for complex64, so no unit
-    // straddles the wrap)
+    // one plane and of D (arrays 6, 7) of another; lane j moves cells 2j, 2j+1
+    // (complex64) or cell j (complex128) of the row, wrapped in x per 16-byte
+    // unit (nx is even for complex64, so no unit straddles the wrap).  Wave wv
+    // copies rows cy0, cy0 + WPA, ... of array ck for the whole march, so the
+    // wrapped row offsets are computed once.
+    constexpr int NW = NT / 64, WPA = NW / 4, NJ = (H + WPA - 1) / WPA;
+    static_assert(NW % 4 == 0, "four equal groups of copying waves");
     const int rl = (w + 4) / CPL;                     // active lanes per row
     const uint32_t lxo = (uint32_t)wrapn(x0 - 2 + lane * CPL, nx) * CS;
-    // dst(k): LDS array of C0, C1, D0, D1 (k = 0..3)
-    auto copy_rows = [&](int pc, int pd, bool with_c, auto dst_of) {
-        const size_t Pc = (size_t)wrapn(pc, nz) * plane, Pd = (size_t)wrapn(pd, nz) * plane;
-        for (int item = wv; item < 4 * H; item += NT / 64) {
-            const int k = item / H, yy = item % H;
-            if (yy >= h + 4 || (k < 2 && !with_c)) continue;
-            const C *src = (k < 2 ? in[4 + k] + Pc : in[4 + k] + Pd) + (size_t)wrapn(y0 + yy - 2, ny) * nx;
-            if (lane < rl) g2lds16((const char *)src + lxo, dst_of(k) + yy * W);
+    const int ck = wv / WPA, cy0 = wv % WPA;
+    const C *csrc = ck == 0 ? in[4] : ck == 1 ? in[5] : ck == 2 ? in[6] : in[7];
+    uint32_t croff[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) croff[j] = (uint32_t)wrapn(y0 + cy0 + WPA * j - 2, ny) * (uint32_t)nx * CS;
+    // pcb, pdb: byte offsets of the C and the D plane; dst: this wave's LDS array
+    auto copy_rows = [&](size_t pcb, size_t pdb, bool with_c, C *dst) {
+        if (ck < 2 && !with_c) return;
+        const char *base = (const char *)csrc + (ck < 2 ? pcb : pdb);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int yy = cy0 + WPA * j;
+            if (yy < h + 4 && lane < rl) g2lds16(base + croff[j] + lxo, dst + yy * W);
         }
     };
 
@@ -190,16 +212,20 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     double nrm[2] = {0.0, 0.0};
 
     const int ps = z0 - 3, pe = z1 + 2;
+    // wrapped indices of planes p-3 .. p+2 along the march, advanced by one per plane
+    int km3 = wrapn(ps - 3, nz);
+    int km2 = wrap_inc(km3, nz), km1 = wrap_inc(km2, nz), k0 = wrap_inc(km1, nz);
+    int kp1 = wrap_inc(k0, nz), kp2 = wrap_inc(kp1, nz);
     {
         // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
-        copy_rows(ps, ps, true, [&](int k) { return old_(k); });
-        copy_rows(ps, ps + 1, false, [&](int k) { return old_(2 + k); });
-        const size_t Pm = (size_t)wrapn(ps - 1, nz) * plane, P0 = (size_t)wrapn(ps, nz) * plane;
+        copy_rows(pofs(k0), pofs(k0), true, old_(ck));
+        copy_rows(pofs(k0), pofs(kp1), false, old_(2 + ck));
+        const size_t Pm = pofs(km1), P0 = pofs(k0);
         if (in1) {
-            cprev[0] = ld_at(in[4] + Pm, go);
-            cprev[1] = ld_at(in[5] + Pm, go);
+            cprev[0] = ld_pl(in[4], Pm, go);
+            cprev[1] = ld_pl(in[5], Pm, go);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pab[q] = ld_at(in[q] + P0, go);
+            for (int q = 0; q < 4; ++q) pab[q] = ld_pl(in[q], P0, go);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -212,18 +238,17 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         const bool more = p < pe;
         if (more) {
             // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
-            copy_rows(p + 1, p + 2, true, [&](int k) { return sStage + k * RN; });
+            copy_rows(pofs(kp1), pofs(kp2), true, sStage + ck * RN);
             if (in1) {
-                const size_t Pn = (size_t)wrapn(p + 1, nz) * plane;
+                const size_t Pn = pofs(kp1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) pabn[q] = ld_at(in[q] + Pn, go);
+                for (int q = 0; q < 4; ++q) pabn[q] = ld_pl(in[q], Pn, go);
             }
         }
 
         // level 1: A,B of plane p after step 1
         if (in1) {
-            const int pk = wrapn(p, nz);
-            const Coef<R> kA = tcoef(tab, nz, 0, pk), kB = tcoef(tab, nz, 1, pk);
+            const Coef<R> kA = tcoef(tab, tstride, 0, k0), kB = tcoef(tab, tstride, 1, k0);
             const C *C0 = old_(0), *C1 = old_(1);
             const C *D0 = old_(2), *D1 = old_(3);
             const C *D0n = old_(4), *D1n = old_(5);
@@ -255,8 +280,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab1h1[3] = B1[i];
         }
         if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
-            const int qk = wrapn(q2, nz);
-            const Coef<R> kC = tcoef(tab, nz, 2, qk), kD = tcoef(tab, nz, 3, qk);
+            const Coef<R> kC = tcoef(tab, tstride, 2, km1), kD = tcoef(tab, tstride, 3, km1);
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab1h1[0], ab1[0], A0[i + 1], A0[i + W],
                                               ab1h1[1], ab1[1], A1[i - 1], A1[i - W],
@@ -277,8 +301,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             cd1h1[3] = D1[i];
         }
         if (in2 && q3 >= z0 - 1 && q3 <= z1) {
-            const int qk = wrapn(q3, nz);
-            const Coef<R> kA = tcoef(tab, nz, 0, qk), kB = tcoef(tab, nz, 1, qk);
+            const Coef<R> kA = tcoef(tab, tstride, 0, km2), kB = tcoef(tab, tstride, 1, km2);
             const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
                                               cd1h1[0], cd1h2[0], C0[i + 1], C0[i + W],
                                               cd1h1[1], cd1h2[1], C1[i - W], C1[i - 1],
@@ -289,9 +312,9 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab2[2] = update(ab1h2[2], S.s2, kB);
             ab2[3] = update(ab1h2[3], S.s3, kB);
             if (in4 && q3 >= z0 && q3 < z1) {
-                const size_t Pq = (size_t)qk * plane;
+                const size_t Pq = pofs(km2);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) st_at(out[q] + Pq, go, ab2[q]);
+                for (int q = 0; q < 4; ++q) st_pl(out[q], Pq, go, ab2[q]);
                 if constexpr (NORM) {
                     double pp = 0.0;
 #pragma unroll
@@ -312,8 +335,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab2h1[3] = B21[i];
         }
         if (in4 && q4 >= z0 && q4 < z1) {
-            const int qk = wrapn(q4, nz);
-            const Coef<R> kC = tcoef(tab, nz, 2, qk), kD = tcoef(tab, nz, 3, qk);
+            const Coef<R> kC = tcoef(tab, tstride, 2, km3), kD = tcoef(tab, tstride, 3, km3);
             const C *A0 = A20, *A1 = A21, *B0 = B20, *B1 = B21;
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab2h1[0], ab2[0], A0[i + 1], A0[i + W],
@@ -325,9 +347,9 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             o[1] = update(cd1h2[1], S.s1, kC);
             o[2] = update(cd1h2[2], S.s2, kD);
             o[3] = update(cd1h2[3], S.s3, kD);
-            const size_t Pq = (size_t)qk * plane;
+            const size_t Pq = pofs(km3);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) st_at(out[4 + q] + Pq, go, o[q]);
+            for (int q = 0; q < 4; ++q) st_pl(out[4 + q], Pq, go, o[q]);
             if constexpr (NORM) {
                 // E_r in its C,D-summed form: |Y|^2 + Re conj(Y) S_Y(A,B)
                 const C sv[4] = {S.s0, S.s1, S.s2, S.s3};
@@ -375,6 +397,12 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         cprev[1] = cown[1];
         dprev[0] = down[0];
         dprev[1] = down[1];
+        km3 = km2;
+        km2 = km1;
+        km1 = k0;
+        k0 = kp1;
+        kp1 = kp2;
+        kp2 = wrap_inc(kp2, nz);
         __syncthreads();
     }
 
@@ -426,6 +454,8 @@ bool fused3x2_supported(int nx, bool fp32, bool site) { return !site && (!fp32 |
 template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStream_t s, int *nblocks_out) {
     FusedArgs<R> a = a0;
     if (a.tab == nullptr || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
+    // plane byte offsets are 32-bit inside the kernel
+    if ((uint64_t)a.nx * (uint64_t)a.ny * sizeof(cx<R>) >= (1ull << 32)) return hipErrorInvalidValue;
     constexpr int TW = sizeof(R) == 4 ? 64 : 32, TY = 8, NT = sizeof(R) == 4 ? 1024 : 512;
     a.ntx = (a.nx + TW - 1) / TW;
     a.nty = (a.ny + TY - 1) / TY;
