@@ -37,6 +37,8 @@ template <typename R> struct FusedArgs {
     int npart_cap;        // capacity of npart in workgroups
     int zh;               // z-slab mode: halo planes per side (arrays hold nz + 2 zh planes,
                           // interior planes zh .. zh + nz - 1, no wrap in z); 0 = periodic
+    int px;               // two-step 3D kernel: tiles across one XCD's concurrent patch
+                          // (0 = whole tile rows); set by its launcher
 };
 
 // Reduction launch over a single lattice.
