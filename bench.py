@@ -450,9 +450,9 @@ def bench_links2d(n, steps):
 def bench_slab3d(steps):
     """One device's share of the 512^3 headline lattice split into 8 z-slabs: a
     512 x 512 x 64 slab (complex64) with two halo planes per side, stepped by the
-    one-step kernel, halos filled before every step (here from the slab's own
-    opposite boundary: a one-slab decomposition, the same bytes a device would
-    receive from its neighbours)."""
+    two-step kernel (the two halo planes serve two steps), halos refilled after
+    every launch (here from the slab's own opposite boundary: a one-slab
+    decomposition, the same bytes a device would receive from its neighbours)."""
     import torch
 
     import paper_1309_3452_amd as P
@@ -467,36 +467,42 @@ def bench_slab3d(steps):
     del st
     torch.cuda.empty_cache()
     e0 = sl.norm()
-    sl.step(2)
     lat = sl.parts[0]
+    k = lat.halo_steps
+    sl.step(2 * k)
     stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    launches = steps // k
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(launches)]
     torch.cuda.synchronize()
-    for q in range(steps):
+    for q in range(launches):
         ev[q][0].record(stream)
-        lat.step(1)
+        lat.step(k)
         ev[q][1].record(stream)
         sl.exchange()
         ev[q][2].record(stream)
     torch.cuda.synchronize()
-    k_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
-    x_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    k_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / launches
+    x_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / launches
     e1 = sl.norm()
     cells = n * n * nzs
     plane = n * n * 8
-    alg = 128.0 * cells
+    alg = 128.0 * cells * k
+    ms = (k_ms + x_ms) / k
     return {"metric": "site-updates/s of one device's z-slab (512x512x64 of a 512^3 lattice over 8 devices), complex64",
-            "value": cells / ((k_ms + x_ms) * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
-            "warmup": 2, "ms_per_step": k_ms + x_ms, "higher_is_better": True, "scaling": "weak",
+            "value": cells / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": launches * k,
+            "warmup": 2 * k, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "(3+1)D z-slab 512x512x64 + 2 halo planes per side, headline physics, "
-                                   "one-step kernel, halo fill on the device", "cells": cells},
-            "slab_kernel_ms_per_step": k_ms, "halo_fill_ms_per_step": x_ms,
+                                   "%d step(s) per launch and per halo refill, refill on the device" % k,
+                       "cells": cells, "steps_per_refill": k},
+            "slab_kernel_ms_per_launch": k_ms, "halo_fill_ms_per_refill": x_ms,
+            "slab_kernel_ms_per_step": k_ms / k, "halo_fill_ms_per_step": x_ms / k,
             "roofline": {"bound": "hbm", "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k3_fused<float> in z-slab mode"},
-            "halo": {"bytes_per_face_filled": 8 * 2 * plane, "bytes_per_face_read_by_kernel": 10 * plane,
-                     "xgmi_link_GBs": 153.0, "modeled_link_ms_per_face": 10 * plane / 153e9 * 1e3},
+                         "kernel": "k3_fused2<float> in z-slab mode" if k == 2 else "k3_fused<float> in z-slab mode",
+                         "steps_per_launch": k},
+            "halo": {"bytes_per_face_filled": 8 * 2 * plane, "refills_per_step": 1.0 / k, "xgmi_link_GBs": 153.0,
+                     "modeled_link_ms_per_face": 8 * 2 * plane / 153e9 * 1e3},
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
 
 

@@ -65,12 +65,16 @@ enum dirac_status {
  * space into sub-domains that trade boundary values).  Every bound array
  * (state, per-site fields) holds nz + 4 planes: two halo planes below, the nz
  * interior planes, two halo planes above; V(z) tables take nz + 4 entries, one
- * per stored plane.  z is not periodic: a step reads the halo planes and writes
- * the interior only, so before each step the caller fills the halos of the
- * current buffer set with the neighbouring slabs' outermost two interior planes
- * (all 8 arrays).  Steps use the one-step fused kernel (the state moves to the
- * other buffer set each step); dirac_step_norm and dirac_norm sum the interior
- * (slab sums add up to the whole lattice's).  dirac_reverse, dirac_observables,
+ * per stored plane.  z is not periodic: a call of dirac_step reads the halo
+ * planes and writes the interior only, so before each call the caller fills
+ * the halos of the current buffer set with the neighbouring slabs' outermost
+ * two interior planes (all 8 arrays).  With V(z) tables (and nx even for
+ * complex64) a call may advance two steps in one launch of the two-step kernel,
+ * whose reach in z over two steps is the two halo planes; otherwise (per-site
+ * coefficients, or DIRAC_KERNEL_FUSED set) one step by the one-step kernel.
+ * dirac_halo_steps tells which; a larger n is refused (DIRAC_E_ARG).  Each
+ * launch moves the state to the other buffer set.  dirac_step_norm and
+ * dirac_norm sum the interior (slab sums add up to the whole lattice's).  dirac_reverse, dirac_observables,
  * dirac_seed_region, dirac_adjoint_vz and links are refused (DIRAC_E_STATE).
  */
 #define DIRAC_SLAB_Z 2u
@@ -125,6 +129,12 @@ int dirac_current(const dirac_ctx *ctx, int *which);
 /* Declare which bound buffer set holds the current state (after the caller
  * wrote a new state into it). */
 int dirac_set_current(dirac_ctx *ctx, int which);
+
+/* z-slab mode: *steps = the most steps one dirac_step / dirac_step_norm call
+ * may advance between halo refills (2 when the two-step kernel applies, else
+ * 1); 0 for other contexts (no limit).  Makes no HIP call; DIRAC_E_ARG for
+ * null arguments. */
+int dirac_halo_steps(const dirac_ctx *ctx, int *steps);
 
 /*
  * Scratch for reductions and gradients.  dirac_scratch_bytes reports the size

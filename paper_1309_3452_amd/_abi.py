@@ -23,7 +23,7 @@ STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SHAPE", -3: "DIRAC_E_UN
 #: every entry point of include/dirac.h
 EXPORTS = (
     "dirac_status_string", "dirac_create", "dirac_destroy", "dirac_last_error", "dirac_bind_state",
-    "dirac_current", "dirac_set_current", "dirac_scratch_bytes", "dirac_bind_scratch",
+    "dirac_current", "dirac_set_current", "dirac_halo_steps", "dirac_scratch_bytes", "dirac_bind_scratch",
     "dirac_set_mass_potential_z", "dirac_theta_from_fields", "dirac_set_theta_field", "dirac_set_kernel",
     "dirac_step", "dirac_step_norm", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
@@ -59,6 +59,7 @@ def lib():
         "dirac_bind_state": ([P, PP, PP], I),
         "dirac_current": ([P, ctypes.POINTER(I)], I),
         "dirac_set_current": ([P, I], I),
+        "dirac_halo_steps": ([P, ctypes.POINTER(I)], I),
         "dirac_scratch_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
         "dirac_bind_scratch": ([P, P, ctypes.c_size_t], I),
         "dirac_set_mass_potential_z": ([P, D, P, P, I64], I),

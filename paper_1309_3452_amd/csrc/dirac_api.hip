@@ -262,12 +262,19 @@ template <typename R> FusedArgs<R> fused_args(dirac_ctx *c) {
 }
 
 int kernel_choice(const dirac_ctx *c) {
-    if (c->zh) return DIRAC_KERNEL_FUSED;          // z-slab mode: the one-step march only
+    // the fused kernels address a plane with 32-bit byte offsets
+    const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
+    if (c->zh) {
+        // z-slab mode: the two-step march where it applies (the two halo planes
+        // serve two steps), else the one-step march; never the split kernels
+        if (c->kernel != DIRAC_KERNEL_FUSED && plane_bytes < (1ull << 32) &&
+            fused3x2_supported((int)c->nx, c->dtype == DIRAC_C64, c->site_mode))
+            return DIRAC_KERNEL_FUSED2;
+        return DIRAC_KERNEL_FUSED;
+    }
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
     // links: the link marches (one step per launch)
     if (c->links_on) return DIRAC_KERNEL_FUSED;
-    // the fused kernels address a plane with 32-bit byte offsets
-    const uint64_t plane_bytes = (uint64_t)c->nx * (uint64_t)c->ny * (c->dtype == DIRAC_C64 ? 8u : 16u);
     if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
     if (c->kernel == DIRAC_KERNEL_FUSED) return DIRAC_KERNEL_FUSED;
     if (c->ndim == 3 && fused3x2_supported((int)c->nx, c->dtype == DIRAC_C64, c->site_mode))
@@ -279,6 +286,16 @@ int kernel_choice(const dirac_ctx *c) {
         (c->kernel == DIRAC_KERNEL_FUSED2 || c->nx * c->ny >= (int64_t)1 << 18))
         return DIRAC_KERNEL_FUSED2;
     return DIRAC_KERNEL_FUSED;
+}
+
+// z-slab mode: the most steps one call may advance between halo refills
+int halo_steps(const dirac_ctx *c) { return kernel_choice(c) == DIRAC_KERNEL_FUSED2 ? 2 : 1; }
+
+int slab_step_check(dirac_ctx *c, int64_t n) {
+    if (c->zh && n > halo_steps(c))
+        return fail(c, DIRAC_E_ARG, halo_steps(c) == 2 ? "z-slab mode: at most 2 steps per call, halos refilled between calls"
+                                                       : "z-slab mode: 1 step per call, halos refilled between calls");
+    return DIRAC_OK;
 }
 
 LinkPtrs link_ptrs(const dirac_ctx *c) {
@@ -446,6 +463,12 @@ int dirac_set_current(dirac_ctx *c, int which) {
     return DIRAC_OK;
 }
 
+int dirac_halo_steps(const dirac_ctx *c, int *steps) {
+    if (!c || !steps) return DIRAC_E_ARG;
+    *steps = (!c->is_batch && c->zh) ? halo_steps(c) : 0;
+    return DIRAC_OK;
+}
+
 int dirac_scratch_bytes(const dirac_ctx *c, size_t *bytes) {
     if (!c || !bytes) return DIRAC_E_ARG;
     *bytes = c->is_batch ? c->batch_scratch_need : scratch_need(c);
@@ -598,6 +621,8 @@ int dirac_step(dirac_ctx *c, int64_t n, void *stream) {
     int rc = check_ready(c, !c || !c->site_mode);
     if (rc) return rc;
     if (n < 0) return fail(c, DIRAC_E_ARG, "n must be >= 0");
+    rc = slab_step_check(c, n);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     return c->dtype == DIRAC_C64 ? run_steps<float>(c, n, false, s) : run_steps<double>(c, n, false, s);
 }
@@ -615,6 +640,8 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
     int rc = check_ready(c, true);
     if (rc) return rc;
     if (n < 1 || !dev_out) return fail(c, DIRAC_E_ARG, "need n >= 1 and an output");
+    rc = slab_step_check(c, n);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     double *part = (double *)scratch_at(c, off_partial(c));
     const int cap = (kReduceBlocks * kObsVals) / 2;

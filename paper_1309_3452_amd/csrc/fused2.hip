@@ -164,12 +164,21 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     // per-wave copy bookkeeping below runs on the scalar unit
     const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    // z-slab mode: zh halo planes stored on each side of the nz interior ones
+    // and no wrap in z; nzt planes (and table entries) are stored
+    const int zh = a.zh, nzt = nz + 2 * zh;
     constexpr uint32_t CS = sizeof(C);
     // bytes of one plane (below 4 GiB, checked by the launcher) and of one
     // class of the coefficient table
     const uint32_t pbytes = (uint32_t)nx * (uint32_t)ny * CS;
-    const uint32_t tstride = (uint32_t)nz * (uint32_t)(4 * sizeof(R));
+    const uint32_t tstride = (uint32_t)nzt * (uint32_t)(4 * sizeof(R));
     auto pofs = [&](int k) -> size_t { return (size_t)(uint32_t)k * (size_t)pbytes; };
+    // stored index of the next plane, and whether a stored index exists (a
+    // slab's march passes two planes beyond its halo on each side; what is
+    // computed from those planes reaches no stored value)
+    auto next_k = [&](int k) { return zh == 0 ? wrap_inc(k, nz) : k + 1; };
+    auto valid = [&](int k) { return (unsigned)k < (unsigned)nzt; };
+    auto tk = [&](int k) { return valid(k) ? k : 0; };
 
     // the region cell of this thread: (xr, yr) relative to the tile origin
     int xr, yr;
@@ -205,10 +214,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     uint32_t croff[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) croff[j] = (uint32_t)wrapn(y0 + cy0 + WPA * j - 2, ny) * (uint32_t)nx * CS;
-    // pcb, pdb: byte offsets of the C and the D plane; dst: this wave's LDS array
-    auto copy_rows = [&](size_t pcb, size_t pdb, bool with_c, C *dst) {
-        if (ck < 2 && !with_c) return;
-        const char *base = (const char *)csrc + (ck < 2 ? pcb : pdb);
+    // kc, kd: stored indices of the C and the D plane (C skipped if !with_c,
+    // either skipped if not stored); dst: this wave's LDS array
+    auto copy_rows = [&](int kc, int kd, bool with_c, C *dst) {
+        if (ck < 2 ? (!with_c || !valid(kc)) : !valid(kd)) return;
+        const char *base = (const char *)csrc + pofs(ck < 2 ? kc : kd);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const int yy = cy0 + WPA * j;
@@ -232,18 +242,20 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     double nrm[2] = {0.0, 0.0};
 
     const int ps = z0 - 3, pe = z1 + 2;
-    // wrapped indices of planes p-3 .. p+2 along the march, advanced by one per plane
-    int km3 = wrapn(ps - 3, nz);
-    int km2 = wrap_inc(km3, nz), km1 = wrap_inc(km2, nz), k0 = wrap_inc(km1, nz);
-    int kp1 = wrap_inc(k0, nz), kp2 = wrap_inc(kp1, nz);
+    // stored indices of planes p-3 .. p+2 along the march, advanced by one per plane
+    int km3 = zh == 0 ? wrapn(ps - 3, nz) : ps - 3 + zh;
+    int km2 = next_k(km3), km1 = next_k(km2), k0 = next_k(km1);
+    int kp1 = next_k(k0), kp2 = next_k(kp1);
     {
         // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
-        copy_rows(pofs(k0), pofs(k0), true, old_(ck));
-        copy_rows(pofs(k0), pofs(kp1), false, old_(2 + ck));
+        copy_rows(k0, k0, true, old_(ck));
+        copy_rows(k0, kp1, false, old_(2 + ck));
         const size_t Pm = pofs(km1), P0 = pofs(k0);
-        if (in1) {
+        if (in1 && valid(km1)) {
             cprev[0] = ld_pl(in[4], Pm, go);
             cprev[1] = ld_pl(in[5], Pm, go);
+        }
+        if (in1 && valid(k0)) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) pab[q] = ld_pl(in[q], P0, go);
         }
@@ -258,8 +270,8 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         const bool more = p < pe;
         if (more) {
             // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
-            copy_rows(pofs(kp1), pofs(kp2), true, sStage + ck * RN);
-            if (in1) {
+            copy_rows(kp1, kp2, true, sStage + ck * RN);
+            if (in1 && valid(kp1)) {
                 const size_t Pn = pofs(kp1);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) pabn[q] = ld_pl(in[q], Pn, go);
@@ -268,7 +280,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
 
         // level 1: A,B of plane p after step 1
         if (in1) {
-            const Coef<R> kA = tcoef(tab, tstride, 0, k0), kB = tcoef(tab, tstride, 1, k0);
+            const Coef<R> kA = tcoef(tab, tstride, 0, tk(k0)), kB = tcoef(tab, tstride, 1, tk(k0));
             const C *C0 = old_(0), *C1 = old_(1);
             const C *D0 = old_(2), *D1 = old_(3);
             const C *D0n = old_(4), *D1n = old_(5);
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab1h1[3] = B1[i];
         }
         if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
-            const Coef<R> kC = tcoef(tab, tstride, 2, km1), kD = tcoef(tab, tstride, 3, km1);
+            const Coef<R> kC = tcoef(tab, tstride, 2, tk(km1)), kD = tcoef(tab, tstride, 3, tk(km1));
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab1h1[0], ab1[0], A0[i + 1], A0[i + W],
                                               ab1h1[1], ab1[1], A1[i - 1], A1[i - W],
@@ -321,7 +333,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             cd1h1[3] = D1[i];
         }
         if (in2 && q3 >= z0 - 1 && q3 <= z1) {
-            const Coef<R> kA = tcoef(tab, tstride, 0, km2), kB = tcoef(tab, tstride, 1, km2);
+            const Coef<R> kA = tcoef(tab, tstride, 0, tk(km2)), kB = tcoef(tab, tstride, 1, tk(km2));
             const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
                                               cd1h1[0], cd1h2[0], C0[i + 1], C0[i + W],
                                               cd1h1[1], cd1h2[1], C1[i - W], C1[i - 1],
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab2h1[3] = B21[i];
         }
         if (in4 && q4 >= z0 && q4 < z1) {
-            const Coef<R> kC = tcoef(tab, tstride, 2, km3), kD = tcoef(tab, tstride, 3, km3);
+            const Coef<R> kC = tcoef(tab, tstride, 2, tk(km3)), kD = tcoef(tab, tstride, 3, tk(km3));
             const C *A0 = A20, *A1 = A21, *B0 = B20, *B1 = B21;
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab2h1[0], ab2[0], A0[i + 1], A0[i + W],
@@ -422,7 +434,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         km1 = k0;
         k0 = kp1;
         kp1 = kp2;
-        kp2 = wrap_inc(kp2, nz);
+        kp2 = next_k(kp2);
         __syncthreads();
     }
 

@@ -89,6 +89,14 @@ class Lattice:
         check(lib().dirac_current(self._ctx, ctypes.byref(w)), self._ctx)
         return int(w.value)
 
+    @property
+    def halo_steps(self) -> int:
+        """z-slab mode: the most steps one step() call may advance between halo
+        refills (2 with the two-step kernel, else 1); 0 otherwise."""
+        k = ctypes.c_int()
+        check(lib().dirac_halo_steps(self._ctx, ctypes.byref(k)), self._ctx)
+        return int(k.value)
+
     def state(self):
         """The tensors currently holding the state (views, not copies)."""
         return self.bufs[self.current]

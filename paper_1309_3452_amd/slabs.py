@@ -1,12 +1,13 @@
 """A periodic (3+1)D lattice split into z-slabs, the unit a multi-GPU run gives
 each device (the paper's closing remark: sub-domains handled separately that
 trade boundary values).  Each slab is a z-slab-mode lattice (DIRAC_SLAB_Z):
-nz/S interior planes plus two halo planes on each side.  Before every step the
-halos of each slab's current buffers are filled with its neighbours' outermost
-two interior planes; with several GPUs those copies are the point-to-point
-sends and receives of the same planes, here they are device copies on the
-current stream.  Stepping the slabs gives the bits of the whole periodic
-lattice stepped by the one-step fused kernel.
+nz/S interior planes plus two halo planes on each side.  Each slab advances
+as many steps as its halos allow (two per launch of the two-step kernel with
+V(z) tables, else one), after which the halos of every slab's current buffers
+are refilled with its neighbours' outermost two interior planes; with several
+GPUs those copies are the point-to-point sends and receives of the same
+planes, here they are device copies on the current stream.  Stepping the slabs
+gives the bits of the whole periodic lattice stepped by the fused kernels.
 """
 from __future__ import annotations
 
@@ -66,11 +67,24 @@ class SlabDecomposition:
                 cur[s][a][0:HALO].copy_(below[a][n:n + HALO])
                 cur[s][a][n + HALO:n + 2 * HALO].copy_(above[a][HALO:2 * HALO])
 
+    def set_kernel(self, kind: str = "auto", zchunk: int = 0):
+        """"auto" (two steps per halo refill where the two-step kernel applies) or "fused" (one)."""
+        for lat in self.parts:
+            lat.set_kernel(kind, 0, zchunk)
+
+    @property
+    def halo_steps(self) -> int:
+        """Steps between halo refills (1 or 2)."""
+        return self.parts[0].halo_steps
+
     def step(self, n: int = 1):
-        for _ in range(int(n)):
+        n, k = int(n), self.halo_steps
+        while n > 0:
+            m = min(k, n)
             for lat in self.parts:
-                lat.step(1)
+                lat.step(m)
             self.exchange()
+            n -= m
 
     def norm(self):
         """(E_r, E_r on the C,D sites, plain norm) of the whole lattice: the slabs' sums added."""
