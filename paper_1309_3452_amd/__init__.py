@@ -11,6 +11,9 @@ from .lattice import Lattice, Lattice2D, Lattice3D  # noqa: F401
 from .batch import BatchedLattices  # noqa: F401
 from .autograd import DiracLoss, potential_gradient  # noqa: F401
 from .slabs import SlabDecomposition  # noqa: F401
+from .checkpoint import load_checkpoint, save_checkpoint  # noqa: F401
+from .watch import DriftError, run_watched  # noqa: F401
 
 __all__ = ["Lattice", "Lattice2D", "Lattice3D", "BatchedLattices", "DiracLoss", "potential_gradient",
-           "SlabDecomposition", "DiracError", "lib"]
+           "SlabDecomposition", "DiracError", "lib", "save_checkpoint", "load_checkpoint", "DriftError",
+           "run_watched"]

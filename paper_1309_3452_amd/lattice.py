@@ -48,7 +48,9 @@ class Lattice:
         self.dtype = dtype
         self.real_dtype = torch.float32 if dtype == torch.complex64 else torch.float64
         self.dt = float(dt)
-        d = tuple(d) if d is not None else (1.0,) * self.ndim
+        d = tuple(float(x) for x in d) if d is not None else (1.0,) * self.ndim
+        self.d = d
+        self.allow_unstable = bool(allow_unstable)
         self.device = torch.device(device)
         self.narr = 8 if self.ndim == 3 else 4
         self.zh = 2 if slab else 0
@@ -71,6 +73,11 @@ class Lattice:
         aligned = (base + 255) & ~255
         check(lib().dirac_bind_scratch(ctx, ctypes.c_void_p(aligned), int(nbytes.value)), ctx)
         self.theta = None
+        # what the coefficients were last set from (kept for checkpoints): V(z)
+        # tables with mass m (None: V = 0), per-site records, absorbing tables
+        self._coef = {"mode": "vz", "m": 0.0, "vz": None}
+        self._wz = None
+        self._links = None
         self._norm_out = torch.zeros(3, dtype=torch.float64, device=self.device)
 
     def __del__(self):
@@ -117,6 +124,8 @@ class Lattice:
         """Mass m and V(z) sampled at integer (v_int) and half-integer (v_half) z."""
         if v_int is None:
             check(lib().dirac_set_mass_potential_z(self._ctx, float(m), None, None, self.nplanes), self._ctx)
+            self._coef = {"mode": "vz", "m": float(m), "vz": None}
+            self.theta = None
             return
         import numpy as np
         vi = np.ascontiguousarray(v_int, dtype=np.float64)
@@ -126,12 +135,15 @@ class Lattice:
         check(lib().dirac_set_mass_potential_z(self._ctx, float(m), vi.ctypes.data_as(ctypes.c_void_p),
                                                vh.ctypes.data_as(ctypes.c_void_p), self.nplanes), self._ctx)
         self._pin = (vi, vh)
+        self._coef = {"mode": "vz", "m": float(m), "vz": (vi, vh)}
+        self.theta = None
 
     def set_absorber_z(self, w_int=None, w_half=None):
         """Imaginary part W(z) of the potential (absorbing layers where W < 0),
         sampled like V(z); None clears it (see dirac_set_potential_im_z)."""
         if w_int is None:
             check(lib().dirac_set_potential_im_z(self._ctx, None, None, self.nplanes), self._ctx)
+            self._wz = None
             return
         import numpy as np
         wi = np.ascontiguousarray(w_int, dtype=np.float64)
@@ -141,6 +153,7 @@ class Lattice:
         check(lib().dirac_set_potential_im_z(self._ctx, wi.ctypes.data_as(ctypes.c_void_p),
                                              wh.ctypes.data_as(ctypes.c_void_p), self.nplanes), self._ctx)
         self._pin_w = (wi, wh)
+        self._wz = (wi, wh)
 
     def set_fields(self, m: float, v_site=None, w_site=None):
         """Per-site potential: v_site[a] holds V at the sites of state array a,
@@ -167,6 +180,7 @@ class Lattice:
                 self.theta.append(rec)
                 self._fields.append((v, w))
             check(lib().dirac_set_theta_field(self._ctx, ptr_array([t.data_ptr() for t in self.theta])), self._ctx)
+            self._coef = {"mode": "site", "m": float(m)}
             return
         self.theta = [torch.empty(self.tshape, dtype=cdt, device=self.device) for _ in range(self.narr)]
         vs = None
@@ -176,6 +190,27 @@ class Lattice:
         check(lib().dirac_theta_from_fields(
             self._ctx, float(m), ptr_array([v.data_ptr() for v in vs]) if vs is not None else None,
             ptr_array([t.data_ptr() for t in self.theta]), _stream_handle()), self._ctx)
+        self._coef = {"mode": "site", "m": float(m)}
+
+    @property
+    def coef_dtype(self):
+        """Element type of the per-site coefficient records: theta (float64) for
+        complex128 lattices, gamma = 1 - alpha (complex64) for complex64 ones."""
+        return torch.complex64 if self.dtype == torch.complex64 else torch.float64
+
+    def set_coef_records(self, records):
+        """Bind per-site coefficient records already in the kernels' format
+        (narr tensors of the state's shape and coef_dtype; see
+        dirac_set_theta_field), e.g. those of another lattice or a checkpoint."""
+        if len(records) != self.narr:
+            raise ValueError("expected %d record arrays" % self.narr)
+        recs = [torch.as_tensor(r).to(device=self.device, dtype=self.coef_dtype).contiguous() for r in records]
+        for r in recs:
+            if tuple(r.shape) != self.tshape:
+                raise ValueError("record shape %s != %s" % (tuple(r.shape), self.tshape))
+        check(lib().dirac_set_theta_field(self._ctx, ptr_array([r.data_ptr() for r in recs])), self._ctx)
+        self.theta = recs
+        self._coef = {"mode": "site", "m": None}
 
     def set_links(self, links=None):
         """Gauge links of a vector potential (Sect. 4): 24 (3D) or 8 (2D) tensors
