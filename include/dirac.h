@@ -253,7 +253,8 @@ int dirac_coef_from_fields(void *coef, int dtype, double dt, double sgn_m, const
  *   tile_y: cells along y per workgroup of the 3D one-step fused kernel: 4 or 8
  *           (default 8); its tile is 64 cells in x (128 for complex64 with nx even)
  *   zchunk: planes (3D) or rows (2D) per workgroup along the march of the fused
- *           kernels (default: enough chunks for ~1024 workgroups)
+ *           kernels (default: chosen per kernel and lattice from the number of
+ *           workgroups the device runs at once and each chunk's pipeline fill)
  * The two-step kernel uses 64 x 8 tiles (complex64) or 32 x 8 (complex128).
  * Every kernel gives the same bits.  The reversed step and the adjoint always
  * use the split kernels. */
