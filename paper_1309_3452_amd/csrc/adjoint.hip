@@ -46,7 +46,13 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
     using C = cx<R>;
     __shared__ double lds[2 * 16];
     const int nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
+    // consecutive blocks go to the 8 XCDs in turn; for complex64 remap them so
+    // that each XCD takes a contiguous range of planes, whose y and z
+    // neighbours then sit in its L2 (128^3 backward: 66.5 -> 53.8 ms for 400
+    // steps; complex128 measured 135 -> 141 ms with the remap, so it keeps the
+    // plain order)
     int b = blockIdx.x;
+    if (sizeof(R) == 4 && (gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
     const int bx = b % nbx;
     b /= nbx;
     const int by = b % nby;
