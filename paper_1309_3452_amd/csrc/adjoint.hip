@@ -14,7 +14,10 @@
 //   sweep 2 (C,D sites): lamY <- conj(alpha2) lamY + K2(beta1 lamX)
 // (in sweep 2, conj(beta1) times the unscaled lamX equals beta1 times the
 // stored conj(alpha1) lamX, since conj(beta) alpha = beta for real theta).
-// dY+/dtheta = -i (Y+ + Y-) beta.  Per-(tile, plane) FP64 sums are
+// dY+/dtheta = -i (Y+ + Y-) beta.  Sweep 2 of one backward step and sweep 0
+// of the next act on the same C,D site and read only A,B values written
+// before them (lamX and X- at the neighbours), so they run as one launch
+// (sweep 3): lamY is then read and written once for both.  Per-(tile, plane) FP64 sums are
 // accumulated in place by the one workgroup owning them: no atomics, so the
 // gradient is bitwise reproducible.
 #include "device.h"
@@ -120,6 +123,7 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
                 l[q][c] = cmulc(alpha_of(kf), lx);
             }
         } else {
+            // (sweep 2, and sweep 3's first half)
             // u = beta1 lamX (stored, already scaled) at every A,B value the C,D stencil reads
             auto u = [&](int arr, size_t idx, int kpl) -> C {
                 return cmul(tcoef(a.tab_f, arr / 2, a.nz, kpl).c2, l[arr][idx]);
@@ -129,15 +133,34 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
                                         u(2, c, k), u(2, zm, km), u(2, xm, k), u(2, yp, k),
                                         u(3, c, k), u(3, zm, km), u(3, xp, k), u(3, ym, k));
             C ss[4] = {s.s0, s.s1, s.s2, s.s3};
+            C lyn[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int cls = 2 + q / 2;
                 Coef<R> kf = tcoef(a.tab_f, cls, a.nz, k);
-                l[4 + q][c] = cadd(cmulc(alpha_of(kf), l[4 + q][c]), ss[q]);
+                lyn[q] = cadd(cmulc(alpha_of(kf), l[4 + q][c]), ss[q]);
             }
+            if constexpr (SWEEP == 3) {
+                // sweep 0 of the next backward step at the same site, with the new lamY
+                St3<C> s0 = stencil_cd<C, R>(rx, ry, rz, f[0][c], f[0][zp], f[0][xp], f[0][yp], f[1][c], f[1][zp],
+                                             f[1][xm], f[1][ym], f[2][c], f[2][zm], f[2][xm], f[2][yp], f[3][c],
+                                             f[3][zm], f[3][xp], f[3][ym]);
+                C ss0[4] = {s0.s0, s0.s1, s0.s2, s0.s3};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cls = 2 + q / 2;
+                    Coef<R> kf = tcoef(a.tab_f, cls, a.nz, k), kr = tcoef(a.tab_r, cls, a.nz, k);
+                    C yp_ = f[4 + q][c];
+                    C ym_ = update(yp_, mk2(-ss0[q].x, -ss0[q].y), kr);
+                    g[cls == 2 ? 1 : 0] += dtheta_term(lyn[q], yp_, ym_, kf);
+                    f[4 + q][c] = ym_;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) l[4 + q][c] = lyn[q];
         }
     }
-    if constexpr (SWEEP < 2) {
+    if constexpr (SWEEP != 2) {
         block_sum<2>(g, lds);
         if (threadIdx.x == 0) {
             double *o = a.gpart + ((size_t)tile * a.nz + k) * 2;
@@ -178,7 +201,8 @@ template <typename R> hipError_t launch_adj3(const AdjArgs<R> &a, int sweep, hip
     dim3 g((unsigned)nblk), b(kTX * kTY);
     if (sweep == 0) hipLaunchKernelGGL((k3_adj<R, 0>), g, b, 0, s, a);
     else if (sweep == 1) hipLaunchKernelGGL((k3_adj<R, 1>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k3_adj<R, 2>), g, b, 0, s, a);
+    else if (sweep == 2) hipLaunchKernelGGL((k3_adj<R, 2>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k3_adj<R, 3>), g, b, 0, s, a);
     return hipGetLastError();
 }
 

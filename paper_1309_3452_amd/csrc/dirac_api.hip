@@ -823,8 +823,13 @@ int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int,
         a.ny = (int)c->ny;
         a.nz = (int)c->nz;
         a.gpart = gpart;
-        for (int64_t t = 0; t < n; ++t)
-            for (int sw = 0; sw < 3; ++sw) HIPCHK(c, launch_adj3<R>(a, sw, s));
+        // sweeps 0, 1, 2 per backward step; sweep 2 of a step and sweep 0 of the
+        // next run as one launch (sweep 3)
+        if (n > 0) HIPCHK(c, launch_adj3<R>(a, 0, s));
+        for (int64_t t = 0; t < n; ++t) {
+            HIPCHK(c, launch_adj3<R>(a, 1, s));
+            HIPCHK(c, launch_adj3<R>(a, t + 1 < n ? 3 : 2, s));
+        }
         return DIRAC_OK;
     };
     rc = c->dtype == DIRAC_C64 ? run(0.0f) : run(0.0);
