@@ -521,7 +521,7 @@ hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStrea
     a.nty = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)a.ntx * a.nty;
     if (a.zchunk <= 0) {
-        const int nzc = default_chunks(tiles, a.nz, 1024);
+        const int nzc = pick_chunks(tiles, a.nz, 3);
         a.zchunk = (a.nz + nzc - 1) / nzc;
     }
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;

@@ -483,8 +483,9 @@ int chunks_for(int64_t tiles, int nz, int target) {
 
 }  // namespace
 
-// Workgroups of the two-step 3D kernel that run at once: one per CU (its LDS
-// allows one), queried once.
+// Workgroups of the 3D fused kernels that run at once: one per CU (the
+// two-step kernel's LDS allows one; the one-step kernel measured best at the
+// same count), queried once.
 int resident_per_round() {
     static int n = 0;
     if (n == 0) {
@@ -496,20 +497,21 @@ int resident_per_round() {
     return n;
 }
 
-// z-chunks per tile column of the two-step 3D march.  A chunk costs its planes
-// plus six of pipeline fill, and the workgroups run in rounds of one per CU,
-// so the count minimising rounds x (planes per chunk + 6) is taken, the
-// largest within 1% of that minimum (more workgroups balance the tail).  It
-// reproduces the best of a sweep at 128^3, 256^3, 512^3 (both precisions) and
-// a 512 x 512 x 64 slab (e.g. 128^3 complex64: 8 chunks of 16 planes, 0.045
-// ms per step against 0.074 with 32 chunks of 4).  Memoised for repeated calls.
-int pick_chunks3x2(int64_t tiles, int nz) {
+// Chunks per tile column of a 3D z-march.  A chunk costs its planes plus
+// `fill` of pipeline fill (two-step kernel 6, one-step 3), and the workgroups
+// run in rounds of one per CU, so the count minimising rounds x (planes per
+// chunk + fill) is taken, the largest within 1% of that minimum (more
+// workgroups balance the tail).  It reproduces the best of sweeps at 128^3,
+// 256^3, 512^3 (both precisions, both kernels) and a 512 x 512 x 64 slab (e.g.
+// 128^3 complex64, two-step: 8 chunks of 16 planes, 0.044 ms per step against
+// 0.074 with 32 chunks of 4).  Memoised for repeated calls.
+int pick_chunks(int64_t tiles, int nz, int fill) {
     static thread_local int64_t m_tiles = -1;
-    static thread_local int m_nz = -1, m_res = 1;
-    if (tiles == m_tiles && nz == m_nz) return m_res;
+    static thread_local int m_nz = -1, m_fill = -1, m_res = 1;
+    if (tiles == m_tiles && nz == m_nz && fill == m_fill) return m_res;
     const int64_t per = resident_per_round();
     const int64_t cap = std::min<int64_t>(nz, 8 * ((per + tiles - 1) / tiles));
-    auto cost = [&](int64_t c) { return (double)((tiles * c + per - 1) / per) * (double)((nz + c - 1) / c + 6); };
+    auto cost = [&](int64_t c) { return (double)((tiles * c + per - 1) / per) * (double)((nz + c - 1) / c + fill); };
     double best = 1e300;
     for (int64_t c = 1; c <= cap; ++c) best = std::min(best, cost(c));
     int res = 1;
@@ -517,6 +519,7 @@ int pick_chunks3x2(int64_t tiles, int nz) {
         if (cost(c) <= 1.01 * best) res = (int)c;
     m_tiles = tiles;
     m_nz = nz;
+    m_fill = fill;
     m_res = res;
     return res;
 }
@@ -533,7 +536,7 @@ template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStre
     a.nty = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)a.ntx * a.nty;
     if (a.zchunk <= 0) {
-        const int nzc = pick_chunks3x2(tiles, a.nz);
+        const int nzc = pick_chunks(tiles, a.nz, 6);
         a.zchunk = (a.nz + nzc - 1) / nzc;
     }
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;

@@ -100,6 +100,9 @@ hipError_t launch_final_sum(const double *partial, int nblocks, int nv, double *
 template <typename R> hipError_t launch_half2(const HalfArgs<R> &a, int which /*0: u  1: v*/, bool site,
                                               hipStream_t s);
 template <typename R> hipError_t launch_fused2(const FusedArgs<R> &a, bool site, hipStream_t s);
+// Chunks per tile column of a 3D z-march of `tiles` tile columns over nz planes,
+// each chunk paying `fill` planes of pipeline fill (see fused2.hip).
+int pick_chunks(int64_t tiles, int nz, int fill);
 template <typename R> hipError_t launch_norm2(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_obs2(const ReduceArgs<R> &a, hipStream_t s);
 template <typename R> hipError_t launch_seed2(const ReduceArgs<R> &a, void *const lam[8], hipStream_t s);
