@@ -256,8 +256,8 @@ int dirac_coef_from_fields(void *coef, int dtype, double dt, double sgn_m, const
  *           kernels (default: chosen per kernel and lattice from the number of
  *           workgroups the device runs at once and each chunk's pipeline fill)
  * The two-step kernel uses 64 x 8 tiles (complex64) or 32 x 8 (complex128).
- * Every kernel gives the same bits.  The reversed step and the adjoint always
- * use the split kernels. */
+ * Every kernel gives the same bits.  The reversed step always uses the split
+ * kernels, the adjoint its own in-place sweeps. */
 int dirac_set_kernel(dirac_ctx *ctx, int kernel, int tile_y, int zchunk);
 
 /*
@@ -331,7 +331,9 @@ int dirac_seed_region(dirac_ctx *ctx, double z0, void *const lam[], void *stream
  * initial state, lam the adjoint at it, and the device FP64 arrays
  * dLdV_int[nz] (V at z = k: A, D sites) and dLdV_half[nz] (V at z = k+1/2:
  * B, C sites) hold dL/dV summed over all steps (overwritten, deterministic).
- * Uses the split kernels.  Asynchronous on stream.
+ * Works in place (state and lam): three per-cell sweeps per backward step in
+ * two launches, the last sweep of a step sharing one with the first of the
+ * next.  Asynchronous on stream.
  */
 int dirac_adjoint_vz(dirac_ctx *ctx, int64_t n, void *const lam[], void *dLdV_int, void *dLdV_half,
                      void *stream);
