@@ -191,6 +191,62 @@ def test_sampled_oracle_parity_256_fp64(P):
             assert abs(box[a][R, R, R] - got[a][k, j, i]) <= 1e-13 * scale, (i, j, k, a)
 
 
+@pytest.mark.parametrize("dtype,nz,beyond,tol", [(torch.complex64, 72, 64, 3e-6), (torch.complex128, 40, 32, 1e-13)])
+def test_sampled_oracle_parity_arrays_over_4gib(P, dtype, nz, beyond, tol):
+    """Arrays larger than 4 GiB (4096 x 2048 x nz cells): 64-bit addressing in the
+    two-step and one-step kernels (3 steps, default launch).  The state is drawn on
+    the device; sub-boxes around the samples -- including cells past the 4 GiB byte
+    offset (planes >= `beyond`) and the last cell -- are cut out on the device and
+    stepped by the oracle, as in the 256^3 sampled test."""
+    nx, ny, steps, R = 4096, 2048, 3, 7
+    print("arrays over 4 GiB: %d x %d x %d %s" % (nx, ny, nz, dtype), flush=True)
+    bytes_per_array = nx * ny * nz * (8 if dtype == torch.complex64 else 16)
+    assert bytes_per_array > 4 << 30 and nx * ny * beyond * (8 if dtype == torch.complex64 else 16) >= 4 << 30
+    m, dt = 0.5, DT3
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 4.0)
+    lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=dt)
+    lat.set_potential_z(m, v_int, v_half)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4242)
+    for t in lat.state():
+        t.copy_(torch.randn(t.shape, dtype=dtype, device="cuda", generator=gen))
+    g = np.random.default_rng(23)
+    samples = [(int(g.integers(0, nx)), int(g.integers(0, ny)), int(g.integers(0, nz))) for _ in range(10)]
+    samples += [(nx - 1, ny - 1, nz - 1), (0, 0, beyond), (nx // 2, ny - 1, beyond + 1), (17, 5, nz - 1),
+                (nx - 3, 1, beyond), (0, 0, 0)]
+
+    def boxes(arrays):
+        out = []
+        for (i, j, k) in samples:
+            ix = torch.arange(i - R, i + R + 1, device="cuda") % nx
+            iy = torch.arange(j - R, j + R + 1, device="cuda") % ny
+            iz = torch.arange(k - R, k + R + 1, device="cuda") % nz
+            out.append([a.index_select(0, iz).index_select(1, iy).index_select(2, ix).cpu().numpy().astype(np.complex128)
+                        for a in arrays])
+        return out
+
+    before = boxes(lat.state())
+    lat.step(steps)
+    torch.cuda.synchronize()
+    after = [[b[a][R, R, R] for a in range(8)] for b in boxes(lat.state())]
+    del lat
+    free()
+    B = 2 * R + 1
+    ol = oracle.Lattice3(B, B, B, dt)
+    scale = max(max(abs(v) for v in row) for row in after)
+    for (i, j, k), box, got in zip(samples, before, after):
+        iz = (np.arange(k - R, k + R + 1)) % nz
+        th = []
+        for a in range(8):
+            # V at the amplitude's own z: integer sites (A, D) take v_int, half-integer (B, C) v_half
+            tab = v_int if workloads.OFF3[a][2] == 0.0 else v_half
+            sgn = 1.0 if a < 4 else -1.0
+            th.append(np.ascontiguousarray(0.5 * dt * (sgn * m + tab[iz])[:, None, None] * np.ones((1, B, B))))
+        ol.step(box, th, steps)
+        for a in range(8):
+            assert abs(box[a][R, R, R] - got[a]) <= tol * scale, (i, j, k, a)
+
+
 def test_sampled_oracle_parity_links_512_fp32(P):
     """The gauge-link workload bench.py times (512^3, complex64, Peierls links of a
     smooth vector potential): after 3 steps, sampled cells against the FP64 oracle
