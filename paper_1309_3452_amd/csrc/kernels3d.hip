@@ -138,7 +138,10 @@ __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
     const MarchMap mm = march_map(a.nx, a.ny, a.nz);
     const size_t plane = (size_t)a.nx * a.ny;
     const int x = threadIdx.x & (kTX - 1), y = threadIdx.x / kTX;
-    for (int item = blockIdx.x; item < mm.items; item += gridDim.x) {
+    // consecutive blocks go to the 8 XCDs in turn: remap so that each XCD takes
+    // a contiguous range of tiles, whose y-neighbour rows then sit in its L2
+    const int blk = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    for (int item = blk; item < mm.items; item += gridDim.x) {
         int r = item;
         const int tx = r % mm.ntx;
         r /= mm.ntx;
@@ -211,7 +214,10 @@ __global__ __launch_bounds__(kReduceThreads) void k3_obs(ReduceArgs<R> a) {
     const MarchMap mm = march_map(a.nx, a.ny, a.nz);
     const size_t plane = (size_t)a.nx * a.ny;
     const int x = threadIdx.x & (kTX - 1), y = threadIdx.x / kTX;
-    for (int item = blockIdx.x; item < mm.items; item += gridDim.x) {
+    // consecutive blocks go to the 8 XCDs in turn: remap so that each XCD takes
+    // a contiguous range of tiles, whose y-neighbour rows then sit in its L2
+    const int blk = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    for (int item = blk; item < mm.items; item += gridDim.x) {
         int r = item;
         const int tx = r % mm.ntx;
         r /= mm.ntx;
