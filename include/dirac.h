@@ -115,11 +115,14 @@ void dirac_destroy(dirac_ctx *ctx);
 const char *dirac_last_error(const dirac_ctx *ctx);
 
 /*
- * Bind the state.  buf0 and buf1 each give 8 (3D) or 4 (2D) device arrays of
- * nx*ny*nz amplitudes in the layout above.  buf0 holds the initial state;
- * buf1 is the partner the fused kernel writes into (it may alias nothing the
- * caller still needs).  The current state flips between them as fused steps
- * run; dirac_current() says where it is.
+ * Bind the state: the staggered amplitudes of Sect. 2 (A, B on sheet n-1/2,
+ * C, D on sheet n; Fig. 1) or Sect. 3 (u, v).  buf0 and buf1 each give 8 (3D)
+ * or 4 (2D) device arrays of nx*ny*nz amplitudes in the layout above.  buf0
+ * holds the initial state; buf1 is the partner the fused kernel writes into
+ * (it may alias nothing the caller still needs).  The current state flips
+ * between them as fused steps run; dirac_current() says where it is.  The
+ * arrays stay caller-owned and must outlive their use; DIRAC_E_ARG for null
+ * pointers.  No HIP call.
  */
 int dirac_bind_state(dirac_ctx *ctx, void *const buf0[], void *const buf1[]);
 
@@ -189,12 +192,15 @@ int dirac_set_potential_im_z(dirac_ctx *ctx, const double *w_int, const double *
 int dirac_theta_from_fields(dirac_ctx *ctx, double m, void *const v_site[], void *const coef[],
                             void *stream);
 
-/* Bind already computed per-site coefficient arrays (format as above). */
+/* Bind already computed per-site coefficient arrays (format as above): the
+ * time-averaged mass and potential term of Eqs. ss1-ss4 (Sect. 3 in 2D).
+ * Caller-owned, read by every later step until replaced.  No HIP call. */
 int dirac_set_theta_field(dirac_ctx *ctx, void *const coef[]);
 
 /*
  * The complex64 per-site coefficient record from theta: coef[t] = gamma(theta[t])
- * (format of dirac_theta_from_fields) for t < n.  theta: device array of n
+ * (format of dirac_theta_from_fields; the Cayley form of the time-averaged term
+ * of Eqs. ss1-ss4) for t < n.  theta: device array of n
  * doubles; coef: device array of n complex64.  Context-free.  Asynchronous on
  * stream; DIRAC_E_ARG for null pointers or n < 0, DIRAC_E_HIP on launch failure.
  */
@@ -204,8 +210,10 @@ int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream
  * As dirac_coef_from_theta for a complex theta = theta[t] + i theta_im[t]
  * (theta_im: device array of n doubles, (dt/2) Im V per site, or NULL): the
  * complex64 record gamma = 1 - alpha, rounded once from FP64 where Im theta !=
- * 0 (|alpha| != 1 there) and by the unit-modulus search elsewhere.  Per-site
+ * 0 (|alpha| != 1 there) and by the unit-modulus search elsewhere (absorbing
+ * potentials, after Sect. 3's remark on imaginary potentials).  Per-site
  * complex potentials are supported for complex64 lattices and batches.
+ * Context-free, asynchronous; DIRAC_E_ARG for null coef/theta or n < 0.
  */
 int dirac_coef_from_theta_c(void *coef, const void *theta, const void *theta_im, int64_t n, void *stream);
 
@@ -295,8 +303,9 @@ int dirac_norm(dirac_ctx *ctx, double out[3], void *stream);
 
 /*
  * n >= 1 steps (as dirac_step) whose last step also evaluates, on the state it
- * produces, the conserved functional in its C,D-summed form (dev_out[0], equal
- * to dirac_norm's values) and the plain norm (dev_out[1]); two FP64 values
+ * produces, the conserved functional (Lemma of Sect. 2.2, Eq. EPM; Sect. 3 in
+ * 2D) in its C,D-summed form (dev_out[0], equal to dirac_norm's values) and
+ * the plain norm (dev_out[1]); two FP64 values
  * written to device memory, asynchronously, in a fixed order.  With the fused
  * (3+1)D kernel the functional is accumulated inside the step at no extra
  * pass over memory; otherwise a step is followed by the reduction.
@@ -304,20 +313,23 @@ int dirac_norm(dirac_ctx *ctx, double out[3], void *stream);
 int dirac_step_norm(dirac_ctx *ctx, int64_t n, void *dev_out, void *stream);
 
 /*
- * Observables of the plain density |X|^2 over all sites, FP64, positions in
+ * Observables of the plain density |X|^2 over all sites (its sum is the naive
+ * norm of Sects. 2.2 and 3; a region sum is a transmitted or reflected
+ * fraction as in the Klein-step simulation of Sect. 5), FP64, positions in
  * cell units (each amplitude at its own site):
  *   3D: out[0] = sum over sites with z >= z0, out[1..3] = sum x|X|^2, y|X|^2,
  *       z|X|^2, out[4] = sum |X|^2, out[5..8] = per component A, B, C, D.
  *   2D: out[0] = sum over sites with x >= z0, out[1..2] = sum x|X|^2, y|X|^2,
  *       out[3] = sum |X|^2, out[4..5] = per component u, v; out[6..8] = 0.
- * Synchronous; out has 9 doubles.
+ * Synchronous; out has 9 doubles; DIRAC_E_NONFINITE if a value is not finite.
  */
 int dirac_observables(dirac_ctx *ctx, double z0, double out[9], void *stream);
 
 /*
- * Seed of the adjoint of L = sum_{z_s >= z0} |psi_s|^2 (3D; x_s >= z0 in 2D):
- * lam[a] = 2 psi on the region, 0 elsewhere, with lam = dL/dRe + i dL/dIm.
- * lam: device arrays shaped like the state.  Asynchronous.
+ * Seed of the adjoint of L = sum_{z_s >= z0} |psi_s|^2 (3D; x_s >= z0 in 2D),
+ * the region probability of dirac_observables: lam[a] = 2 psi on the region, 0
+ * elsewhere, with lam = dL/dRe + i dL/dIm.  lam: caller-owned device arrays
+ * shaped like the state.  Asynchronous; DIRAC_E_ARG for null arrays.
  */
 int dirac_seed_region(dirac_ctx *ctx, double z0, void *const lam[], void *stream);
 
@@ -344,9 +356,11 @@ int dirac_adjoint_vz(dirac_ctx *ctx, int64_t n, void *const lam[], void *dLdV_in
 /* ------------------------------------------------------------------------ */
 
 /*
- * Create a batch of `count` 2D lattices, lattice b having nx[b] x ny[b] cells
- * (each >= 1), common dtype and dt (unit spacing), per-site theta supplied by
- * dirac_batch_bind.  Stability is checked as for dirac_create.  No HIP call.
+ * Create a batch of `count` 2D lattices advanced by the scheme of Sect. 3
+ * (Eqs. scheme2Deq-scheme4thline), lattice b having nx[b] x ny[b] cells (each
+ * >= 1), common dtype and dt (unit spacing), per-site theta supplied by
+ * dirac_batch_bind.  Stability is checked as for dirac_create (Sect. 3's
+ * bound).  No HIP call; DIRAC_E_ARG / DIRAC_E_UNSTABLE as for dirac_create.
  */
 int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype,
                        double dt, unsigned flags);
@@ -370,7 +384,8 @@ int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[],
  */
 int dirac_batch_run(dirac_ctx *ctx, int64_t n, int mode, int use_graph, void *stream);
 
-/* E_r, E_r (C,D form), plain norm of every lattice: host out[3*count]. Synchronous. */
+/* The conserved functional of Sect. 3 in both summed-by-parts forms and the
+ * plain norm of every lattice: host out[3*count], FP64.  Synchronous. */
 int dirac_batch_norms(dirac_ctx *ctx, double *out, void *stream);
 
 /*
