@@ -160,6 +160,15 @@ int dirac_bind_scratch(dirac_ctx *ctx, void *dev, size_t bytes);
 int dirac_set_mass_potential_z(dirac_ctx *ctx, double m, const double *v_int, const double *v_half,
                                int64_t nz);
 
+/* The mass alone (the m of Eqs. ss1-ss4), keeping the V(z) tables last set (V = 0
+ * if none): dirac_set_mass_potential_z(ctx, m, <current tables>).  Leaves a
+ * per-site mode for the V(z) mode.  No HIP call; errors as that call. */
+int dirac_set_mass(dirac_ctx *ctx, double m);
+
+/* The V(z) tables alone (as dirac_set_mass_potential_z), keeping the mass last
+ * set.  No HIP call; errors as that call. */
+int dirac_set_potential_z(dirac_ctx *ctx, const double *v_int, const double *v_half, int64_t nz);
+
 /*
  * Imaginary part of a z-dependent potential, V(z) = V_re(z) + i W(z): absorbing
  * layers (the growth factors of Sect. 3's stability analysis have modulus
@@ -350,6 +359,14 @@ int dirac_seed_region(dirac_ctx *ctx, double z0, void *const lam[], void *stream
 int dirac_adjoint_vz(dirac_ctx *ctx, int64_t n, void *const lam[], void *dLdV_int, void *dLdV_half,
                      void *stream);
 
+/* The gradient of the region probability L = sum_{z_s >= z0} |psi_s|^2 after n
+ * steps with respect to V(z): dirac_seed_region(ctx, z0, lam) then
+ * dirac_adjoint_vz(ctx, n, lam, dLdV_int, dLdV_half).  lam: caller-owned work
+ * arrays shaped like the state (on return the adjoint at the initial state).
+ * Errors as those two calls. */
+int dirac_adjoint(dirac_ctx *ctx, int64_t n, void *const lam[], double z0, void *dLdV_int, void *dLdV_half,
+                  void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched (2+1)D lattices: many independent lattices of different size,    */
 /* mass and potential advanced together.                                     */
@@ -399,6 +416,11 @@ int dirac_batch_norms(dirac_ctx *ctx, double *out, void *stream);
  * (candidate for mode 1) | (candidate for mode 0) << 8.
  */
 int dirac_batch_autotune(dirac_ctx *ctx, const char *cache_path, int *chosen_out, void *stream);
+
+/* dirac_batch_autotune(ctx, cache_path, NULL, default stream): tile shapes are an
+ * implementation choice with no counterpart in the paper.  DIRAC_E_STATE for a
+ * single-lattice context (its knobs are dirac_set_kernel's). */
+int dirac_autotune(dirac_ctx *ctx, const char *cache_path);
 
 #ifdef __cplusplus
 }

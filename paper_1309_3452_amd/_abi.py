@@ -28,7 +28,8 @@ EXPORTS = (
     "dirac_step", "dirac_step_norm", "dirac_reverse", "dirac_norm_device", "dirac_norm", "dirac_observables",
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
-    "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields",
+    "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields", "dirac_set_mass",
+    "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune",
 )
 
 
@@ -74,6 +75,10 @@ def lib():
         "dirac_observables": ([P, D, ctypes.POINTER(D), P], I),
         "dirac_seed_region": ([P, D, PP, P], I),
         "dirac_adjoint_vz": ([P, I64, PP, P, P, P], I),
+        "dirac_adjoint": ([P, I64, PP, D, P, P, P], I),
+        "dirac_set_mass": ([P, D], I),
+        "dirac_set_potential_z": ([P, P, P, I64], I),
+        "dirac_autotune": ([P, ctypes.c_char_p], I),
         "dirac_batch_create": ([ctypes.POINTER(P), I64, ctypes.POINTER(I64), ctypes.POINTER(I64), I, D, U], I),
         "dirac_batch_bind": ([P, PP, PP, PP, P, ctypes.c_size_t], I),
         "dirac_batch_run": ([P, I64, I, I, P], I),

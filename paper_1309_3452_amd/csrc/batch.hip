@@ -636,4 +636,6 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
     return DIRAC_OK;
 }
 
+int dirac_autotune(dirac_ctx *c, const char *cache_path) { return dirac_batch_autotune(c, cache_path, nullptr, nullptr); }
+
 }  // extern "C"

@@ -536,6 +536,18 @@ int dirac_set_mass_potential_z(dirac_ctx *c, double m, const double *v_int, cons
     return DIRAC_OK;
 }
 
+int dirac_set_mass(dirac_ctx *c, double m) {
+    if (!c) return DIRAC_E_ARG;
+    if (c->v_int.empty()) return dirac_set_mass_potential_z(c, m, nullptr, nullptr, planes_of(c));
+    const std::vector<double> vi = c->v_int, vh = c->v_half;
+    return dirac_set_mass_potential_z(c, m, vi.data(), vh.data(), planes_of(c));
+}
+
+int dirac_set_potential_z(dirac_ctx *c, const double *v_int, const double *v_half, int64_t nz) {
+    if (!c) return DIRAC_E_ARG;
+    return dirac_set_mass_potential_z(c, c->m, v_int, v_half, nz);
+}
+
 int dirac_set_theta_field(dirac_ctx *c, void *const theta[]) {
     if (!c || !theta) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
@@ -785,6 +797,13 @@ int dirac_seed_region(dirac_ctx *c, double z0, void *const lam[], void *stream) 
         HIPCHK(c, c->ndim == 3 ? launch_seed3<double>(a, l8, s) : launch_seed2<double>(a, l8, s));
     }
     return DIRAC_OK;
+}
+
+int dirac_adjoint(dirac_ctx *c, int64_t n, void *const lam[], double z0, void *dLdV_int, void *dLdV_half,
+                  void *stream) {
+    int rc = dirac_seed_region(c, z0, lam, stream);
+    if (rc) return rc;
+    return dirac_adjoint_vz(c, n, lam, dLdV_int, dLdV_half, stream);
 }
 
 int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int, void *dLdV_half, void *stream) {

@@ -168,3 +168,25 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_abi, "_lib", None)
     with pytest.raises(ImportError):
         _abi.lib()
+
+
+def test_split_setters_and_wrappers_validate(L):
+    """dirac_set_mass / dirac_set_potential_z / dirac_adjoint / dirac_autotune:
+    argument and state checks before any HIP call."""
+    assert L.dirac_set_mass(None, 0.5) == -1
+    assert L.dirac_set_potential_z(None, None, None, 4) == -1
+    assert L.dirac_autotune(None, None) == -1
+    c = ctypes.c_void_p()
+    assert L.dirac_create(ctypes.byref(c), 3, 8, 8, 4, 2, 0.5, 1.0, 1.0, 1.0, 0) == 0
+    assert L.dirac_set_mass(c, float("nan")) == -1
+    assert L.dirac_set_mass(c, 0.5) == 0
+    v = (ctypes.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    assert L.dirac_set_potential_z(c, v, v, 5) == -2
+    assert L.dirac_set_potential_z(c, v, None, 4) == -1
+    assert L.dirac_set_potential_z(c, v, v, 4) == 0
+    assert L.dirac_set_mass(c, 0.7) == 0            # keeps the tables
+    assert L.dirac_autotune(c, None) == -6          # single lattice: no tuner
+    from paper_1309_3452_amd._abi import ptr_array
+    lam = ptr_array([256] * 8)
+    assert L.dirac_adjoint(c, 2, lam, 0.0, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -6   # no state
+    L.dirac_destroy(c)

@@ -862,3 +862,42 @@ def test_fused_links_2d_bitwise_equals_split(P, dtype, site, shape, zchunk, step
         out.append([t.clone() for t in lat.state()])
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+def test_split_setters_and_adjoint_wrapper(P):
+    """dirac_set_mass + dirac_set_potential_z give the bits of
+    dirac_set_mass_potential_z; dirac_adjoint gives those of dirac_seed_region then
+    dirac_adjoint_vz."""
+    import ctypes
+    from paper_1309_3452_amd._abi import lib, ptr_array
+    print("split setters and adjoint wrapper", flush=True)
+    nx, ny, nz = 40, 12, 16
+    g = np.random.default_rng(811)
+    f0 = [torch.from_numpy(g.standard_normal((nz, ny, nx)) + 1j * g.standard_normal((nz, ny, nx))) for _ in range(8)]
+    vi, vh = 0.4 * g.standard_normal(nz), 0.4 * g.standard_normal(nz)
+    outs = []
+    for split in (False, True):
+        lat = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+        if split:
+            assert lib().dirac_set_potential_z(lat._ctx, vi.ctypes.data_as(ctypes.c_void_p),
+                                               vh.ctypes.data_as(ctypes.c_void_p), nz) == 0
+            assert lib().dirac_set_mass(lat._ctx, 0.45) == 0
+        else:
+            lat.set_potential_z(0.45, vi, vh)
+        lat.load(f0)
+        lat.step(5)
+        lam = [torch.empty((nz, ny, nx), dtype=torch.complex128, device="cuda") for _ in range(8)]
+        dvi = torch.zeros(nz, dtype=torch.float64, device="cuda")
+        dvh = torch.zeros(nz, dtype=torch.float64, device="cuda")
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if split:
+            assert lib().dirac_adjoint(lat._ctx, 5, ptr_array([t.data_ptr() for t in lam]), 8.0,
+                                       ctypes.c_void_p(dvi.data_ptr()), ctypes.c_void_p(dvh.data_ptr()), stream) == 0
+        else:
+            lam = lat.seed_region(8.0)
+            dvi, dvh = lat.adjoint_vz(5, lam)
+        torch.cuda.synchronize()
+        outs.append(([t.clone() for t in lat.state()], [t.clone() for t in lam], dvi.clone(), dvh.clone()))
+    for a, b in zip(outs[0][0] + outs[0][1], outs[1][0] + outs[1][1]):
+        assert torch.equal(a, b)
+    assert torch.equal(outs[0][2], outs[1][2]) and torch.equal(outs[0][3], outs[1][3])
