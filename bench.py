@@ -48,7 +48,7 @@ def parse():
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
                     choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "links2d", "klein2d",
-                             "slab3d"],
+                             "slab3d", "site3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -341,6 +341,62 @@ def bench_links3d(n, steps, dtype_name):
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]), "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
 
 
+def bench_site3d(n, steps, dtype_name):
+    """(3+1)D n^3 step with per-site coefficient records (a potential V(x, y, z)):
+    the one-step and the two-step z-march kernels on the same lattice."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    dtype = torch.complex64 if dtype_name == "f32" else torch.complex128
+    cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    # V at each array's own sites: the headline's step in z plus 0.05 N(0, 1)
+    # site noise (seeded), so that no two sites share a record
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13093452)
+    V = []
+    for a in range(8):
+        z = torch.arange(n, dtype=torch.float64, device="cuda") + workloads.OFF3[a][2]
+        vz = 1.5 * (1.0 + torch.tanh((z - n / 2.0) / 4.0)) / 2.0
+        noise = torch.randn((n, n, n), generator=gen, dtype=torch.float64, device="cuda")
+        V.append((vz.view(n, 1, 1) + 0.05 * noise).to(lat.real_dtype).contiguous())
+        del noise
+    lat.set_fields(cfg["m"], V)
+    del V
+    lat._vsite = None
+    torch.cuda.empty_cache()
+    e0 = lat.norm()
+    out = {}
+    for kern in ("fused", "fused2"):
+        lat.set_kernel(kern)
+        lat.step(2)
+        out[kern] = _timed(lambda: lat.step(steps)) / steps
+    e1 = lat.norm()
+    cells = n ** 3
+    b = 8 if dtype_name == "f32" else 16
+    # per cell-step: 16 amplitudes read or written once, 8 per-site records read
+    # once (complex64 gamma or float64 theta, 8 B each)
+    alg_step = (16 * b + 8 * 8) * cells
+    ms = out["fused2"]
+    achieved = alg_step / (ms * 1e-3) / 1e9
+    return {"metric": "site-updates/s, (3+1)D %d^3 with per-site potential records" % n,
+            "value": cells / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
+            "warmup": 2, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
+            "config": {"workload": "(3+1)D %d^3 lattice of the headline workload with V(x, y, z) = the z-step "
+                                   "plus 0.05 N(0,1) per site as per-site coefficient records, m = 0.5, "
+                                   "two-step z-march kernel" % n, "cells": cells},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k3_fused2 per-site (two steps per launch)", "avg_launch_ms": 2 * ms,
+                         "alg_bytes_per_launch": 2 * alg_step},
+            "one_step_kernel_ms_per_step": out["fused"],
+            "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
+
+
 def bench_klein2d(phi_deg):
     """(2+1)D Klein-step scattering (m = 0, step height twice the packet energy,
     absorbing frame), complex64: steps timed; the transmitted probability and
@@ -584,6 +640,11 @@ def main():
     if args.workload == "klein2d":
         for phi in (0.0, 37.0):
             print(json.dumps(bench_klein2d(phi)), flush=True)
+        return
+    if args.workload == "site3d":
+        for d in ("f32", "f64"):
+            print(json.dumps(bench_site3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
+            torch.cuda.empty_cache()
         return
     if args.workload == "links3d":
         for d in ("f32", "f64"):

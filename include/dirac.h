@@ -68,10 +68,11 @@ enum dirac_status {
  * per stored plane.  z is not periodic: a call of dirac_step reads the halo
  * planes and writes the interior only, so before each call the caller fills
  * the halos of the current buffer set with the neighbouring slabs' outermost
- * two interior planes (all 8 arrays).  With V(z) tables (and nx even for
- * complex64) a call may advance two steps in one launch of the two-step kernel,
- * whose reach in z over two steps is the two halo planes; otherwise (per-site
- * coefficients, or DIRAC_KERNEL_FUSED set) one step by the one-step kernel.
+ * two interior planes (all 8 arrays).  With nx even for complex64 (any nx for
+ * complex128) a call may advance two steps in one launch of the two-step
+ * kernel, whose reach in z over two steps is the two halo planes; otherwise
+ * (odd nx in complex64, or DIRAC_KERNEL_FUSED set) one step by the one-step
+ * kernel.
  * dirac_halo_steps tells which; a larger n is refused (DIRAC_E_ARG).  Each
  * launch moves the state to the other buffer set.  dirac_step_norm and
  * dirac_norm sum the interior (slab sums add up to the whole lattice's).  dirac_reverse, dirac_observables,
@@ -84,9 +85,9 @@ enum dirac_kernel {
     DIRAC_KERNEL_AUTO = 0,   /* FUSED2 where it applies, else FUSED                */
     DIRAC_KERNEL_SPLIT = 1,  /* one launch per half-step, in place                 */
     DIRAC_KERNEL_FUSED = 2,  /* one launch per step, ping-pong between the buffers */
-    DIRAC_KERNEL_FUSED2 = 3  /* one launch per two steps (3D, V(z) tables, nx even
-                                for complex64), ping-pong; an odd remainder and
-                                other cases take FUSED                            */
+    DIRAC_KERNEL_FUSED2 = 3  /* one launch per two steps (3D: V(z) tables or
+                                per-site records, nx even for complex64; 2D), ping-
+                                pong; an odd remainder and other cases take FUSED */
 };
 
 /* Human-readable name of a status code (static storage). */

@@ -314,7 +314,7 @@ template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipSt
     if (kc == DIRAC_KERNEL_FUSED2) {
         for (; t + 2 <= n; t += 2) {
             FusedArgs<R> a = fused_args<R>(c);
-            if (c->ndim == 3) HIPCHK(c, launch_fused3x2<R>(a, s));
+            if (c->ndim == 3) HIPCHK(c, launch_fused3x2<R>(a, site, s));
             else HIPCHK(c, launch_fused2x2<R>(a, site, s));
             c->cur = 1 - c->cur;
         }
@@ -669,12 +669,12 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
             FusedArgs<float> a = fused_args<float>(c);
             a.npart = part;
             a.npart_cap = cap;
-            e = launch_fused3x2<float>(a, s, &nb);
+            e = launch_fused3x2<float>(a, c->site_mode, s, &nb);
         } else {
             FusedArgs<double> a = fused_args<double>(c);
             a.npart = part;
             a.npart_cap = cap;
-            e = launch_fused3x2<double>(a, s, &nb);
+            e = launch_fused3x2<double>(a, c->site_mode, s, &nb);
         }
         if (e == hipSuccess) {
             c->cur = 1 - c->cur;

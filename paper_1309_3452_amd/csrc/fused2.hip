@@ -134,7 +134,26 @@ template <int TW, int TY, int NT> __device__ __forceinline__ int region_slot(int
     return r;
 }
 
-template <typename R, int TW, int TY, int NT, bool NORM>
+// Per-site coefficient record: gamma (float2) for complex64 lattices, theta
+// (double) for complex128 ones, turned into Cayley coefficients exactly as the
+// one-step kernels do.
+template <typename R> struct SiteRec;
+template <> struct SiteRec<float> {
+    typedef float2 T;
+    static __device__ __forceinline__ T load(const float *th, size_t pb, uint32_t boff) {
+        return *(const float2 *)((const char *)th + pb + boff);
+    }
+    static __device__ __forceinline__ Coef<float> coef(T g) { return coef_site(g, 1.0f); }
+};
+template <> struct SiteRec<double> {
+    typedef double T;
+    static __device__ __forceinline__ T load(const double *th, size_t pb, uint32_t boff) {
+        return *(const double *)((const char *)th + pb + boff);
+    }
+    static __device__ __forceinline__ Coef<double> coef(T th) { return coef_theta(1.0 * th); }
+};
+
+template <typename R, int TW, int TY, int NT, bool NORM, bool SITE>
 __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int W = TW + 4, H = TY + 4, RN = W * H;
@@ -190,6 +209,19 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     const bool in2 = in1 && xr >= -1 && xr <= w && yr >= -1 && yr <= h;        // levels 2, 3 (ring 1)
     const bool in4 = in1 && xr >= 0 && xr < w && yr >= 0 && yr < h;            // level 4 (tile)
     uint32_t go = in1 ? ((uint32_t)wrapn(y0 + yr, ny) * (uint32_t)nx + (uint32_t)wrapn(x0 + xr, nx)) * CS : 0u;
+    // per-site mode: records of arrays arr0 .. arr0 + 3 at stored plane k and
+    // this thread's cell, loaded where a level uses them (a plane not stored reads plane 0; nothing it feeds is stored)
+    // (a wave-uniform plane base plus this lane's 32-bit byte offset, as for
+    // the amplitudes)
+    using Rec = typename SiteRec<R>::T;
+    constexpr uint32_t RS = sizeof(Rec);
+    const uint32_t rbytes = (uint32_t)nx * (uint32_t)ny * RS;
+    auto ld_rec = [&](int arr0, int k, Rec *dst) {
+        const size_t pb = (size_t)(uint32_t)tk(k) * (size_t)rbytes;
+        const uint32_t ro = go / (CS / RS);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = SiteRec<R>::load(a.th[arr0 + q], pb, ro);
+    };
 
     const C *in[8];
     C *out[8];
@@ -282,7 +314,16 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
 
         // level 1: A,B of plane p after step 1
         if (in1) {
-            const Coef<R> kA = tcoef(tab, tstride, 0, tk(k0)), kB = tcoef(tab, tstride, 1, tk(k0));
+            Coef<R> kq[4];
+            if constexpr (SITE) {
+                Rec rr[4];
+                ld_rec(0, k0, rr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+            } else {
+                kq[0] = kq[1] = tcoef(tab, tstride, 0, tk(k0));
+                kq[2] = kq[3] = tcoef(tab, tstride, 1, tk(k0));
+            }
             const C *C0 = old_(0), *C1 = old_(1);
             const C *D0 = old_(2), *D1 = old_(3);
             const C *D0n = old_(4), *D1n = old_(5);
@@ -295,10 +336,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                                               cown[1], cprev[1], C1[i - W], C1[i - 1],
                                               down[0], D0[i - 1], D0[i + W], D0n[i],
                                               down[1], D1[i - W], D1[i + 1], D1n[i]);
-            ab1[0] = update(pab[0], S.s0, kA);
-            ab1[1] = update(pab[1], S.s1, kA);
-            ab1[2] = update(pab[2], S.s2, kB);
-            ab1[3] = update(pab[3], S.s3, kB);
+            ab1[0] = update(pab[0], S.s0, kq[0]);
+            ab1[1] = update(pab[1], S.s1, kq[1]);
+            ab1[2] = update(pab[2], S.s2, kq[2]);
+            ab1[3] = update(pab[3], S.s3, kq[3]);
         }
         // level 2: C,D of plane p-1 after step 1 (LDS: level 1 of plane p-1)
         const int q2 = p - 1;
@@ -314,16 +355,25 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab1h1[3] = B1[i];
         }
         if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
-            const Coef<R> kC = tcoef(tab, tstride, 2, tk(km1)), kD = tcoef(tab, tstride, 3, tk(km1));
+            Coef<R> kq[4];
+            if constexpr (SITE) {
+                Rec rr[4];
+                ld_rec(4, km1, rr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+            } else {
+                kq[0] = kq[1] = tcoef(tab, tstride, 2, tk(km1));
+                kq[2] = kq[3] = tcoef(tab, tstride, 3, tk(km1));
+            }
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab1h1[0], ab1[0], A0[i + 1], A0[i + W],
                                               ab1h1[1], ab1[1], A1[i - 1], A1[i - W],
                                               ab1h1[2], ab1h2[2], B0[i - 1], B0[i + W],
                                               ab1h1[3], ab1h2[3], B1[i + 1], B1[i - W]);
-            cd1[0] = update(cprev[0], S.s0, kC);
-            cd1[1] = update(cprev[1], S.s1, kC);
-            cd1[2] = update(dprev[0], S.s2, kD);
-            cd1[3] = update(dprev[1], S.s3, kD);
+            cd1[0] = update(cprev[0], S.s0, kq[0]);
+            cd1[1] = update(cprev[1], S.s1, kq[1]);
+            cd1[2] = update(dprev[0], S.s2, kq[2]);
+            cd1[3] = update(dprev[1], S.s3, kq[3]);
         }
         // level 3: A,B of plane p-2 after step 2 (LDS: level 2 of plane p-2)
         const int q3 = p - 2;
@@ -335,16 +385,25 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             cd1h1[3] = D1[i];
         }
         if (in2 && q3 >= z0 - 1 && q3 <= z1) {
-            const Coef<R> kA = tcoef(tab, tstride, 0, tk(km2)), kB = tcoef(tab, tstride, 1, tk(km2));
+            Coef<R> kq[4];
+            if constexpr (SITE) {
+                Rec rr[4];
+                ld_rec(0, km2, rr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+            } else {
+                kq[0] = kq[1] = tcoef(tab, tstride, 0, tk(km2));
+                kq[2] = kq[3] = tcoef(tab, tstride, 1, tk(km2));
+            }
             const St3<C> S = stencil_ab<C, R>(rx, ry, rz,
                                               cd1h1[0], cd1h2[0], C0[i + 1], C0[i + W],
                                               cd1h1[1], cd1h2[1], C1[i - W], C1[i - 1],
                                               cd1h1[2], D0[i - 1], D0[i + W], cd1[2],
                                               cd1h1[3], D1[i - W], D1[i + 1], cd1[3]);
-            ab2[0] = update(ab1h2[0], S.s0, kA);
-            ab2[1] = update(ab1h2[1], S.s1, kA);
-            ab2[2] = update(ab1h2[2], S.s2, kB);
-            ab2[3] = update(ab1h2[3], S.s3, kB);
+            ab2[0] = update(ab1h2[0], S.s0, kq[0]);
+            ab2[1] = update(ab1h2[1], S.s1, kq[1]);
+            ab2[2] = update(ab1h2[2], S.s2, kq[2]);
+            ab2[3] = update(ab1h2[3], S.s3, kq[3]);
             if (in4 && q3 >= z0 && q3 < z1) {
                 const size_t Pq = pofs(km2);
 #pragma unroll
@@ -369,7 +428,16 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
             ab2h1[3] = B21[i];
         }
         if (in4 && q4 >= z0 && q4 < z1) {
-            const Coef<R> kC = tcoef(tab, tstride, 2, tk(km3)), kD = tcoef(tab, tstride, 3, tk(km3));
+            Coef<R> kq[4];
+            if constexpr (SITE) {
+                Rec rr[4];
+                ld_rec(4, km3, rr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+            } else {
+                kq[0] = kq[1] = tcoef(tab, tstride, 2, tk(km3));
+                kq[2] = kq[3] = tcoef(tab, tstride, 3, tk(km3));
+            }
             const C *A0 = A20, *A1 = A21, *B0 = B20, *B1 = B21;
             const St3<C> S = stencil_cd<C, R>(rx, ry, rz,
                                               ab2h1[0], ab2[0], A0[i + 1], A0[i + W],
@@ -377,10 +445,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                                               ab2h1[2], b2h2[0], B0[i - 1], B0[i + W],
                                               ab2h1[3], b2h2[1], B1[i + 1], B1[i - W]);
             C o[4];
-            o[0] = update(cd1h2[0], S.s0, kC);
-            o[1] = update(cd1h2[1], S.s1, kC);
-            o[2] = update(cd1h2[2], S.s2, kD);
-            o[3] = update(cd1h2[3], S.s3, kD);
+            o[0] = update(cd1h2[0], S.s0, kq[0]);
+            o[1] = update(cd1h2[1], S.s1, kq[1]);
+            o[2] = update(cd1h2[2], S.s2, kq[2]);
+            o[3] = update(cd1h2[3], S.s3, kq[3]);
             const size_t Pq = pofs(km3);
 #pragma unroll
             for (int q = 0; q < 4; ++q) st_pl(out[4 + q], Pq, go, o[q]);
@@ -524,11 +592,15 @@ int pick_chunks(int64_t tiles, int nz, int fill) {
     return res;
 }
 
-bool fused3x2_supported(int nx, bool fp32, bool site) { return !site && (!fp32 || nx % 2 == 0); }
+bool fused3x2_supported(int nx, bool fp32, bool site) { (void)site; return !fp32 || nx % 2 == 0; }
 
-template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStream_t s, int *nblocks_out) {
+template <typename R>
+hipError_t launch_fused3x2(const FusedArgs<R> &a0, bool site, hipStream_t s, int *nblocks_out) {
     FusedArgs<R> a = a0;
-    if (a.tab == nullptr || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
+    if ((!site && a.tab == nullptr) || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
+    if (site)
+        for (int q = 0; q < 8; ++q)
+            if (a.th[q] == nullptr) return hipErrorInvalidValue;
     // plane byte offsets are 32-bit inside the kernel
     if ((uint64_t)a.nx * (uint64_t)a.ny * sizeof(cx<R>) >= (1ull << 32)) return hipErrorInvalidValue;
     constexpr int TW = sizeof(R) == 4 ? 64 : 32, TY = 8, NT = sizeof(R) == 4 ? 1024 : 512;
@@ -550,8 +622,14 @@ template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a0, hipStre
     if (nblocks_out) *nblocks_out = (int)nblk;
     const bool norm = a.npart != nullptr;
     if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;
-    if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true>), dim3((unsigned)nblk), dim3(NT), 0, s, a, a.tab);
-    else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false>), dim3((unsigned)nblk), dim3(NT), 0, s, a, a.tab);
+    const dim3 g((unsigned)nblk), b(NT);
+    if (site) {
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, true>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, true>), g, b, 0, s, a, a.tab);
+    } else {
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, false>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, false>), g, b, 0, s, a, a.tab);
+    }
     return hipGetLastError();
 }
 
@@ -580,7 +658,7 @@ template <typename R> hipError_t launch_fused2x2(const FusedArgs<R> &a0, bool si
 
 template hipError_t launch_fused2x2<float>(const FusedArgs<float> &, bool, hipStream_t);
 template hipError_t launch_fused2x2<double>(const FusedArgs<double> &, bool, hipStream_t);
-template hipError_t launch_fused3x2<float>(const FusedArgs<float> &, hipStream_t, int *);
-template hipError_t launch_fused3x2<double>(const FusedArgs<double> &, hipStream_t, int *);
+template hipError_t launch_fused3x2<float>(const FusedArgs<float> &, bool, hipStream_t, int *);
+template hipError_t launch_fused3x2<double>(const FusedArgs<double> &, bool, hipStream_t, int *);
 
 }  // namespace dirac

@@ -79,9 +79,10 @@ template <typename R> hipError_t launch_half3(const HalfArgs<R> &a, int which /*
                                               hipStream_t s);
 template <typename R> hipError_t launch_fused3(const FusedArgs<R> &a, bool site, int tile_y, hipStream_t s,
                                                int *nblocks_out = nullptr);
-// Two steps per launch (fused2.hip); V(z) tables only, nx even for complex64.
+// Two steps per launch (fused2.hip); V(z) tables or per-site records, nx even for complex64.
 bool fused3x2_supported(int nx, bool fp32, bool site);
-template <typename R> hipError_t launch_fused3x2(const FusedArgs<R> &a, hipStream_t s, int *nblocks_out = nullptr);
+template <typename R>
+hipError_t launch_fused3x2(const FusedArgs<R> &a, bool site, hipStream_t s, int *nblocks_out = nullptr);
 // (2+1)D two steps per launch (fused2.hip, march2x2.h); nx even for complex64.
 bool fused2x2_supported(int nx, bool fp32);
 template <typename R> hipError_t launch_fused2x2(const FusedArgs<R> &a, bool site, hipStream_t s);

@@ -116,9 +116,9 @@ def test_calls_out_of_order_are_rejected(L):
     assert L.dirac_reverse(cs, 1, None) == -6
     assert L.dirac_observables(cs, 0.0, (ctypes.c_double * 9)(), None) == -6
     assert L.dirac_set_links(cs, ptr_array([256] * 24)) == -6
-    # steps per halo refill: two with V(z) tables (two-step kernel), one with the
-    # one-step kernel or per-site coefficients; more per call is refused before
-    # any launch
+    # steps per halo refill: two with the two-step kernel (V(z) tables or
+    # per-site coefficients), one with the one-step kernel; more per call is
+    # refused before any launch
     hs = ctypes.c_int(-1)
     assert L.dirac_halo_steps(cs, ctypes.byref(hs)) == 0 and hs.value == 2
     assert L.dirac_step(cs, 3, None) == -1
@@ -130,7 +130,7 @@ def test_calls_out_of_order_are_rejected(L):
     assert b"1 step per call" in L.dirac_last_error(cs)
     assert L.dirac_set_kernel(cs, 0, 0, 0) == 0
     assert L.dirac_set_theta_field(cs, fake) == 0
-    assert L.dirac_halo_steps(cs, ctypes.byref(hs)) == 0 and hs.value == 1
+    assert L.dirac_halo_steps(cs, ctypes.byref(hs)) == 0 and hs.value == 2
     assert L.dirac_halo_steps(cs, None) == -1
     assert L.dirac_halo_steps(c, ctypes.byref(hs)) == 0 and hs.value == 0
     L.dirac_destroy(cs)

@@ -113,7 +113,7 @@ def test_3d_potential_z_parity(P, kernel, tile_y, zchunk, shape):
         assert abs(ob[q] - oo[q]) <= 1e-12 * max(abs(oo[q]), oo[4])
 
 
-@pytest.mark.parametrize("kernel", ["split", "fused"])
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
 def test_3d_site_fields_parity(P, kernel):
     nx, ny, nz = 66, 9, 12
     print("3d fields %s" % kernel, flush=True)
@@ -306,6 +306,39 @@ def test_fused2_bitwise_equals_one_step(P, dtype, shape, zchunk, steps):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("shape,zchunk,steps", [((70, 20, 22), 0, 6), ((64, 8, 16), 0, 7), ((130, 9, 5), 2, 5),
+                                                ((2, 1, 3), 0, 4), ((36, 17, 9), 4, 8)])
+def test_fused2_site_bitwise_equals_one_step(P, dtype, shape, zchunk, steps):
+    """Per-site coefficient records (complex64: with an absorbing W, so gamma is
+    complex): two steps per launch give the one-step bits, and the in-step
+    functional of the two-step launch agrees with the standalone reduction."""
+    nx, ny, nz = shape
+    print("fused2 site bitwise %s %s zc=%d n=%d" % (shape, dtype, zchunk, steps), flush=True)
+    g = np.random.default_rng(98)
+    V = [torch.from_numpy(np.ascontiguousarray(0.5 * g.standard_normal((nz, ny, nx)))) for _ in range(8)]
+    W = ([torch.from_numpy(np.ascontiguousarray(-0.05 * np.abs(g.standard_normal((nz, ny, nx))))) for _ in range(8)]
+         if dtype == torch.complex64 else None)
+    f0 = rand_state((nz, ny, nx), 8, 99)
+    res = []
+    for kernel in ("fused2", "fused"):
+        lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+        lat.set_kernel(kernel, 0, zchunk)
+        lat.set_fields(0.3, V, W)
+        lat.load(f0)
+        lat.step(steps)
+        res.append([t.cpu() for t in lat.state()])
+        if kernel == "fused2":
+            e = lat.step_norm(2).cpu().numpy()
+            ref = lat.norm()
+            # as for the V(z) tables: the same FP64 sums in another order
+            # (complex64: of the FP32-evaluated stencil)
+            tol = 1e-12 if dtype == torch.complex128 else 2e-9
+            assert abs(e[0] - ref[0]) <= tol * ref[2] and abs(e[1] - ref[2]) <= 1e-12 * ref[2]
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
 # --------------------------------------------------------------------------
 # complex64 per-site coefficient records: gamma = 1 - alpha rounded once per
 # site so that |1 - gamma| = 1 as closely as FP32 allows; beta = 1 - gamma/2.
@@ -340,7 +373,7 @@ def test_fp32_site_coefficients(P):
     assert np.array_equal(gn.real, out.cpu().numpy().real) and np.array_equal(gn.imag, -out.cpu().numpy().imag)
 
 
-@pytest.mark.parametrize("kernel", ["split", "fused"])
+@pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
 def test_3d_site_fields_fp32_vs_oracle(P, kernel):
     nx, ny, nz = 66, 9, 12
     print("3d fields fp32 %s" % kernel, flush=True)
