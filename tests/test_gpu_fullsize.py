@@ -191,6 +191,66 @@ def test_sampled_oracle_parity_256_fp64(P):
             assert abs(box[a][R, R, R] - got[a][k, j, i]) <= 1e-13 * scale, (i, j, k, a)
 
 
+def test_sampled_oracle_parity_512_fp32_headline(P):
+    """The benchmark's own workload and launch sequence: 512^3 complex64, the
+    Klein-step V(z) and packet, two-step launches (the second one also summing
+    E_r, as the timed loop does every tenth step).  After 4 steps, cells sampled
+    around the packet (where the amplitudes are not negligible), on the step and
+    at random are compared with the FP64 oracle run from the same FP32 initial
+    state on a periodic sub-box of half-width 2*4+1 around each; FP32 rounding
+    allows about 1e-6 of the largest amplitude per step."""
+    n, steps, R = 512, 4, 9
+    cfg = workloads.config_step3d(n, dtype=torch.complex64, device="cuda")
+    print("sampled parity 512^3 fp32 headline", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex64, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    assert lat.halo_steps == 0
+    g = np.random.default_rng(29)
+    c = (n // 2, n // 2, n // 4)
+    samples = [tuple(int(round(c[q] + 12.0 * g.standard_normal())) % n for q in range(3)) for _ in range(20)]
+    samples += [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(4)]
+    samples += [(c[0], c[1], c[2]), (c[0], c[1], n // 2), (0, 0, 0), (n - 1, n - 1, n - 1)]
+    B = 2 * R + 1
+
+    def boxes(arrays):
+        out = []
+        for (i, j, k) in samples:
+            ix = torch.arange(i - R, i + R + 1, device="cuda") % n
+            iy = torch.arange(j - R, j + R + 1, device="cuda") % n
+            iz = torch.arange(k - R, k + R + 1, device="cuda") % n
+            out.append([a.index_select(0, iz).index_select(1, iy).index_select(2, ix).cpu().numpy().astype(np.complex128)
+                        for a in arrays])
+        return out
+
+    before = boxes(lat.state())
+    lat.step_norm(2)
+    e = lat.step_norm(2).cpu().numpy()
+    torch.cuda.synchronize()
+    after = [[b[a][R, R, R] for a in range(8)] for b in boxes(lat.state())]
+    ref = lat.norm()
+    assert abs(e[0] - ref[0]) <= 2e-9 * ref[2]
+    del lat
+    free()
+    ol = oracle.Lattice3(B, B, B, cfg["dt"])
+    scale = max(max(abs(v) for v in row) for row in after)
+    m, v_int, v_half = cfg["m"], cfg["v_int"], cfg["v_half"]
+    big = 0
+    for (i, j, k), box, got in zip(samples, before, after):
+        iz = (np.arange(k - R, k + R + 1)) % n
+        th = []
+        for a in range(8):
+            tab = v_int if workloads.OFF3[a][2] == 0.0 else v_half
+            sgn = 1.0 if a < 4 else -1.0
+            th.append(np.ascontiguousarray(0.5 * cfg["dt"] * (sgn * m + tab[iz])[:, None, None] * np.ones((1, B, B))))
+        ol.step(box, th, steps)
+        for a in range(8):
+            assert abs(box[a][R, R, R] - got[a]) <= steps * 1e-6 * scale, (i, j, k, a)
+            big += abs(got[a]) > 1e-2 * scale
+    assert big >= 40       # the packet samples carry the comparison
+
+
 @pytest.mark.parametrize("dtype,nz,beyond,tol", [(torch.complex64, 72, 64, 3e-6), (torch.complex128, 40, 32, 1e-13)])
 def test_sampled_oracle_parity_arrays_over_4gib(P, dtype, nz, beyond, tol):
     """Arrays larger than 4 GiB (4096 x 2048 x nz cells): 64-bit addressing in the
