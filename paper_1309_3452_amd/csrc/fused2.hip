@@ -150,7 +150,7 @@ template <> struct SiteRec<double> {
     static __device__ __forceinline__ T load(const double *th, size_t pb, uint32_t boff) {
         return *(const double *)((const char *)th + pb + boff);
     }
-    static __device__ __forceinline__ Coef<double> coef(T th) { return coef_theta(1.0 * th); }
+    static __device__ __forceinline__ Coef<double> coef(T th) { return coef_theta(th); }
 };
 
 template <typename R, int TW, int TY, int NT, bool NORM, bool SITE>
@@ -209,10 +209,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     const bool in2 = in1 && xr >= -1 && xr <= w && yr >= -1 && yr <= h;        // levels 2, 3 (ring 1)
     const bool in4 = in1 && xr >= 0 && xr < w && yr >= 0 && yr < h;            // level 4 (tile)
     uint32_t go = in1 ? ((uint32_t)wrapn(y0 + yr, ny) * (uint32_t)nx + (uint32_t)wrapn(x0 + xr, nx)) * CS : 0u;
-    // per-site mode: records of arrays arr0 .. arr0 + 3 at stored plane k and
-    // this thread's cell, loaded where a level uses them (a plane not stored reads plane 0; nothing it feeds is stored)
-    // (a wave-uniform plane base plus this lane's 32-bit byte offset, as for
-    // the amplitudes)
+    // per-site mode: the records of arrays arr0 .. arr0 + 3 at stored plane k
+    // and this thread's cell, loaded where a level uses them, addressed as a
+    // wave-uniform plane base plus this lane's 32-bit byte offset (a plane not
+    // stored reads plane 0; nothing computed from it is stored)
     using Rec = typename SiteRec<R>::T;
     constexpr uint32_t RS = sizeof(Rec);
     const uint32_t rbytes = (uint32_t)nx * (uint32_t)ny * RS;
