@@ -79,7 +79,7 @@ def profiled_traffic(dtype_tag, n, steps_per_launch=1):
     return float(t.group(1))
 
 
-def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel):
+def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel, keep=False):
     import torch
 
     import paper_1309_3452_amd as P
@@ -134,9 +134,28 @@ def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel):
                e_start=e_start, e_end=e_end,
                drift=abs(e_end[0] - e_start[0]) / abs(e_start[0]), drift_max=drift_series,
                plain_norm_change=abs(e_end[2] - e_start[2]) / e_start[2], steps_total=steps + warmup)
-    del lat
-    torch.cuda.empty_cache()
+    if keep:
+        out["lat"] = lat          # the final state, for the FP32 / FP64 comparison
+    else:
+        del lat
+        torch.cuda.empty_cache()
     return out
+
+
+def compare_states(s32, s64):
+    """Relative L2 distance of the FP32 state from the FP64 one and the phase of
+    their overlap <psi64, psi32>, summed in FP64 array by array."""
+    import torch
+    num = den = 0.0
+    ov = 0j
+    for a, b in zip(s32, s64):
+        a64 = a.to(torch.complex128)
+        num += float(torch.sum(torch.abs(a64 - b) ** 2))
+        den += float(torch.sum(torch.abs(b) ** 2))
+        ov += complex(torch.sum(torch.conj(b) * a64))
+        del a64
+    import cmath
+    return math.sqrt(num / den), cmath.phase(ov)
 
 
 def copy_ceiling_gbs(nbytes=4 << 30, reps=5):
@@ -653,10 +672,18 @@ def main():
         return
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3
-    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel)
+    same = not args.no_fp64 and (args.fp64_steps or K) == K
+    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel, keep=same)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(n, torch.complex128, args.fp64_steps or K, W, 0, 0, args.kernel)
+        r64 = run_gpu(n, torch.complex128, args.fp64_steps or K, W, 0, 0, args.kernel, keep=same)
+    packet = None
+    if same:
+        # the FP32 form against the FP64 path after the same steps from the same packet
+        l2, ph = compare_states(r32["lat"].state(), r64["lat"].state())
+        packet = {"rel_l2_fp32_vs_fp64": l2, "overlap_phase_rad": ph, "steps": K + W}
+        del r32["lat"], r64["lat"]
+        torch.cuda.empty_cache()
     value = cells * K / r32["wall_s"]
     G = r32["steps_per_launch"]
     # algorithmic bytes per launch: 16 amplitudes x 8 B per cell-step (each amplitude
@@ -713,6 +740,8 @@ def main():
                         "roofline_frac": a64 / HBM_PEAK_GBS, "achieved_GBs": a64, "avg_launch_ms": r64["launch_ms"],
                         "steps_per_launch": G64, "E_r_rel_drift": r64["drift"]}
         line["fp32_speedup_over_fp64"] = value / v64
+    if packet is not None:
+        line["norm_error"]["packet_vs_fp64"] = packet
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
