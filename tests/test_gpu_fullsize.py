@@ -251,6 +251,62 @@ def test_sampled_oracle_parity_512_fp32_headline(P):
     assert big >= 40       # the packet samples carry the comparison
 
 
+def test_sampled_oracle_parity_512_fp32_site(P):
+    """Per-site coefficient records at the benchmark size (512^3 complex64, the
+    headline packet, V = the z-step plus 0.05 N(0, 1) per site, as `bench.py
+    --workload site3d`), default two-step launches: after 4 steps, cells around
+    the packet and at random against the FP64 oracle stepping sub-boxes with
+    theta = (dt/2)(+-m + V) of the same (FP32) site values."""
+    n, steps, R = 512, 4, 9
+    cfg = workloads.config_step3d(n, dtype=torch.complex64, device="cuda")
+    print("sampled parity 512^3 fp32 per-site", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex64, dt=cfg["dt"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13093452)
+    V = []
+    for a in range(8):
+        z = torch.arange(n, dtype=torch.float64, device="cuda") + workloads.OFF3[a][2]
+        vz = 1.5 * (1.0 + torch.tanh((z - n / 2.0) / 4.0)) / 2.0
+        V.append((vz.view(n, 1, 1) + 0.05 * torch.randn((n, n, n), generator=gen, dtype=torch.float64,
+                                                         device="cuda")).to(torch.float32).contiguous())
+    lat.set_fields(cfg["m"], V)
+    g = np.random.default_rng(31)
+    c = (n // 2, n // 2, n // 4)
+    samples = [tuple(int(round(c[q] + 12.0 * g.standard_normal())) % n for q in range(3)) for _ in range(20)]
+    samples += [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(4)] + [c, (0, 0, 0)]
+    B = 2 * R + 1
+
+    def boxes(arrays):
+        out = []
+        for (i, j, k) in samples:
+            ix = torch.arange(i - R, i + R + 1, device="cuda") % n
+            iy = torch.arange(j - R, j + R + 1, device="cuda") % n
+            iz = torch.arange(k - R, k + R + 1, device="cuda") % n
+            out.append([a.index_select(0, iz).index_select(1, iy).index_select(2, ix).cpu().numpy()
+                        .astype(np.complex128 if a.is_complex() else np.float64) for a in arrays])
+        return out
+
+    before, vbox = boxes(lat.state()), boxes(V)
+    del V
+    lat.step(steps)
+    torch.cuda.synchronize()
+    after = [[b[a][R, R, R] for a in range(8)] for b in boxes(lat.state())]
+    del lat
+    free()
+    ol = oracle.Lattice3(B, B, B, cfg["dt"])
+    scale = max(max(abs(v) for v in row) for row in after)
+    big = 0
+    for box, vb, got in zip(before, vbox, after):
+        th = [np.ascontiguousarray(0.5 * cfg["dt"] * ((1.0 if a < 4 else -1.0) * cfg["m"] + vb[a])) for a in range(8)]
+        ol.step(box, th, steps)
+        for a in range(8):
+            assert abs(box[a][R, R, R] - got[a]) <= steps * 1e-6 * scale
+            big += abs(got[a]) > 1e-2 * scale
+    assert big >= 40
+
+
 @pytest.mark.parametrize("dtype,nz,beyond,tol", [(torch.complex64, 72, 64, 3e-6), (torch.complex128, 40, 32, 1e-13)])
 def test_sampled_oracle_parity_arrays_over_4gib(P, dtype, nz, beyond, tol):
     """Arrays larger than 4 GiB (4096 x 2048 x nz cells): 64-bit addressing in the
