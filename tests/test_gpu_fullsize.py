@@ -152,6 +152,32 @@ def test_full_oracle_parity_256_fp64(P):
     assert rel_l2(got, f) <= 1e-13
 
 
+def test_full_oracle_parity_128_fp64_1000_steps(P):
+    """Long-run parity: the Klein-step workload at 128^3 (complex128, default
+    two-step launches with the in-step functional every tenth step, as the
+    benchmark runs it) for 1000 steps against the oracle on every cell, with E_r
+    of both against its start."""
+    n, steps = 128, 1000
+    cfg = workloads.config_step3d(n, dtype=torch.complex128, device="cpu")
+    print("full parity 128^3, %d steps" % steps, flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    e0 = lat.norm()
+    for _ in range(steps // 10):
+        e = lat.step_norm(10)
+    e = e.cpu().numpy()
+    got = [t.cpu().numpy() for t in lat.state()]
+    del lat
+    free()
+    ol = oracle.Lattice3(n, n, n, cfg["dt"])
+    f = [np.ascontiguousarray(t.numpy()) for t in cfg["state"]]
+    ol.step(f, ol.theta_vz(cfg["m"], cfg["v_int"], cfg["v_half"]), steps)
+    assert rel_l2(got, f) <= 1e-13
+    eo = ol.energy(f)
+    assert abs(e[0] - eo[0]) <= 1e-13 * eo[2] and abs(e[0] - e0[0]) <= 1e-13 * abs(e0[0])
+
+
 def test_sampled_oracle_parity_256_fp64(P):
     """Klein-step workload at 256^3 (fused kernel, bench launch configuration): after
     3 steps, sampled cells against the oracle run on a periodic sub-box of half-width
