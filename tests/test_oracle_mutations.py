@@ -21,6 +21,8 @@ PINS = {
     "reverse": lambda: pins.test_reverse_is_inverse_dense(),
     "complex3": lambda: pins.test_complex_theta_dense_matches_oracle(3),
     "links3": lambda: pins.test_links_match_dense_from_potential(3),
+    "obs3": lambda: (pins.test_observables_single_site_3d(), pins.test_observables_eigen_plane_wave_3d((1, 2))),
+    "obs2": lambda: (pins.test_observables_single_site_2d(), pins.test_observables_eigen_plane_wave_2d(1)),
 }
 
 # (name, text in dirac_oracle.c, replacement, pins expected to catch it)
@@ -65,6 +67,23 @@ MUTANTS = [
     ("2D: S_u x neighbour offset",
      "/* u */ {{PX, CV, 1, 0, 0}, {MX, CV, -1, 0, 0},", "/* u */ {{PX, CV, 1, 0, 0}, {MX, CV, 1, 0, 0},",
      ["dense2"]),
+    ("observables: z offset of the half-integer sites doubled",
+     "double pz = 0.5 * (double)(2 * k + OFF3[a][2]);", "double pz = 0.5 * (double)(2 * k + 2 * OFF3[a][2]);",
+     ["obs3"]),
+    ("observables: x offset halved",
+     "double px = 0.5 * (double)(2 * i + OFF3[a][0]);", "double px = 0.5 * (double)(2 * i) + 0.25 * OFF3[a][0];",
+     ["obs3"]),
+    ("observables: strict > for the region boundary",
+     "if (pz >= z0) kadd(&acc[0], p);", "if (pz > z0) kadd(&acc[0], p);", ["obs3"]),
+    ("observables: per-component sum indexed by array",
+     "kadd(&acc[5 + a / 2], p);", "kadd(&acc[5 + a % 4], p);", ["obs3"]),
+    ("2D observables: y offset taken from x",
+     "double py = 0.5 * (double)(2 * j + OFF2[a][1]);", "double py = 0.5 * (double)(2 * j + OFF2[a][0]);",
+     ["obs2"]),
+    ("2D observables: strict > for the region boundary",
+     "if (px >= x0) kadd(&acc[0], p);", "if (px > x0) kadd(&acc[0], p);", ["obs2"]),
+    ("2D observables: per-component sum indexed by array",
+     "kadd(&acc[4 + a / 2], p);", "kadd(&acc[4 + a % 2], p);", ["obs2"]),
 ]
 
 

@@ -744,3 +744,153 @@ def test_linearised_rule_is_second_order(dim):
     assert diffs[1] > 1e-5
     for q in range(2):
         assert 3.6 < diffs[q] / diffs[q + 1] < 4.4, diffs
+
+
+# --------------------------------------------------------------------------
+# Observables of the plain density (its sum is the naive norm of Sect. 2.2 and
+# Sect. 3; a region sum is a transmitted or reflected fraction, Sect. 5).
+# Pinned against the site positions of the staggered grid (Sect. 2, Eq.
+# ABCDgrid; Sect. 3 for 2D) written out here from the paper by array name, not
+# from the oracle's tables: a single nonzero amplitude sits at one known site,
+# and an eigen plane wave of Sect. 2.1 has a uniform density per array, so its
+# first moments are the mean site coordinate of each array times its weight.
+# --------------------------------------------------------------------------
+#: paper positions of the amplitude stored for cell (i, j, k), by array name
+GRID3 = {"A0": (0.0, 0.0, 0.0), "A1": (0.5, 0.5, 0.0), "B0": (0.5, 0.0, 0.5), "B1": (0.0, 0.5, 0.5),
+         "C0": (0.0, 0.0, 0.5), "C1": (0.5, 0.5, 0.5), "D0": (0.5, 0.0, 0.0), "D1": (0.0, 0.5, 0.0)}
+NAMES3 = ["A0", "A1", "B0", "B1", "C0", "C1", "D0", "D1"]
+GRID2 = {"u0": (0.0, 0.0), "u1": (0.5, 0.5), "v0": (0.5, 0.0), "v1": (0.0, 0.5)}
+NAMES2 = ["u0", "u1", "v0", "v1"]
+
+
+def test_observables_single_site_3d():
+    """One amplitude at a time: the region sum includes the site iff z_s >= z0
+    (z0 on the site's own plane, and just above and below it), the moments are
+    the site's position times |X|^2, and the weight lands on its component."""
+    nx, ny, nz = 5, 4, 6
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    for a, name in enumerate(NAMES3):
+        for (i, j, k) in [(0, 0, 0), (4, 3, 5), (2, 1, 3)]:
+            f = lat.zeros()
+            val = 0.75 - 0.5j * (1 + a)          # dyadic: |val|^2 and its moments are exact
+            w = val.real ** 2 + val.imag ** 2
+            f[a][k, j, i] = val
+            ox, oy, oz = GRID3[name]
+            x, y, z = i + ox, j + oy, k + oz
+            comp = "ABCD".index(name[0])
+            out = lat.observe(f, z)
+            assert out[0] == w, (name, "z0 on the site plane is inside the region")
+            assert lat.observe(f, z + 1e-9)[0] == 0.0, (name, "just above the site")
+            assert lat.observe(f, z - 1e-9)[0] == w, (name, "just below the site")
+            assert lat.observe(f, z + 0.5)[0] == 0.0 and lat.observe(f, z - 0.5)[0] == w, name
+            assert out[4] == w
+            np.testing.assert_allclose(out[1:4], (x * w, y * w, z * w), rtol=1e-15, err_msg=name)
+            per = [0.0] * 4
+            per[comp] = w
+            assert list(out[5:9]) == per, name
+
+
+def test_observables_single_site_2d():
+    nx, ny = 5, 3
+    lat = oracle.Lattice2(nx, ny, DT2)
+    for a, name in enumerate(NAMES2):
+        for (i, j) in [(0, 0), (4, 2), (3, 1)]:
+            f = lat.zeros()
+            val = 0.25 + 1.5j * (2 + a)          # dyadic, as above
+            w = val.real ** 2 + val.imag ** 2
+            f[a][j, i] = val
+            ox, oy = GRID2[name]
+            x, y = i + ox, j + oy
+            out = lat.observe(f, x)
+            assert out[0] == w, name
+            assert lat.observe(f, x + 1e-9)[0] == 0.0 and lat.observe(f, x - 1e-9)[0] == w, name
+            assert out[3] == w
+            np.testing.assert_allclose(out[1:3], (x * w, y * w), rtol=1e-15, err_msg=name)
+            per = [0.0, 0.0]
+            per["uv".index(name[0])] = w
+            assert list(out[4:6]) == per, name
+
+
+def _uniform_moments(n_cells, mean_pos, weights):
+    """Sum of (position * weight) over arrays of uniform density: each array has
+    n_cells sites of weight w whose coordinate averages mean_pos."""
+    return sum(n_cells * w * p for w, p in zip(weights, mean_pos))
+
+
+@pytest.mark.parametrize("branches", [(1,), (2,), (1, 2), (3, 4)])
+def test_observables_eigen_plane_wave_3d(branches):
+    """Eigenkets of Sect. 2.1 (after Eq. pwdsip) at one k, alone or superposed on
+    the same energy shell: each array has the constant modulus of its spinor
+    component, so the per-component sums are 2 N |psi_c|^2 in closed form, the
+    first moments are the mean site coordinate times the weight, and the region
+    z >= z0 holds exactly the sites on planes from z0 up.  Evolving the state
+    (it is an eigenmode) leaves all of them unchanged."""
+    nx, ny, nz = 6, 4, 10
+    m = 0.5
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    k = (2 * np.pi * 1 / nx, 2 * np.pi * 1 / ny, 2 * np.pi * 3 / nz)
+    amps = np.zeros(4, complex)
+    for b in branches:
+        w, a4 = eigenket3(k, m, DT3, b)
+        amps += np.asarray(a4, complex)
+    f = plane_wave3(lat.shape, k, list(amps), w, DT3)
+    ncell = nx * ny * nz
+    wt = [abs(amps["ABCD".index(nm[0])]) ** 2 for nm in NAMES3]
+    z0 = 4.5                     # B and C sites sit on z = 4.5; A and D on z = 5
+    region = sum(wt[a] * nx * ny * sum(1 for kk in range(nz) if kk + GRID3[nm][2] >= z0)
+                 for a, nm in enumerate(NAMES3))
+    expect = [region]
+    for ax, nn in enumerate((nx, ny, nz)):
+        mean = [(nn - 1) / 2.0 + GRID3[nm][ax] for nm in NAMES3]
+        expect.append(_uniform_moments(ncell, mean, wt))
+    expect.append(ncell * sum(wt))
+    expect += [2 * ncell * abs(amps[c]) ** 2 for c in range(4)]
+    th = lat.theta(m)
+    for steps in (0, 7):
+        g = [a.copy() for a in f]
+        lat.step(g, th, steps)
+        out = lat.observe(g, z0)
+        np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-12, err_msg=str((branches, steps)))
+
+
+@pytest.mark.parametrize("branch", [1, 2])
+def test_observables_eigen_plane_wave_2d(branch):
+    nx, ny = 8, 6
+    m = 0.7
+    lat = oracle.Lattice2(nx, ny, DT2)
+    k = (2 * np.pi * 3 / nx, 2 * np.pi * 1 / ny)
+    w, amps = eigenket2(k, m, DT2, branch)
+    f = plane_wave2(lat.shape, k, amps, w, DT2)
+    ncell = nx * ny
+    wt = [abs(amps["uv".index(nm[0])]) ** 2 for nm in NAMES2]
+    x0 = 3.5                     # u1 and v0 sit on x = 3.5
+    region = sum(wt[a] * ny * sum(1 for i in range(nx) if i + GRID2[nm][0] >= x0) for a, nm in enumerate(NAMES2))
+    expect = [region]
+    for ax, nn in enumerate((nx, ny)):
+        mean = [(nn - 1) / 2.0 + GRID2[nm][ax] for nm in NAMES2]
+        expect.append(_uniform_moments(ncell, mean, wt))
+    expect.append(ncell * sum(wt))
+    expect += [2 * ncell * abs(amps[c]) ** 2 for c in range(2)]
+    th = lat.theta(m)
+    for steps in (0, 9):
+        g = [a.copy() for a in f]
+        lat.step(g, th, steps)
+        np.testing.assert_allclose(lat.observe(g, x0), expect, rtol=1e-12, atol=1e-12, err_msg=str(steps))
+
+
+def test_observables_translation_covariance_3d():
+    """Moving a localised random state by one cell along x, y or z moves the
+    matching first moment by the norm and leaves the rest (norm, per-component
+    sums) unchanged; the region sum moves by the weight of one plane pair."""
+    g = rng(77)
+    nx, ny, nz = 7, 6, 9
+    lat = oracle.Lattice3(nx, ny, nz, DT3)
+    f = lat.zeros()
+    for a in range(8):
+        f[a][2:5, 1:4, 1:5] = g.standard_normal((3, 3, 4)) + 1j * g.standard_normal((3, 3, 4))
+    base = lat.observe(f, 3.0)
+    for ax in range(3):
+        sh = [np.ascontiguousarray(np.roll(a, 1, axis=2 - ax)) for a in f]
+        out = lat.observe(sh, 3.0)
+        np.testing.assert_allclose(out[1 + ax], base[1 + ax] + base[4], rtol=1e-13)
+        np.testing.assert_allclose(out[4:], base[4:], rtol=1e-13)
