@@ -68,6 +68,10 @@ def load(path: str):
     L.oracle_adjoint3.argtypes = [P] * 7
     L.oracle_adjoint2.argtypes = [P] * 7
     L.oracle_threads.restype = ctypes.c_int
+    L.oracle_set_threads.restype = ctypes.c_int
+    L.oracle_set_threads.argtypes = [ctypes.c_int]
+    L.oracle_set_zero_bc.restype = ctypes.c_int
+    L.oracle_set_zero_bc.argtypes = [ctypes.c_int]
     return L
 
 
@@ -80,6 +84,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads for later oracle calls; returns the count now in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def _ptrs(arrs, dtype):
@@ -96,10 +105,21 @@ def _check(rc, what):
         raise RuntimeError("%s failed with code %d" % (what, rc))
 
 
-class Lattice3:
-    """(3+1)D lattice of nx*ny*nz cells, periodic, r_j = dt / d_j."""
+class _Boundary:
+    """Each call into the C oracle first sets the lattice's boundary: periodic,
+    or zero values outside the lattice (zero_bc)."""
+    zero_bc = False
 
-    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0):
+    def _bc(self):
+        lib().oracle_set_zero_bc(1 if self.zero_bc else 0)
+        return lib()
+
+
+class Lattice3(_Boundary):
+    """(3+1)D lattice of nx*ny*nz cells, periodic (or zero outside, zero_bc), r_j = dt / d_j."""
+
+    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0, zero_bc=False):
+        self.zero_bc = bool(zero_bc)
         self.shape = (int(nz), int(ny), int(nx))
         self.n = (ctypes.c_int64 * 3)(int(nx), int(ny), int(nz))
         self.dt = float(dt)
@@ -146,50 +166,51 @@ class Lattice3:
                 raise ValueError("links with a complex theta are not combined here")
             u = _ptrs(links, np.complex128)
             for _ in range(n):
-                _check(lib().oracle_step3_links(self.n, self.r, p, t, u), "oracle_step3_links")
+                _check(self._bc().oracle_step3_links(self.n, self.r, p, t, u), "oracle_step3_links")
             return
         if thi is not None:
             ti = _ptrs(thi, np.float64)
             for _ in range(n):
-                _check(lib().oracle_step3c(self.n, self.r, p, t, ti), "oracle_step3c")
+                _check(self._bc().oracle_step3c(self.n, self.r, p, t, ti), "oracle_step3c")
             return
         for _ in range(n):
-            _check(lib().oracle_step3(self.n, self.r, p, t), "oracle_step3")
+            _check(self._bc().oracle_step3(self.n, self.r, p, t), "oracle_step3")
 
     def energy_links(self, f, links):
         """E_r with gauge links (see oracle_energy3_links)."""
         out = (ctypes.c_double * 3)()
-        _check(lib().oracle_energy3_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
+        _check(self._bc().oracle_energy3_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
                                           out), "oracle_energy3_links")
         return tuple(out)
 
     def reverse(self, f, th, n=1):
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
         for _ in range(n):
-            _check(lib().oracle_reverse3(self.n, self.r, p, t), "oracle_reverse3")
+            _check(self._bc().oracle_reverse3(self.n, self.r, p, t), "oracle_reverse3")
 
     def energy(self, f):
         """(E_r as Eq. EPM, E_r summed by parts on the C,D sites, plain norm)."""
         out = (ctypes.c_double * 3)()
-        _check(lib().oracle_energy3(self.n, self.r, _ptrs(f, np.complex128), out), "oracle_energy3")
+        _check(self._bc().oracle_energy3(self.n, self.r, _ptrs(f, np.complex128), out), "oracle_energy3")
         return tuple(out)
 
     def observe(self, f, z0):
         """(P[z >= z0], sum x p, sum y p, sum z p, plain norm, |A|^2, |B|^2, |C|^2, |D|^2)."""
         out = (ctypes.c_double * 9)()
-        _check(lib().oracle_observe3(self.n, _ptrs(f, np.complex128), float(z0), out), "oracle_observe3")
+        _check(self._bc().oracle_observe3(self.n, _ptrs(f, np.complex128), float(z0), out), "oracle_observe3")
         return tuple(out)
 
     def adjoint(self, pre, post, lam, th, gth):
-        _check(lib().oracle_adjoint3(self.n, self.r, _ptrs(pre, np.complex128), _ptrs(post, np.complex128),
+        _check(self._bc().oracle_adjoint3(self.n, self.r, _ptrs(pre, np.complex128), _ptrs(post, np.complex128),
                                      _ptrs(lam, np.complex128), _ptrs(th, np.float64),
                                      _ptrs(gth, np.float64)), "oracle_adjoint3")
 
 
-class Lattice2:
-    """(2+1)D lattice of nx*ny cells, periodic, r_j = dt / d_j."""
+class Lattice2(_Boundary):
+    """(2+1)D lattice of nx*ny cells, periodic (or zero outside, zero_bc), r_j = dt / d_j."""
 
-    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0):
+    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0, zero_bc=False):
+        self.zero_bc = bool(zero_bc)
         self.shape = (int(ny), int(nx))
         self.n = (ctypes.c_int64 * 2)(int(nx), int(ny))
         self.dt = float(dt)
@@ -224,42 +245,42 @@ class Lattice2:
                 raise ValueError("links with a complex theta are not combined here")
             u = _ptrs(links, np.complex128)
             for _ in range(n):
-                _check(lib().oracle_step2_links(self.n, self.r, p, t, u), "oracle_step2_links")
+                _check(self._bc().oracle_step2_links(self.n, self.r, p, t, u), "oracle_step2_links")
             return
         if thi is not None:
             ti = _ptrs(thi, np.float64)
             for _ in range(n):
-                _check(lib().oracle_step2c(self.n, self.r, p, t, ti), "oracle_step2c")
+                _check(self._bc().oracle_step2c(self.n, self.r, p, t, ti), "oracle_step2c")
             return
         for _ in range(n):
-            _check(lib().oracle_step2(self.n, self.r, p, t), "oracle_step2")
+            _check(self._bc().oracle_step2(self.n, self.r, p, t), "oracle_step2")
 
     def energy_links(self, f, links):
         """E_r with gauge links (see oracle_energy2_links)."""
         out = (ctypes.c_double * 3)()
-        _check(lib().oracle_energy2_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
+        _check(self._bc().oracle_energy2_links(self.n, self.r, _ptrs(f, np.complex128), _ptrs(links, np.complex128),
                                           out), "oracle_energy2_links")
         return tuple(out)
 
     def reverse(self, f, th, n=1):
         p, t = _ptrs(f, np.complex128), _ptrs(th, np.float64)
         for _ in range(n):
-            _check(lib().oracle_reverse2(self.n, self.r, p, t), "oracle_reverse2")
+            _check(self._bc().oracle_reverse2(self.n, self.r, p, t), "oracle_reverse2")
 
     def energy(self, f):
         """(E_r with delta_+, E_r with delta_- as printed, plain norm)."""
         out = (ctypes.c_double * 3)()
-        _check(lib().oracle_energy2(self.n, self.r, _ptrs(f, np.complex128), out), "oracle_energy2")
+        _check(self._bc().oracle_energy2(self.n, self.r, _ptrs(f, np.complex128), out), "oracle_energy2")
         return tuple(out)
 
     def observe(self, f, x0):
         """(P[x >= x0], sum x p, sum y p, plain norm, |u|^2, |v|^2)."""
         out = (ctypes.c_double * 6)()
-        _check(lib().oracle_observe2(self.n, _ptrs(f, np.complex128), float(x0), out), "oracle_observe2")
+        _check(self._bc().oracle_observe2(self.n, _ptrs(f, np.complex128), float(x0), out), "oracle_observe2")
         return tuple(out)
 
     def adjoint(self, pre, post, lam, th, gth):
-        _check(lib().oracle_adjoint2(self.n, self.r, _ptrs(pre, np.complex128), _ptrs(post, np.complex128),
+        _check(self._bc().oracle_adjoint2(self.n, self.r, _ptrs(pre, np.complex128), _ptrs(post, np.complex128),
                                      _ptrs(lam, np.complex128), _ptrs(th, np.float64),
                                      _ptrs(gth, np.float64)), "oracle_adjoint2")
 

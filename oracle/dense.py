@@ -17,6 +17,9 @@ per cell length (a = q A Delta / (hbar c)), positions in cell units:
                  difference psi(+) - psi(-) replaced by psi(+) - psi(-)
                  - i a_j (psi(+) + psi(-))/2 with a_j taken at the row's site.
 
+zero_bc=True drops every coupling to a position outside the lattice (zero
+values there) instead of wrapping it periodically.
+
 State vector order: the arrays of the oracle's convention concatenated,
 3D: A0 A1 B0 B1 | C0 C1 D0 D1, 2D: u0 u1 | v0 v1, each flattened [k][j][i].
 """
@@ -58,8 +61,8 @@ def _factors(a_fn, rule, pos2, axis, e2):
 
 
 class Dense3:
-    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0, a_fn=None, rule="exact"):
-        self.a_fn, self.rule = a_fn, rule
+    def __init__(self, nx, ny, nz, dt, dx=1.0, dy=1.0, dz=1.0, a_fn=None, rule="exact", zero_bc=False):
+        self.a_fn, self.rule, self.zero_bc = a_fn, rule, zero_bc
         self.nx, self.ny, self.nz = nx, ny, nz
         self.dt = dt
         self.r = {"x": dt / dx, "y": dt / dy, "z": dt / dz}
@@ -78,6 +81,9 @@ class Dense3:
         self.K = self._difference_operator()
 
     def _find(self, comp, pos):
+        """Row index of the site, or None for a zero ghost outside the lattice."""
+        if self.zero_bc and not all(0 <= p < 2 * n for p, n in zip(pos, (self.nx, self.ny, self.nz))):
+            return None
         key = (comp, (pos[0] % (2 * self.nx), pos[1] % (2 * self.ny), pos[2] % (2 * self.nz)))
         return self.index[key]
 
@@ -92,8 +98,11 @@ class Dense3:
                 plus = (pos[0] + e[0], pos[1] + e[1], pos[2] + e[2])
                 minus = (pos[0] - e[0], pos[1] - e[1], pos[2] - e[2])
                 fp, fm = _factors(self.a_fn, self.rule, pos, axis[d], e)
-                K[s, self._find(src, plus)] += c * self.r[d] * fp
-                K[s, self._find(src, minus)] -= c * self.r[d] * fm
+                ip, im = self._find(src, plus), self._find(src, minus)
+                if ip is not None:
+                    K[s, ip] += c * self.r[d] * fp
+                if im is not None:
+                    K[s, im] -= c * self.r[d] * fm
         return K
 
     def step_matrix(self, theta):
@@ -132,8 +141,8 @@ class Dense3:
 
 
 class Dense2:
-    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0, a_fn=None, rule="exact"):
-        self.a_fn, self.rule = a_fn, rule
+    def __init__(self, nx, ny, dt, dx=1.0, dy=1.0, a_fn=None, rule="exact", zero_bc=False):
+        self.a_fn, self.rule, self.zero_bc = a_fn, rule, zero_bc
         self.nx, self.ny = nx, ny
         self.dt = dt
         self.r = {"x": dt / dx, "y": dt / dy}
@@ -151,6 +160,8 @@ class Dense2:
         self.K = self._difference_operator()
 
     def _find(self, comp, pos):
+        if self.zero_bc and not (0 <= pos[0] < 2 * self.nx and 0 <= pos[1] < 2 * self.ny):
+            return None
         return self.index[(comp, (pos[0] % (2 * self.nx), pos[1] % (2 * self.ny)))]
 
     def _difference_operator(self):
@@ -161,8 +172,12 @@ class Dense2:
             for d, c, src in _RULES2[comp]:
                 e = unit[d]
                 fp, fm = _factors(self.a_fn, self.rule, pos, axis[d], e)
-                K[s, self._find(src, (pos[0] + e[0], pos[1] + e[1]))] += c * self.r[d] * fp
-                K[s, self._find(src, (pos[0] - e[0], pos[1] - e[1]))] -= c * self.r[d] * fm
+                ip = self._find(src, (pos[0] + e[0], pos[1] + e[1]))
+                im = self._find(src, (pos[0] - e[0], pos[1] - e[1]))
+                if ip is not None:
+                    K[s, ip] += c * self.r[d] * fp
+                if im is not None:
+                    K[s, im] -= c * self.r[d] * fm
         return K
 
     def step_matrix(self, theta):

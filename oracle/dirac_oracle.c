@@ -56,6 +56,11 @@ enum { CA = 0, CB = 1, CC = 2, CD = 3 };       /* 3D components */
 enum { CU = 0, CV = 1 };                       /* 2D components */
 
 static int g_bad_lookup = 0;                   /* set when a position is not a site */
+/* Boundary: 0 = periodic wrap in every direction; 1 = zero values outside the
+ * lattice (a site whose doubled coordinate leaves [0, 2n) holds 0).  The
+ * summation by parts of the Lemmas (Sect. 2, Sect. 3) then has no boundary
+ * terms either, so E_r stays exactly conserved. */
+static int g_zero_bc = 0;
 
 static int64_t wrap(int64_t a, int64_t n) {
     a %= n;
@@ -81,6 +86,8 @@ static const int OFF3[8][3] = {
 
 /* Address of component `comp` at doubled position (X,Y,Z); NULL if no such site. */
 static cplx *site3(const lat3 *L, int comp, int64_t X, int64_t Y, int64_t Z) {
+    if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny || Z < 0 || Z >= 2 * L->nz))
+        return NULL;                           /* outside: a zero ghost, not a lookup error */
     X = wrap(X, 2 * L->nx);
     Y = wrap(Y, 2 * L->ny);
     Z = wrap(Z, 2 * L->nz);
@@ -300,6 +307,7 @@ int oracle_reverse3(const int64_t n[3], const double r[3], void *const f[8], con
 /* One forward step with gauge links U[24] (see stencil3_links). */
 int oracle_step3_links(const int64_t n[3], const double r[3], void *const f[8], const double *const th[8],
                        void *const U[24]) {
+    if (g_zero_bc) return -1;                  /* links: periodic lattices only */
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     for (int q = 0; q < 24; ++q)
@@ -400,6 +408,7 @@ int oracle_energy3(const int64_t n[3], const double r[3], void *const f[8], doub
  */
 int oracle_energy3_links(const int64_t n[3], const double r[3], void *const f[8], void *const U[24],
                          double out[3]) {
+    if (g_zero_bc) return -1;                  /* links: periodic lattices only */
     lat3 L;
     if (mk3(&L, n, f)) return -1;
     for (int q = 0; q < 24; ++q)
@@ -554,6 +563,8 @@ typedef struct {
 static const int OFF2[4][2] = {{0, 0}, {1, 1}, {1, 0}, {0, 1}};
 
 static cplx *site2(const lat2 *L, int comp, int64_t X, int64_t Y) {
+    if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny))
+        return NULL;                           /* outside: a zero ghost */
     X = wrap(X, 2 * L->nx);
     Y = wrap(Y, 2 * L->ny);
     for (int s = 0; s < 2; ++s) {
@@ -699,6 +710,7 @@ int oracle_reverse2(const int64_t n[2], const double r[3], void *const f[4], con
 /* One forward (2+1)D step with gauge links U[8] (see stencil2_links). */
 int oracle_step2_links(const int64_t n[2], const double r[3], void *const f[4], const double *const th[4],
                        void *const U[8]) {
+    if (g_zero_bc) return -1;                  /* links: periodic lattices only */
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     for (int q = 0; q < 8; ++q)
@@ -713,6 +725,7 @@ int oracle_step2_links(const int64_t n[2], const double r[3], void *const f[4], 
  * out[1] = sum |psi|^2 - Re sum_u conj(u) S_u(v), out[2] = sum |psi|^2. */
 int oracle_energy2_links(const int64_t n[2], const double r[3], void *const f[4], void *const U[8],
                          double out[3]) {
+    if (g_zero_bc) return -1;                  /* links: periodic lattices only */
     lat2 L;
     if (mk2(&L, n, f)) return -1;
     for (int q = 0; q < 8; ++q)
@@ -847,4 +860,26 @@ int oracle_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* Set the number of OpenMP threads of later calls (n >= 1); returns the
+ * number now in effect.  The benchmark times the oracle on one thread and on
+ * all host cores. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* Boundary of later calls: zero != 0 for zero values outside the lattice,
+ * 0 for periodic wrap (the default).  Gauge-link calls are periodic only and
+ * return -1 while zero boundaries are set.  Returns the previous setting. */
+int oracle_set_zero_bc(int zero) {
+    int old = g_zero_bc;
+    g_zero_bc = zero != 0;
+    return old;
 }

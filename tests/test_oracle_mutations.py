@@ -23,6 +23,8 @@ PINS = {
     "links3": lambda: pins.test_links_match_dense_from_potential(3),
     "obs3": lambda: (pins.test_observables_single_site_3d(), pins.test_observables_eigen_plane_wave_3d((1, 2))),
     "obs2": lambda: (pins.test_observables_single_site_2d(), pins.test_observables_eigen_plane_wave_2d(1)),
+    "zbc3": lambda: (pins.test_zero_bc_dense_matches_oracle_3d((3, 2, 4)), pins.test_zero_bc_conserves_functional(3)),
+    "zbc2": lambda: (pins.test_zero_bc_dense_matches_oracle_2d((4, 3)), pins.test_zero_bc_conserves_functional(2)),
 }
 
 # (name, text in dirac_oracle.c, replacement, pins expected to catch it)
@@ -84,6 +86,17 @@ MUTANTS = [
      "if (px >= x0) kadd(&acc[0], p);", "if (px > x0) kadd(&acc[0], p);", ["obs2"]),
     ("2D observables: per-component sum indexed by array",
      "kadd(&acc[4 + a / 2], p);", "kadd(&acc[4 + a % 2], p);", ["obs2"]),
+    ("zero boundary: upper x face off by one (the outside site wraps)",
+     "if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny || Z < 0 || Z >= 2 * L->nz))",
+     "if (g_zero_bc && (X < 0 || X > 2 * L->nx || Y < 0 || Y >= 2 * L->ny || Z < 0 || Z >= 2 * L->nz))",
+     ["zbc3"]),
+    ("zero boundary: z left periodic",
+     "if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny || Z < 0 || Z >= 2 * L->nz))",
+     "if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny))", ["zbc3"]),
+    ("2D zero boundary: lower y face missing",
+     "if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y < 0 || Y >= 2 * L->ny))\n        return NULL;                           /* outside: a zero ghost */",
+     "if (g_zero_bc && (X < 0 || X >= 2 * L->nx || Y >= 2 * L->ny))\n        return NULL;                           /* outside: a zero ghost */",
+     ["zbc2"]),
 ]
 
 

@@ -894,3 +894,98 @@ def test_observables_translation_covariance_3d():
         out = lat.observe(sh, 3.0)
         np.testing.assert_allclose(out[1 + ax], base[1 + ax] + base[4], rtol=1e-13)
         np.testing.assert_allclose(out[4:], base[4:], rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Zero values outside the lattice (a Dirichlet frame).  The Lemmas of Sect. 2
+# and Sect. 3 sum by parts over the lattice; with zero ghosts, as with periodic
+# wrap, no boundary terms remain, so E_r is conserved exactly.  Pinned by the
+# dense matrix assembled with the outside couplings dropped, M^H G M = G, the
+# reversed step, and agreement with the periodic oracle while the light cone
+# of an interior state has not reached the boundary.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(3, 2, 4), (2, 3, 2), (4, 4, 3)])
+def test_zero_bc_dense_matches_oracle_3d(shape):
+    g = rng(201)
+    nx, ny, nz = shape
+    lat = oracle.Lattice3(nx, ny, nz, DT3, zero_bc=True)
+    D = Dense3(nx, ny, nz, DT3, zero_bc=True)
+    th = rand_theta(lat.shape, 8, g)
+    f = rand_state(lat.shape, 8, g)
+    x = D.pack(f)
+    M = D.step_matrix(D.pack(th).real)
+    lat.step(f, th, 3)
+    assert rel_l2([D.pack(f)], [M @ (M @ (M @ x))]) < 1e-14
+    # the periodic matrix is a different operator on these shapes
+    Mp = Dense3(nx, ny, nz, DT3).step_matrix(D.pack(th).real)
+    assert np.abs(Mp - M).max() > 0.1
+
+
+@pytest.mark.parametrize("shape", [(4, 3), (2, 5), (1, 3)])
+def test_zero_bc_dense_matches_oracle_2d(shape):
+    g = rng(202)
+    nx, ny = shape
+    lat = oracle.Lattice2(nx, ny, DT2, zero_bc=True)
+    D = Dense2(nx, ny, DT2, zero_bc=True)
+    th = rand_theta(lat.shape, 4, g)
+    f = rand_state(lat.shape, 4, g)
+    x = D.pack(f)
+    M = D.step_matrix(D.pack(th).real)
+    lat.step(f, th, 3)
+    assert rel_l2([D.pack(f)], [M @ (M @ (M @ x))]) < 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_bc_conserves_functional(dim):
+    """M^H G M = G for the truncated operator (random site-dependent theta), the
+    oracle's E_r equals psi^H G psi in both its forms, and a long run with
+    time-dependent theta conserves it to rounding."""
+    g = rng(203 + dim)
+    if dim == 3:
+        lat, D, cnt = oracle.Lattice3(3, 4, 2, DT3, zero_bc=True), Dense3(3, 4, 2, DT3, zero_bc=True), 8
+    else:
+        lat, D, cnt = oracle.Lattice2(5, 3, DT2, zero_bc=True), Dense2(5, 3, DT2, zero_bc=True), 4
+    th = rand_theta(lat.shape, cnt, g)
+    M = D.step_matrix(D.pack(th).real)
+    G = D.gram()
+    assert np.abs(M.conj().T @ G @ M - G).max() < 1e-13
+    f = rand_state(lat.shape, cnt, g)
+    x = D.pack(f)
+    e = lat.energy(f)
+    ref = float(np.real(x.conj() @ G @ x))
+    assert abs(e[0] - ref) <= 1e-13 * abs(ref)
+    if dim == 3:
+        assert abs(e[1] - ref) <= 1e-13 * abs(ref)
+    e0 = e[0]
+    for _ in range(300):
+        lat.step(f, rand_theta(lat.shape, cnt, g, scale=0.8))
+    assert abs(lat.energy(f)[0] - e0) <= 1e-13 * abs(e0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_bc_reverse_and_light_cone(dim):
+    """The reversed step undoes the step; a state four cells from every face
+    evolves for two steps exactly as on the periodic lattice (its light cone,
+    one cell per step, does not reach the boundary), and differently once it
+    has."""
+    g = rng(205 + dim)
+    if dim == 3:
+        mk = lambda z: oracle.Lattice3(10, 9, 11, DT3, zero_bc=z)
+        cnt, sl = 8, (slice(4, 7), slice(4, 5), slice(4, 6))
+    else:
+        mk = lambda z: oracle.Lattice2(10, 9, DT2, zero_bc=z)
+        cnt, sl = 4, (slice(4, 5), slice(4, 6))
+    zl, pl = mk(True), mk(False)
+    th = rand_theta(zl.shape, cnt, g)
+    f = [np.zeros(zl.shape, np.complex128) for _ in range(cnt)]
+    for a in f:
+        a[sl] = g.standard_normal(a[sl].shape) + 1j * g.standard_normal(a[sl].shape)
+    fz, fp = [a.copy() for a in f], [a.copy() for a in f]
+    zl.step(fz, th, 2)
+    pl.step(fp, th, 2)
+    assert all(np.array_equal(a, b) for a, b in zip(fz, fp))
+    zl.step(fz, th, 6)
+    pl.step(fp, th, 6)
+    assert rel_l2(fz, fp) > 1e-6
+    zl.reverse(fz, th, 8)
+    assert rel_l2(fz, f) < 1e-13
