@@ -18,7 +18,7 @@
  * v0 (i+1/2,j), v1 (i,j+1/2) on sheet n.  Each array holds one complex
  * amplitude per cell, interleaved (re, im), [k][j][i] with i fastest, no
  * padding: complex64 (DIRAC_C64) or complex128 (DIRAC_C128).  Boundaries are
- * periodic in every direction.
+ * periodic in every direction (zero outside the lattice with DIRAC_ZERO_BC).
  *
  * Ownership: every device buffer is allocated by the caller and borrowed by
  * raw pointer; it must stay valid while bound.  The library allocates only its
@@ -79,6 +79,17 @@ enum dirac_status {
  * dirac_seed_region, dirac_adjoint_vz and links are refused (DIRAC_E_STATE).
  */
 #define DIRAC_SLAB_Z 2u
+/*
+ * Zero values outside the lattice (2D and 3D): every neighbour that lies
+ * across a face of the box of cells reads as zero, in the steps, the reversed
+ * steps and the conserved functional, instead of wrapping periodically.  The
+ * summation by parts in the proofs of the Lemmas (Sect. 2, Sect. 3) leaves no
+ * boundary terms with zero values outside either, so E_r stays exactly
+ * conserved.  Steps run on the split kernels (one launch per half-step, in
+ * place).  Not combined with DIRAC_SLAB_Z (DIRAC_E_ARG); dirac_set_links and
+ * dirac_adjoint_vz are refused (DIRAC_E_STATE).
+ */
+#define DIRAC_ZERO_BC 4u
 
 /* step kernels (dirac_set_kernel) */
 enum dirac_kernel {
@@ -102,7 +113,8 @@ const char *dirac_status_string(int status);
  *   dt     time step (Delta_o = dt); dx, dy, dz > 0 grid spacings.
  *   flags  DIRAC_ALLOW_UNSTABLE to accept sum r_j^2 > 1 (the scheme then
  *          grows, Sect. 2.2 and Sect. 3 "reality condition"); DIRAC_SLAB_Z
- *          (ndim == 3) for z-slab mode, nz then counting interior planes.
+ *          (ndim == 3) for z-slab mode, nz then counting interior planes;
+ *          DIRAC_ZERO_BC for zero values outside the lattice.
  * Validates the stability bound sum_j r_j^2 <= 1 of Sect. 2.2 (3D) / Sect. 3
  * (2D).  The context starts with m = 0, V = 0.  Makes no HIP call.
  */
@@ -215,6 +227,16 @@ int dirac_set_theta_field(dirac_ctx *ctx, void *const coef[]);
  * stream; DIRAC_E_ARG for null pointers or n < 0, DIRAC_E_HIP on launch failure.
  */
 int dirac_coef_from_theta(void *coef, const void *theta, int64_t n, void *stream);
+
+/*
+ * dirac_coef_from_theta computed on the host: coef[2t], coef[2t+1] = the
+ * complex64 record gamma(theta[t]) (the same rounding, from the same source,
+ * as the device records and the V(z) tables) for t < n.  theta: host array of
+ * n doubles; coef: host array of 2n floats.  Context-free, synchronous, makes
+ * no HIP call; DIRAC_E_ARG for null pointers or n < 0, DIRAC_E_NONFINITE for a
+ * non-finite theta (records before it are written).
+ */
+int dirac_coef_from_theta_host(float *coef, const double *theta, int64_t n);
 
 /*
  * As dirac_coef_from_theta for a complex theta = theta[t] + i theta_im[t]
@@ -398,7 +420,11 @@ int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[],
  * Advance every lattice by n steps.  mode 0: one persistent launch for all n
  * steps with per-lattice step barriers; mode 1: one launch per step over all
  * lattices (both replayed from a captured HIP graph when use_graph != 0).
- * After an odd n the partner buffers hold the state (dirac_current).
+ * After an odd n the partner buffers hold the state (dirac_current).  Every
+ * per-lattice wait of mode 0 is bounded: if one times out (a grid that is not
+ * co-resident) every workgroup leaves, the call returns DIRAC_E_HIP, and the
+ * lattices are left stepped unevenly across both buffer sets -- the bound
+ * state is then invalid and must be reloaded.
  */
 int dirac_batch_run(dirac_ctx *ctx, int64_t n, int mode, int use_graph, void *stream);
 
@@ -411,6 +437,9 @@ int dirac_batch_norms(dirac_ctx *ctx, double *out, void *stream);
  * each mode by timing every candidate for a few steps on the bound lattices.
  * This advances the bound state by an even number of steps (it stays in the
  * same buffer set); callers that need the state unchanged save and restore it.
+ * If a persistent (mode 0) candidate times out (see dirac_batch_run) it is
+ * skipped, the choice is still made, stored and written to chosen_out, and the
+ * call returns DIRAC_E_STATE: the bound state is no longer valid (reload it).
  * cache_path: JSON file consulted first and updated (NULL = no cache), keyed
  * by device architecture, dtype and batch shape.  The choice is kept in the
  * context.  Synchronous.  chosen_out (may be NULL) receives

@@ -16,7 +16,9 @@ DIRAC_C64 = 1
 DIRAC_C128 = 2
 DIRAC_ALLOW_UNSTABLE = 1
 DIRAC_SLAB_Z = 2
+DIRAC_ZERO_BC = 4
 DIRAC_KERNEL_AUTO, DIRAC_KERNEL_SPLIT, DIRAC_KERNEL_FUSED, DIRAC_KERNEL_FUSED2 = 0, 1, 2, 3
+DIRAC_E_STATE = -6
 STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SHAPE", -3: "DIRAC_E_UNSTABLE",
           -4: "DIRAC_E_NONFINITE", -5: "DIRAC_E_HIP", -6: "DIRAC_E_STATE"}
 
@@ -29,7 +31,7 @@ EXPORTS = (
     "dirac_seed_region", "dirac_adjoint_vz", "dirac_batch_create", "dirac_batch_bind", "dirac_batch_run",
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
     "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields", "dirac_set_mass",
-    "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune",
+    "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune", "dirac_coef_from_theta_host",
 )
 
 
@@ -85,6 +87,7 @@ def lib():
         "dirac_batch_norms": ([P, ctypes.POINTER(D), P], I),
         "dirac_batch_autotune": ([P, ctypes.c_char_p, ctypes.POINTER(I), P], I),
         "dirac_coef_from_theta": ([P, P, I64, P], I),
+        "dirac_coef_from_theta_host": ([P, P, I64], I),
         "dirac_coef_from_theta_c": ([P, P, P, I64, P], I),
         "dirac_set_potential_im_z": ([P, P, P, I64], I),
         "dirac_set_links": ([P, PP], I),

@@ -91,7 +91,20 @@ class BatchedLattices:
         return [tuple(out[3 * b:3 * b + 3]) for b in range(self.count)]
 
     def autotune(self, cache_path=None):
-        ch = ctypes.c_int()
-        check(lib().dirac_batch_autotune(self._ctx, cache_path.encode() if cache_path else None,
-                                         ctypes.byref(ch), _stream_handle()), self._ctx)
+        """Tile choice per mode; the state is advanced by an even number of steps.
+        If a persistent candidate timed out (the library then reports the bound
+        state as invalid), the state from before the call is restored."""
+        cur = self.current
+        snap = [[t.clone() for t in self.bufs[cur][b]] for b in range(self.count)]
+        ch = ctypes.c_int(-1)
+        rc = lib().dirac_batch_autotune(self._ctx, cache_path.encode() if cache_path else None,
+                                        ctypes.byref(ch), _stream_handle())
+        if rc == _abi.DIRAC_E_STATE and ch.value >= 0:
+            check(lib().dirac_set_current(self._ctx, cur), self._ctx)
+            for b in range(self.count):
+                for t, s0 in zip(self.bufs[cur][b], snap[b]):
+                    t.copy_(s0)
+        else:
+            check(rc, self._ctx)
+        del snap
         return int(ch.value) & 0xff, int(ch.value) >> 8

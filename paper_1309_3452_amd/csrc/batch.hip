@@ -600,6 +600,7 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
         BCHK(c, hipEventCreate(&e0));
         BCHK(c, hipEventCreate(&e1));
         const int warm = 2, timed = 8;
+        bool aborted = false;
         for (int mode = 1; mode >= 0; --mode) {
             float best = 1e30f;
             for (int q = 0; q < kNumCands; ++q) {
@@ -616,7 +617,10 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
                 if (flips & 1) c->cur = 1 - c->cur;
                 BCHK(c, hipEventRecord(e1, s));
                 BCHK(c, hipEventSynchronize(e1));
-                if (mode == 0 && check_abort(c, s)) continue;   // candidate unusable here
+                if (mode == 0 && check_abort(c, s)) {   // candidate unusable here
+                    aborted = true;
+                    continue;
+                }
                 float ms = 0.f;
                 BCHK(c, hipEventElapsedTime(&ms, e0, e1));
                 if (ms < best) {
@@ -630,6 +634,14 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
         if (pick[0] < 0) pick[0] = kDefaultCand;
         if (pick[1] < 0) pick[1] = kDefaultCand;
         if (cache_path) cache_store(cache_path, key, pick);
+        if (aborted) {
+            // an aborted persistent launch leaves lattices stepped unevenly across
+            // both buffer sets: keep the choice, report that the state is gone
+            c->tune_choice = pick[0] | (pick[1] << 8);
+            if (chosen_out) *chosen_out = c->tune_choice;
+            return bfail(c, DIRAC_E_STATE, "autotune: a persistent candidate's per-lattice barrier timed out; "
+                                           "the tile choice is kept, the bound state is no longer valid (reload it)");
+        }
     }
     c->tune_choice = pick[0] | (pick[1] << 8);
     if (chosen_out) *chosen_out = c->tune_choice;

@@ -15,6 +15,7 @@ struct dirac_ctx {
     double dt = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
     unsigned flags = 0;
     int zh = 0;               // z-slab mode: halo planes per side (arrays hold nz + 2 zh planes)
+    bool zbc = false;         // zero values outside the lattice instead of periodic wrap
     std::string err;
 
     // state: two caller-owned buffer sets; cur says which holds the state

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cayley32.h"
+
 namespace dirac {
 
 template <typename R> struct V2;
@@ -16,6 +18,15 @@ template <typename R> using cx = typename V2<R>::T;
 
 __device__ __forceinline__ double2 mk2(double x, double y) { return make_double2(x, y); }
 __device__ __forceinline__ float2 mk2(float x, float y) { return make_float2(x, y); }
+
+// Load p[idx], or zero when ok is false (a zero value outside the lattice).
+template <typename C> __device__ __forceinline__ C ld_or0(const C *p, size_t idx, bool ok) {
+    if (ok) return p[idx];
+    C z;
+    z.x = 0;
+    z.y = 0;
+    return z;
+}
 
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk2(a.x + b.x, a.y + b.y); }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk2(a.x - b.x, a.y - b.y); }
@@ -101,64 +112,12 @@ template <> __device__ __forceinline__ Coef<double> coef_site_at<double>(const d
     return coef_theta(sgn * th[idx]);
 }
 
-// Adjacent float in direction dir (+1 up, -1 down), for finite x.
-__device__ __forceinline__ float float_step(float x, int dir) {
-    if (x == 0.0f) return dir > 0 ? __int_as_float(1) : -__int_as_float(1);
-    const int b = __float_as_int(x);
-    return __int_as_float(((x > 0.0f) == (dir > 0)) ? b + 1 : b - 1);
-}
-// gamma = 2 i th / (1 + i th) = 1 - alpha rounded to a float pair, chosen
-// among pairs within 1e-6 max(1, |gamma|) of the exact value, to make
-// |1 - gamma|^2 = 1 as closely as FP32 allows.  Candidates: each component in
-// turn as the primary (up to 8 ulps from its exact value), the other derived
-// from the unit modulus on the side of the circle where the exact value lies
-// (alpha_re = (1 - th^2)/(1 + th^2) changes sign at |th| = 1) and tried
-// within 2 ulps.  Ties go to the pair closest to the exact value.  The search
-// is symmetric in the sign of th, so gamma(-th) = conj(gamma(th)).
-__device__ inline float2 gamma32_search(double th) {
-#pragma clang fp contract(off)
-    const double d = 1.0 + th * th;
-    const double gr0 = 2.0 * th * th / d, gi0 = 2.0 * th / d, ar0 = (1.0 - th * th) / d;
-    const double lim = 1e-6 * fmax(1.0, sqrt(gr0 * gr0 + gi0 * gi0));
-    float best_r = (float)gr0, best_i = (float)gi0;
-    double best = 1e300, best_d = 1e300;
-    auto consider = [&](float c, float ci) {
-        const double cd = (double)c, cid = (double)ci;
-        const double dist = fabs(cd - gr0) + fabs(cid - gi0);
-        if (dist > lim) return;
-        const double one_m = 1.0 - cd;
-        const double err = fabs(one_m * one_m + cid * cid - 1.0);
-        if (err < best || (err == best && dist < best_d)) {
-            best = err;
-            best_d = dist;
-            best_r = c;
-            best_i = ci;
-        }
-    };
-    for (int da = -8; da <= 8; ++da) {
-        // gamma_im primary
-        float ci = (float)gi0;
-        for (int q = 0; q < (da < 0 ? -da : da); ++q) ci = float_step(ci, da < 0 ? -1 : 1);
-        const double cid = (double)ci;
-        const double sq = sqrt(fmax(0.0, 1.0 - cid * cid));
-        const float cr = ar0 >= 0.0 ? (float)(cid * cid / (1.0 + sq)) : (float)(1.0 + sq);
-        for (int db = -2; db <= 2; ++db) {
-            float c = cr;
-            for (int q = 0; q < (db < 0 ? -db : db); ++q) c = float_step(c, db < 0 ? -1 : 1);
-            consider(c, ci);
-        }
-        // gamma_re primary
-        float c = (float)gr0;
-        for (int q = 0; q < (da < 0 ? -da : da); ++q) c = float_step(c, da < 0 ? -1 : 1);
-        const double a = 1.0 - (double)c;
-        const float ci0 = (float)copysign(sqrt(fmax(0.0, 1.0 - a * a)), gi0);
-        for (int db = -2; db <= 2; ++db) {
-            float cj = ci0;
-            for (int q = 0; q < (db < 0 ? -db : db); ++q) cj = float_step(cj, db < 0 ? -1 : 1);
-            consider(c, cj);
-        }
-    }
-    return make_float2(best_r, best_i);
+// Unit-modulus rounding of the complex64 record gamma = 1 - alpha (the search
+// itself is shared with the host tables).
+__device__ inline float2 gamma32_record(double th) {
+    float2 g;
+    gamma32_search(th, &g.x, &g.y);
+    return g;
 }
 
 // dX+/dtheta = -i (X+ + X-) beta ; contribution Re[conj(lam) dX+/dtheta] in FP64

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/dirac.h"
+#include "cayley32.h"
 #include "ctx.h"
 #include "gauge.h"
 #include "internal.h"
@@ -56,60 +57,13 @@ void cayley64(double th, double out[4]) {
     out[3] = -(th / d);
 }
 
-// FP32 increment-form coefficients gamma = 2 i th / (1 + i th), beta = 1 / (1 + i th).
-// The rounded pair (gamma_re, gamma_im) is chosen among pairs within
-// 1e-6 max(1, |gamma|) of the exact value to make |1 - gamma|^2 = 1 as closely
-// as FP32 allows (the factor multiplying X- is then unit-modulus to a few
-// 1e-9 typically, so the conserved functional does not drift systematically
-// where theta is constant over space).  Candidates: each component in turn as
-// the primary (up to 8 ulps from exact), the other derived from the unit
-// modulus on the side of the circle where the exact value lies (alpha_re
-// changes sign at |th| = 1) and tried within 2 ulps; ties go to the pair
-// closest to the exact value.  Same rule as the per-site records on the device.
-float step_f(float x, int dir) { return nextafterf(x, dir < 0 ? -INFINITY : INFINITY); }
+// FP32 increment-form coefficients: gamma = 2 i th / (1 + i th) by the
+// unit-modulus rounding shared with the device records (cayley32.h), beta =
+// 1 / (1 + i th) rounded from FP64.
 void cayley32(double th, float out[4]) {
 #pragma clang fp contract(off)
     const double d = 1.0 + th * th;
-    const double gr0 = 2.0 * th * th / d, gi0 = 2.0 * th / d, ar0 = (1.0 - th * th) / d;
-    const double lim = 1e-6 * fmax(1.0, sqrt(gr0 * gr0 + gi0 * gi0));
-    float best_r = (float)gr0, best_i = (float)gi0;
-    double best = 1e300, best_d = 1e300;
-    auto consider = [&](float c, float ci) {
-        const double cd = (double)c, cid = (double)ci;
-        const double dist = fabs(cd - gr0) + fabs(cid - gi0);
-        if (dist > lim) return;
-        const double one_m = 1.0 - cd;
-        const double err = fabs(one_m * one_m + cid * cid - 1.0);
-        if (err < best || (err == best && dist < best_d)) {
-            best = err;
-            best_d = dist;
-            best_r = c;
-            best_i = ci;
-        }
-    };
-    for (int da = -8; da <= 8; ++da) {
-        float ci = (float)gi0;
-        for (int q = 0; q < (da < 0 ? -da : da); ++q) ci = step_f(ci, da);
-        const double cid = (double)ci;
-        const double sq = sqrt(fmax(0.0, 1.0 - cid * cid));
-        const float cr = ar0 >= 0.0 ? (float)(cid * cid / (1.0 + sq)) : (float)(1.0 + sq);
-        for (int db = -2; db <= 2; ++db) {
-            float c = cr;
-            for (int q = 0; q < (db < 0 ? -db : db); ++q) c = step_f(c, db);
-            consider(c, ci);
-        }
-        float c = (float)gr0;
-        for (int q = 0; q < (da < 0 ? -da : da); ++q) c = step_f(c, da);
-        const double a = 1.0 - (double)c;
-        const float ci0 = (float)copysign(sqrt(fmax(0.0, 1.0 - a * a)), gi0);
-        for (int db = -2; db <= 2; ++db) {
-            float cj = ci0;
-            for (int q = 0; q < (db < 0 ? -db : db); ++q) cj = step_f(cj, db);
-            consider(c, cj);
-        }
-    }
-    out[0] = best_r;
-    out[1] = best_i;
+    gamma32_search(th, &out[0], &out[1]);
     out[2] = (float)(1.0 / d);
     out[3] = (float)(-th / d);
 }
@@ -170,8 +124,20 @@ size_t tab_bytes_of(const dirac_ctx *c) {
 }
 
 // scratch layout
+// Per-workgroup partials of the in-step functional (two doubles each): every
+// z-march launch has at most ceil(nx/32) ceil(ny/4) tile columns (its tiles are
+// at least 32 x 4 cells) times at most nz chunks, so the area is sized for that
+// and an in-step reduction is never refused for lack of slots.  The standalone
+// reductions use kReduceBlocks x kObsVals doubles of the same area.
+size_t step_partials(const dirac_ctx *c) {
+    return (size_t)((c->nx + 31) / 32) * (size_t)((c->ny + 3) / 4) * (size_t)c->nz;
+}
+size_t partial_doubles(const dirac_ctx *c) {
+    const size_t red = (size_t)kReduceBlocks * kObsVals, stp = 2 * step_partials(c);
+    return red > stp ? red : stp;
+}
 size_t off_partial(const dirac_ctx *) { return 0; }
-size_t off_result(const dirac_ctx *) { return align256((size_t)kReduceBlocks * kObsVals * sizeof(double)); }
+size_t off_result(const dirac_ctx *c) { return align256(partial_doubles(c) * sizeof(double)); }
 size_t off_tab(const dirac_ctx *c) { return off_result(c) + 256; }
 size_t off_gpart(const dirac_ctx *c) { return off_tab(c) + 2 * align256(tab_bytes_of(c)); }
 size_t scratch_need(const dirac_ctx *c) {
@@ -237,6 +203,7 @@ template <typename R> HalfArgs<R> half_args(dirac_ctx *c, bool reverse) {
     a.nx = (int)c->nx;
     a.ny = (int)c->ny;
     a.nz = (int)c->nz;
+    a.zbc = c->zbc ? 1 : 0;
     return a;
 }
 
@@ -273,6 +240,8 @@ int kernel_choice(const dirac_ctx *c) {
         return DIRAC_KERNEL_FUSED;
     }
     if (c->kernel == DIRAC_KERNEL_SPLIT) return DIRAC_KERNEL_SPLIT;
+    // zero values outside the lattice: the split kernels (in place)
+    if (c->zbc) return DIRAC_KERNEL_SPLIT;
     // links: the link marches (one step per launch)
     if (c->links_on) return DIRAC_KERNEL_FUSED;
     if (plane_bytes >= (1ull << 32)) return DIRAC_KERNEL_SPLIT;
@@ -304,9 +273,52 @@ LinkPtrs link_ptrs(const dirac_ctx *c) {
     return L;
 }
 
+// The forward march kernels run the reversed sequence: with r -> -r, the
+// reversed coefficient tables (theta -> -theta) and per-site records read with
+// theta -> -theta they apply H1' then H2', the two half-steps solved backwards
+// (H1' undoes ss1, ss2; H2' undoes ss3, ss4).  n reversed steps are
+// (H1' H2')^n = H1' (H2' H1')^(n-1) H2': one split H2', n - 1 march steps, one
+// split H1'.
+template <typename R> FusedArgs<R> fused_args_rev(dirac_ctx *c) {
+    FusedArgs<R> a = fused_args<R>(c);
+    a.rx = -a.rx;
+    a.ry = -a.ry;
+    a.rz = -a.rz;
+    if (!c->site_mode) a.tab = (const R *)scratch_at(c, off_tab(c) + align256(tab_bytes<R>(c)));
+    a.rev = 1;
+    return a;
+}
+
+// 3D lattices whose forward steps take a march kernel reverse on it too
+bool reverse_on_march(const dirac_ctx *c) {
+    if (c->ndim != 3 || c->links_on || c->zh) return false;
+    const int kc = kernel_choice(c);
+    return kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2;
+}
+
+template <typename R> int run_reverse_march(dirac_ctx *c, int64_t n, hipStream_t s) {
+    if (n <= 0) return DIRAC_OK;
+    const bool site = c->site_mode;
+    HIPCHK(c, launch_half3<R>(half_args<R>(c, true), 1, site, s));      // H2'
+    int64_t t = 1;
+    if (kernel_choice(c) == DIRAC_KERNEL_FUSED2) {
+        for (; t + 2 <= n; t += 2) {
+            HIPCHK(c, launch_fused3x2<R>(fused_args_rev<R>(c), site, s));
+            c->cur = 1 - c->cur;
+        }
+    }
+    for (; t < n; ++t) {
+        HIPCHK(c, launch_fused3<R>(fused_args_rev<R>(c), site, c->tile_y, s));
+        c->cur = 1 - c->cur;
+    }
+    HIPCHK(c, launch_half3<R>(half_args<R>(c, true), 0, site, s));      // H1'
+    return DIRAC_OK;
+}
+
 template <typename R> int run_steps(dirac_ctx *c, int64_t n, bool reverse, hipStream_t s) {
     int rc = upload_tables(c, s);
     if (rc) return rc;
+    if (reverse && reverse_on_march(c)) return run_reverse_march<R>(c, n, s);
     const bool site = c->site_mode;
     const int kc = reverse ? DIRAC_KERNEL_SPLIT : kernel_choice(c);
     const bool fused = kc == DIRAC_KERNEL_FUSED || kc == DIRAC_KERNEL_FUSED2;
@@ -363,6 +375,7 @@ template <typename R> ReduceArgs<R> reduce_args(dirac_ctx *c, double z0) {
     a.z0 = z0;
     a.partial = (double *)scratch_at(c, off_partial(c));
     a.zh = c->zh;
+    a.zbc = c->zbc ? 1 : 0;
     return a;
 }
 
@@ -400,8 +413,9 @@ int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, 
     *out = nullptr;
     if (ndim != 2 && ndim != 3) return DIRAC_E_ARG;
     if (dtype != DIRAC_C64 && dtype != DIRAC_C128) return DIRAC_E_ARG;
-    if ((flags & ~(DIRAC_ALLOW_UNSTABLE | DIRAC_SLAB_Z)) != 0) return DIRAC_E_ARG;
+    if ((flags & ~(DIRAC_ALLOW_UNSTABLE | DIRAC_SLAB_Z | DIRAC_ZERO_BC)) != 0) return DIRAC_E_ARG;
     if ((flags & DIRAC_SLAB_Z) && ndim != 3) return DIRAC_E_ARG;
+    if ((flags & DIRAC_SLAB_Z) && (flags & DIRAC_ZERO_BC)) return DIRAC_E_ARG;
     if (nx < 1 || ny < 1 || nz < 1) return DIRAC_E_SHAPE;
     if (ndim == 2 && nz != 1) return DIRAC_E_SHAPE;
     if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return DIRAC_E_SHAPE;
@@ -423,6 +437,7 @@ int dirac_create(dirac_ctx **out, int ndim, int64_t nx, int64_t ny, int64_t nz, 
     c->rz = rz;
     c->flags = flags;
     c->zh = (flags & DIRAC_SLAB_Z) ? 2 : 0;
+    c->zbc = (flags & DIRAC_ZERO_BC) != 0;
     *out = c;
     return DIRAC_OK;
 }
@@ -563,6 +578,7 @@ int dirac_set_links(dirac_ctx *c, void *const links[]) {
     if (!c) return DIRAC_E_ARG;
     if (c->is_batch) return fail(c, DIRAC_E_STATE, "batch context");
     if (c->zh && links) return fail(c, DIRAC_E_STATE, "links are not available in z-slab mode");
+    if (c->zbc && links) return fail(c, DIRAC_E_STATE, "links are not available with DIRAC_ZERO_BC");
     for (int q = 0; q < 24; ++q) c->links[q] = nullptr;
     c->links_on = false;
     if (!links) return DIRAC_OK;
@@ -571,6 +587,15 @@ int dirac_set_links(dirac_ctx *c, void *const links[]) {
         if (!links[q]) return fail(c, DIRAC_E_ARG, "null link array %d", q);
     for (int q = 0; q < nl; ++q) c->links[q] = links[q];
     c->links_on = true;
+    return DIRAC_OK;
+}
+
+int dirac_coef_from_theta_host(float *coef, const double *theta, int64_t n) {
+    if (!coef || !theta || n < 0) return DIRAC_E_ARG;
+    for (int64_t t = 0; t < n; ++t) {
+        if (!isfinite(theta[t])) return DIRAC_E_NONFINITE;
+        gamma32_search(theta[t], &coef[2 * t], &coef[2 * t + 1]);
+    }
     return DIRAC_OK;
 }
 
@@ -656,7 +681,8 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     double *part = (double *)scratch_at(c, off_partial(c));
-    const int cap = (kReduceBlocks * kObsVals) / 2;
+    const size_t cap_sz = partial_doubles(c) / 2;
+    const int cap = cap_sz > 0x7fffffff ? 0x7fffffff : (int)cap_sz;
     const int kc = kernel_choice(c);
     if (c->ndim == 3 && kc == DIRAC_KERNEL_FUSED2 && n >= 2 && !c->links_on) {
         rc = dirac_step(c, n - 2, stream);
@@ -681,9 +707,20 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
             HIPCHK(c, launch_final_sum(part, nb, 2, (double *)dev_out, s));
             return DIRAC_OK;
         }
-        if (nb <= cap) HIPCHK(c, e);   // a real launch failure; otherwise fall through
-        rc = dirac_step(c, 1, stream);
+        if (nb <= cap) HIPCHK(c, e);   // a real launch failure
+        // more workgroups than partial slots (the area is sized so that this
+        // does not happen).  A z-slab's halos are stale after a launch, so a
+        // reduction after the step would be wrong there: refuse.  Otherwise the
+        // same two steps without the in-step sum, then the reduction.
+        if (c->zh) return fail(c, DIRAC_E_SHAPE, "z-slab mode: %d workgroups exceed the %d partial slots", nb, cap);
+        if (c->dtype == DIRAC_C64) HIPCHK(c, launch_fused3x2<float>(fused_args<float>(c), c->site_mode, s));
+        else HIPCHK(c, launch_fused3x2<double>(fused_args<double>(c), c->site_mode, s));
+        c->cur = 1 - c->cur;
+        double *res = (double *)scratch_at(c, off_result(c));
+        rc = dirac_norm_device(c, res, stream);
         if (rc) return rc;
+        HIPCHK(c, hipMemcpyAsync(dev_out, res + 1, 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return DIRAC_OK;
     } else {
         rc = dirac_step(c, n - 1, stream);
         if (rc) return rc;
@@ -707,7 +744,8 @@ int dirac_step_norm(dirac_ctx *c, int64_t n, void *dev_out, void *stream) {
             HIPCHK(c, launch_final_sum(part, nb, 2, (double *)dev_out, s));
             return DIRAC_OK;
         }
-        if (nb <= cap) HIPCHK(c, e);   // a real launch failure; otherwise fall through
+        if (nb <= cap) HIPCHK(c, e);   // a real launch failure
+        if (c->zh) return fail(c, DIRAC_E_SHAPE, "z-slab mode: %d workgroups exceed the %d partial slots", nb, cap);
     }
     rc = dirac_step(c, 1, stream);
     if (rc) return rc;
@@ -815,6 +853,7 @@ int dirac_adjoint_vz(dirac_ctx *c, int64_t n, void *const lam[], void *dLdV_int,
     if (!c->w_int.empty())
         return fail(c, DIRAC_E_STATE, "the reversal-based adjoint needs a real potential (no absorbing layers)");
     if (c->links_on) return fail(c, DIRAC_E_STATE, "the V(z) gradient kernels carry no gauge links");
+    if (c->zbc) return fail(c, DIRAC_E_STATE, "the V(z) gradient kernels are periodic (no DIRAC_ZERO_BC)");
     if (n < 0 || !lam || !dLdV_int || !dLdV_half) return fail(c, DIRAC_E_ARG, "bad arguments");
     for (int q = 0; q < 8; ++q)
         if (!lam[q]) return fail(c, DIRAC_E_ARG, "null lam array %d", q);

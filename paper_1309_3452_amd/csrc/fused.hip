@@ -45,10 +45,12 @@ template <typename R> __device__ __forceinline__ int zplane(const FusedArgs<R> &
     return a.zh ? pl + a.zh : wrapn(pl, a.nz);
 }
 
-template <typename R, bool SITE>
+// SITE: 0 = V(z) tables, 1 = per-site records, 2 = per-site records with
+// theta -> -theta (the reversed step's sequence).
+template <typename R, int SITE>
 __device__ __forceinline__ Coef<R> fcoef(const FusedArgs<R> &a, int arr, int cls, int pk, size_t idx) {
-    if constexpr (SITE) {
-        return coef_site_at<R>(a.th[arr], idx, (R)1);
+    if constexpr (SITE != 0) {
+        return coef_site_at<R>(a.th[arr], idx, SITE == 2 ? (R)-1 : (R)1);
     } else {
         const R *e = a.tab + ((size_t)cls * (a.nz + 2 * a.zh) + pk) * 4;
         Coef<R> k;
@@ -173,7 +175,7 @@ template <int LB> __device__ __forceinline__ void g2lds(const void *gsrc, void *
 // state in its C,D-summed form E_r = sum |X|^2 + Re sum_{C,D} conj(Y) S_Y(A,B)
 // (Lemma of Sect. 2 after summation by parts; S_Y(A,B) is exactly the stencil
 // the C,D update evaluates) and the plain norm, into a.npart.
-template <typename R, bool SITE, int TY, int CPT, bool NORM>
+template <typename R, int SITE, int TY, int CPT, bool NORM>
 __global__ __launch_bounds__(kTX *TY, sizeof(R) * CPT == 4 ? 3 : 2) void k3_fused(FusedArgs<R> a) {
     using C = cx<R>;
     using V = Cells<C, CPT>;
@@ -531,15 +533,17 @@ hipError_t launch_fused3(const FusedArgs<R> &a0, bool site, int tile_y, hipStrea
     const bool norm = a.npart != nullptr;
     if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;   // caller falls back
     dim3 g((unsigned)nblk), b(kTX * TY);
-#define L3(T, P)                                                                          \
-    if (TY == T && CPT == P) {                                                            \
-        if (norm) {                                                                       \
-            if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P, true>), g, b, 0, s, a);  \
-            else hipLaunchKernelGGL((k3_fused<R, false, T, P, true>), g, b, 0, s, a);      \
-        } else {                                                                          \
-            if (site) hipLaunchKernelGGL((k3_fused<R, true, T, P, false>), g, b, 0, s, a); \
-            else hipLaunchKernelGGL((k3_fused<R, false, T, P, false>), g, b, 0, s, a);     \
-        }                                                                                 \
+    if (norm && site && a.rev) return hipErrorInvalidValue;     // no functional on reversed steps
+#define L3(T, P)                                                                              \
+    if (TY == T && CPT == P) {                                                                \
+        if (norm) {                                                                           \
+            if (site) hipLaunchKernelGGL((k3_fused<R, 1, T, P, true>), g, b, 0, s, a);         \
+            else hipLaunchKernelGGL((k3_fused<R, 0, T, P, true>), g, b, 0, s, a);              \
+        } else {                                                                              \
+            if (site && a.rev) hipLaunchKernelGGL((k3_fused<R, 2, T, P, false>), g, b, 0, s, a); \
+            else if (site) hipLaunchKernelGGL((k3_fused<R, 1, T, P, false>), g, b, 0, s, a);  \
+            else hipLaunchKernelGGL((k3_fused<R, 0, T, P, false>), g, b, 0, s, a);             \
+        }                                                                                     \
     }
     L3(4, 1) L3(8, 1)
     if constexpr (sizeof(R) == 4) {

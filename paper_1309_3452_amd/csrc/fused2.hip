@@ -143,17 +143,23 @@ template <> struct SiteRec<float> {
     static __device__ __forceinline__ T load(const float *th, size_t pb, uint32_t boff) {
         return *(const float2 *)((const char *)th + pb + boff);
     }
-    static __device__ __forceinline__ Coef<float> coef(T g) { return coef_site(g, 1.0f); }
+    template <int SITE> static __device__ __forceinline__ Coef<float> coef(T g) {
+        return coef_site(g, SITE == 2 ? -1.0f : 1.0f);
+    }
 };
 template <> struct SiteRec<double> {
     typedef double T;
     static __device__ __forceinline__ T load(const double *th, size_t pb, uint32_t boff) {
         return *(const double *)((const char *)th + pb + boff);
     }
-    static __device__ __forceinline__ Coef<double> coef(T th) { return coef_theta(th); }
+    template <int SITE> static __device__ __forceinline__ Coef<double> coef(T th) {
+        return coef_theta(SITE == 2 ? -th : th);
+    }
 };
 
-template <typename R, int TW, int TY, int NT, bool NORM, bool SITE>
+// SITE: 0 = V(z) tables, 1 = per-site records, 2 = per-site records with
+// theta -> -theta (the reversed step's sequence).
+template <typename R, int TW, int TY, int NT, bool NORM, int SITE>
 __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int W = TW + 4, H = TY + 4, RN = W * H;
@@ -315,11 +321,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         // level 1: A,B of plane p after step 1
         if (in1) {
             Coef<R> kq[4];
-            if constexpr (SITE) {
+            if constexpr (SITE != 0) {
                 Rec rr[4];
                 ld_rec(0, k0, rr);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::template coef<SITE>(rr[q]);
             } else {
                 kq[0] = kq[1] = tcoef(tab, tstride, 0, tk(k0));
                 kq[2] = kq[3] = tcoef(tab, tstride, 1, tk(k0));
@@ -356,11 +362,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         }
         if (in2 && q2 >= z0 - 2 && q2 <= z1 + 1) {
             Coef<R> kq[4];
-            if constexpr (SITE) {
+            if constexpr (SITE != 0) {
                 Rec rr[4];
                 ld_rec(4, km1, rr);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::template coef<SITE>(rr[q]);
             } else {
                 kq[0] = kq[1] = tcoef(tab, tstride, 2, tk(km1));
                 kq[2] = kq[3] = tcoef(tab, tstride, 3, tk(km1));
@@ -386,11 +392,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         }
         if (in2 && q3 >= z0 - 1 && q3 <= z1) {
             Coef<R> kq[4];
-            if constexpr (SITE) {
+            if constexpr (SITE != 0) {
                 Rec rr[4];
                 ld_rec(0, km2, rr);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::template coef<SITE>(rr[q]);
             } else {
                 kq[0] = kq[1] = tcoef(tab, tstride, 0, tk(km2));
                 kq[2] = kq[3] = tcoef(tab, tstride, 1, tk(km2));
@@ -429,11 +435,11 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         }
         if (in4 && q4 >= z0 && q4 < z1) {
             Coef<R> kq[4];
-            if constexpr (SITE) {
+            if constexpr (SITE != 0) {
                 Rec rr[4];
                 ld_rec(4, km3, rr);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::coef(rr[q]);
+                for (int q = 0; q < 4; ++q) kq[q] = SiteRec<R>::template coef<SITE>(rr[q]);
             } else {
                 kq[0] = kq[1] = tcoef(tab, tstride, 2, tk(km3));
                 kq[2] = kq[3] = tcoef(tab, tstride, 3, tk(km3));
@@ -622,13 +628,15 @@ hipError_t launch_fused3x2(const FusedArgs<R> &a0, bool site, hipStream_t s, int
     if (nblocks_out) *nblocks_out = (int)nblk;
     const bool norm = a.npart != nullptr;
     if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;
+    if (norm && site && a.rev) return hipErrorInvalidValue;     // no functional on reversed steps
     const dim3 g((unsigned)nblk), b(NT);
     if (site) {
-        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, true>), g, b, 0, s, a, a.tab);
-        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, true>), g, b, 0, s, a, a.tab);
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 1>), g, b, 0, s, a, a.tab);
+        else if (a.rev) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 2>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 1>), g, b, 0, s, a, a.tab);
     } else {
-        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, false>), g, b, 0, s, a, a.tab);
-        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, false>), g, b, 0, s, a, a.tab);
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 0>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 0>), g, b, 0, s, a, a.tab);
     }
     return hipGetLastError();
 }

@@ -20,6 +20,7 @@ template <typename R> struct HalfArgs {
     R rx, ry, rz;         // signed: negated for the reversed step
     R tsgn;               // +1 forward, -1 reversed (site mode)
     int nx, ny, nz;
+    int zbc;              // 1: zero values outside the lattice; 0: periodic
 };
 
 // Fused one-step launch (3D z-march / 2D y-march), ping-pong in -> out.
@@ -39,6 +40,8 @@ template <typename R> struct FusedArgs {
                           // interior planes zh .. zh + nz - 1, no wrap in z); 0 = periodic
     int px;               // two-step 3D kernel: tiles across one XCD's concurrent patch
                           // (0 = whole tile rows); set by its launcher
+    int rev;              // 3D: per-site records taken with theta -> -theta (steps of the
+                          // reversed sequence; r and the table pointer are set by the caller)
 };
 
 // Reduction launch over a single lattice.
@@ -49,6 +52,7 @@ template <typename R> struct ReduceArgs {
     double z0;
     double *partial;      // [nblocks][nv]
     int zh;               // z-slab mode (as in FusedArgs); 0 = periodic
+    int zbc;              // 1: zero values outside the lattice (x, y, z); 0: periodic
 };
 
 // Gauge-link arrays (vector potential, Sect. 4): u[6 a + t] (3D) or u[4 a + t]

@@ -40,12 +40,17 @@ __global__ __launch_bounds__(256) void k2_half(HalfArgs<R> a) {
     C *f[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) f[q] = (C *)a.f[q];
+    // zero values outside the lattice: a neighbour across an edge reads as zero
+    const bool zb = a.zbc != 0;
+    const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
     if constexpr (WHICH == 0) {
-        St2<C> s = stencil_u<C, R>(a.rx, a.ry, f[2][c], f[2][xm], f[2][yp], f[3][c], f[3][ym], f[3][xp]);
+        St2<C> s = stencil_u<C, R>(a.rx, a.ry, f[2][c], ld_or0(f[2], xm, oxm), ld_or0(f[2], yp, oyp), f[3][c],
+                                   ld_or0(f[3], ym, oym), ld_or0(f[3], xp, oxp));
         f[0][c] = update(f[0][c], s.s0, coef2<R, SITE>(a, 0, 0, c));
         f[1][c] = update(f[1][c], s.s1, coef2<R, SITE>(a, 1, 0, c));
     } else {
-        St2<C> s = stencil_v<C, R>(a.rx, a.ry, f[0][c], f[0][xp], f[0][yp], f[1][c], f[1][ym], f[1][xm]);
+        St2<C> s = stencil_v<C, R>(a.rx, a.ry, f[0][c], ld_or0(f[0], xp, oxp), ld_or0(f[0], yp, oyp), f[1][c],
+                                   ld_or0(f[1], ym, oym), ld_or0(f[1], xm, oxm));
         f[2][c] = update(f[2][c], s.s0, coef2<R, SITE>(a, 2, 3, c));
         f[3][c] = update(f[3][c], s.s1, coef2<R, SITE>(a, 3, 3, c));
     }
@@ -76,10 +81,14 @@ __global__ __launch_bounds__(kReduceThreads) void k2_norm(ReduceArgs<R> a) {
         double2 x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = to_d(f[q][c]);
-        St2<double2> su = stencil_u<double2, double>(rx, ry, x[2], to_d(f[2][xm]), to_d(f[2][yp]), x[3],
-                                                      to_d(f[3][ym]), to_d(f[3][xp]));
-        St2<double2> sv = stencil_v<double2, double>(rx, ry, x[0], to_d(f[0][xp]), to_d(f[0][yp]), x[1],
-                                                      to_d(f[1][ym]), to_d(f[1][xm]));
+        const bool zb = a.zbc != 0;
+        const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
+        St2<double2> su = stencil_u<double2, double>(rx, ry, x[2], to_d(ld_or0(f[2], xm, oxm)),
+                                                      to_d(ld_or0(f[2], yp, oyp)), x[3], to_d(ld_or0(f[3], ym, oym)),
+                                                      to_d(ld_or0(f[3], xp, oxp)));
+        St2<double2> sv = stencil_v<double2, double>(rx, ry, x[0], to_d(ld_or0(f[0], xp, oxp)),
+                                                      to_d(ld_or0(f[0], yp, oyp)), x[1], to_d(ld_or0(f[1], ym, oym)),
+                                                      to_d(ld_or0(f[1], xm, oxm)));
         v[0] -= re_conj_mul(x[0], su.s0) + re_conj_mul(x[1], su.s1);
         v[1] += re_conj_mul(x[2], sv.s0) + re_conj_mul(x[3], sv.s1);
         const double p = abs2(x[0]) + abs2(x[1]) + abs2(x[2]) + abs2(x[3]);

@@ -66,22 +66,26 @@ __global__ __launch_bounds__(256) void k3_half(HalfArgs<R> a) {
     C *f[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) f[q] = (C *)a.f[q];
+    // zero values outside the lattice: a neighbour across a face reads as zero
+    const bool zb = a.zbc != 0;
+    const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
+    const bool ozm = !zb || k > 0, ozp = !zb || k < a.nz - 1;
     if constexpr (WHICH == 0) {
         St3<C> s = stencil_ab<C, R>(a.rx, a.ry, a.rz,
-                                     f[4][c], f[4][zm], f[4][xp], f[4][yp],
-                                     f[5][c], f[5][zm], f[5][ym], f[5][xm],
-                                     f[6][c], f[6][xm], f[6][yp], f[6][zp],
-                                     f[7][c], f[7][ym], f[7][xp], f[7][zp]);
+                                     f[4][c], ld_or0(f[4], zm, ozm), ld_or0(f[4], xp, oxp), ld_or0(f[4], yp, oyp),
+                                     f[5][c], ld_or0(f[5], zm, ozm), ld_or0(f[5], ym, oym), ld_or0(f[5], xm, oxm),
+                                     f[6][c], ld_or0(f[6], xm, oxm), ld_or0(f[6], yp, oyp), ld_or0(f[6], zp, ozp),
+                                     f[7][c], ld_or0(f[7], ym, oym), ld_or0(f[7], xp, oxp), ld_or0(f[7], zp, ozp));
         f[0][c] = update(f[0][c], s.s0, coef_at<R, SITE>(a, 0, 0, k, c));
         f[1][c] = update(f[1][c], s.s1, coef_at<R, SITE>(a, 1, 0, k, c));
         f[2][c] = update(f[2][c], s.s2, coef_at<R, SITE>(a, 2, 1, k, c));
         f[3][c] = update(f[3][c], s.s3, coef_at<R, SITE>(a, 3, 1, k, c));
     } else {
         St3<C> s = stencil_cd<C, R>(a.rx, a.ry, a.rz,
-                                     f[0][c], f[0][zp], f[0][xp], f[0][yp],
-                                     f[1][c], f[1][zp], f[1][xm], f[1][ym],
-                                     f[2][c], f[2][zm], f[2][xm], f[2][yp],
-                                     f[3][c], f[3][zm], f[3][xp], f[3][ym]);
+                                     f[0][c], ld_or0(f[0], zp, ozp), ld_or0(f[0], xp, oxp), ld_or0(f[0], yp, oyp),
+                                     f[1][c], ld_or0(f[1], zp, ozp), ld_or0(f[1], xm, oxm), ld_or0(f[1], ym, oym),
+                                     f[2][c], ld_or0(f[2], zm, ozm), ld_or0(f[2], xm, oxm), ld_or0(f[2], yp, oyp),
+                                     f[3][c], ld_or0(f[3], zm, ozm), ld_or0(f[3], xp, oxp), ld_or0(f[3], ym, oym));
         f[4][c] = update(f[4][c], s.s0, coef_at<R, SITE>(a, 4, 2, k, c));
         f[5][c] = update(f[5][c], s.s1, coef_at<R, SITE>(a, 5, 2, k, c));
         f[6][c] = update(f[6][c], s.s2, coef_at<R, SITE>(a, 6, 3, k, c));
@@ -155,27 +159,32 @@ __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
         const uint32_t ym = (uint32_t)wrap_dec(j, a.ny) * a.nx + i, yp = (uint32_t)wrap_inc(j, a.ny) * a.nx + i;
         // storage planes: periodic wrap, or in z-slab mode the interior offset by the halo
         auto zpl = [&](int pl) { return a.zh ? pl + a.zh : (pl < 0 ? pl + a.nz : pl >= a.nz ? pl - a.nz : pl); };
+        // zero values outside the lattice: neighbours across a face read as zero
+        const bool zb = a.zbc != 0;
+        const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
         const size_t Pb = (size_t)zpl(z0 - 1) * plane, P0 = (size_t)zpl(z0) * plane;
-        double2 cm0 = to_d(f[4][Pb + c]), cm1 = to_d(f[5][Pb + c]);      // C(k-1)
-        double2 bm0 = to_d(f[2][Pb + c]), bm1 = to_d(f[3][Pb + c]);      // B(k-1)
+        const bool ob = !zb || z0 > 0;
+        double2 cm0 = to_d(ld_or0(f[4], Pb + c, ob)), cm1 = to_d(ld_or0(f[5], Pb + c, ob));      // C(k-1)
+        double2 bm0 = to_d(ld_or0(f[2], Pb + c, ob)), bm1 = to_d(ld_or0(f[3], Pb + c, ob));      // B(k-1)
         double2 a0 = to_d(f[0][P0 + c]), a1 = to_d(f[1][P0 + c]), d0 = to_d(f[6][P0 + c]), d1 = to_d(f[7][P0 + c]);
         for (int k = z0; k < z1; ++k) {
             const size_t Pk = (size_t)zpl(k) * plane;
             const size_t Pn = (size_t)zpl(k + 1) * plane;
-            const double2 an0 = to_d(f[0][Pn + c]), an1 = to_d(f[1][Pn + c]);
-            const double2 dn0 = to_d(f[6][Pn + c]), dn1 = to_d(f[7][Pn + c]);
+            const bool on = !zb || k + 1 < a.nz;
+            const double2 an0 = to_d(ld_or0(f[0], Pn + c, on)), an1 = to_d(ld_or0(f[1], Pn + c, on));
+            const double2 dn0 = to_d(ld_or0(f[6], Pn + c, on)), dn1 = to_d(ld_or0(f[7], Pn + c, on));
             const double2 b0 = to_d(f[2][Pk + c]), b1 = to_d(f[3][Pk + c]);
             const double2 c0 = to_d(f[4][Pk + c]), c1 = to_d(f[5][Pk + c]);
             St3<double2> sab = stencil_ab<double2, double>(rx, ry, rz,
-                c0, cm0, to_d(f[4][Pk + xp]), to_d(f[4][Pk + yp]),
-                c1, cm1, to_d(f[5][Pk + ym]), to_d(f[5][Pk + xm]),
-                d0, to_d(f[6][Pk + xm]), to_d(f[6][Pk + yp]), dn0,
-                d1, to_d(f[7][Pk + ym]), to_d(f[7][Pk + xp]), dn1);
+                c0, cm0, to_d(ld_or0(f[4], Pk + xp, oxp)), to_d(ld_or0(f[4], Pk + yp, oyp)),
+                c1, cm1, to_d(ld_or0(f[5], Pk + ym, oym)), to_d(ld_or0(f[5], Pk + xm, oxm)),
+                d0, to_d(ld_or0(f[6], Pk + xm, oxm)), to_d(ld_or0(f[6], Pk + yp, oyp)), dn0,
+                d1, to_d(ld_or0(f[7], Pk + ym, oym)), to_d(ld_or0(f[7], Pk + xp, oxp)), dn1);
             St3<double2> scd = stencil_cd<double2, double>(rx, ry, rz,
-                a0, an0, to_d(f[0][Pk + xp]), to_d(f[0][Pk + yp]),
-                a1, an1, to_d(f[1][Pk + xm]), to_d(f[1][Pk + ym]),
-                b0, bm0, to_d(f[2][Pk + xm]), to_d(f[2][Pk + yp]),
-                b1, bm1, to_d(f[3][Pk + xp]), to_d(f[3][Pk + ym]));
+                a0, an0, to_d(ld_or0(f[0], Pk + xp, oxp)), to_d(ld_or0(f[0], Pk + yp, oyp)),
+                a1, an1, to_d(ld_or0(f[1], Pk + xm, oxm)), to_d(ld_or0(f[1], Pk + ym, oym)),
+                b0, bm0, to_d(ld_or0(f[2], Pk + xm, oxm)), to_d(ld_or0(f[2], Pk + yp, oyp)),
+                b1, bm1, to_d(ld_or0(f[3], Pk + xp, oxp)), to_d(ld_or0(f[3], Pk + ym, oym)));
             const double p = abs2(a0) + abs2(a1) + abs2(b0) + abs2(b1) + abs2(c0) + abs2(c1) + abs2(d0) + abs2(d1);
             v[0] += p - (re_conj_mul(a0, sab.s0) + re_conj_mul(a1, sab.s1) + re_conj_mul(b0, sab.s2) +
                          re_conj_mul(b1, sab.s3));
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(256) void k3_seed(ReduceArgs<R> a, CPtr8 lam) {
 // as theta (complex128 lattices) or as the rounded gamma pair (complex64).
 __device__ __forceinline__ void put_site_coef(double *th, int64_t t, double theta) { th[t] = theta; }
 __device__ __forceinline__ void put_site_coef(float *th, int64_t t, double theta) {
-    ((float2 *)th)[t] = gamma32_search(theta);
+    ((float2 *)th)[t] = gamma32_record(theta);
 }
 
 template <typename R>
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(256) void k_theta_fields(CPtr8 th, CPtr8 v, int nar
 // rounded once from FP64; real theta keeps the unit-modulus search.
 __device__ inline float2 gamma32_complex(double th, double thi) {
 #pragma clang fp contract(off)
-    if (thi == 0.0) return gamma32_search(th);
+    if (thi == 0.0) return gamma32_record(th);
     const double den = (1.0 - thi) * (1.0 - thi) + th * th;
     const double ar = (1.0 - thi * thi - th * th) / den, ai = -((2.0 * th) / den);
     return make_float2((float)(1.0 - ar), (float)(-ai));

@@ -36,10 +36,12 @@ class Lattice:
     slab: (3D) a z-slab of a larger lattice (DIRAC_SLAB_Z): nz interior planes,
     arrays of nz + 4 planes with two halo planes on each side that the caller
     fills before every step (see SlabDecomposition).
+    zero_bc: zero values outside the lattice instead of periodic wrap
+    (DIRAC_ZERO_BC).
     """
 
     def __init__(self, shape: Sequence[int], dtype=torch.complex128, dt: float = 0.5, d=None,
-                 allow_unstable: bool = False, device="cuda", slab: bool = False):
+                 allow_unstable: bool = False, device="cuda", slab: bool = False, zero_bc: bool = False):
         if len(shape) not in (2, 3):
             raise ValueError("shape must have 2 or 3 entries")
         self.ndim = len(shape)
@@ -58,7 +60,9 @@ class Lattice:
         self.tshape = (self.nplanes, self.ny, self.nx) if self.ndim == 3 else (self.ny, self.nx)
         ctx = ctypes.c_void_p()
         dz = d[2] if self.ndim == 3 else 1.0
-        flags = (_abi.DIRAC_ALLOW_UNSTABLE if allow_unstable else 0) | (_abi.DIRAC_SLAB_Z if slab else 0)
+        flags = ((_abi.DIRAC_ALLOW_UNSTABLE if allow_unstable else 0) | (_abi.DIRAC_SLAB_Z if slab else 0)
+                 | (_abi.DIRAC_ZERO_BC if zero_bc else 0))
+        self.zero_bc = bool(zero_bc)
         check(lib().dirac_create(ctypes.byref(ctx), self.ndim, self.nx, self.ny, self.nz, _dtype_code(dtype),
                                  self.dt, float(d[0]), float(d[1]), float(dz), flags))
         self._ctx = ctx

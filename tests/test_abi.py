@@ -190,3 +190,22 @@ def test_split_setters_and_wrappers_validate(L):
     lam = ptr_array([256] * 8)
     assert L.dirac_adjoint(c, 2, lam, 0.0, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -6   # no state
     L.dirac_destroy(c)
+
+
+def test_zero_bc_flag_validation(L):
+    """DIRAC_ZERO_BC: 2D and 3D; not with z-slab mode; links and the V(z)
+    gradient are refused before any HIP call."""
+    from paper_1309_3452_amd._abi import DIRAC_SLAB_Z, DIRAC_ZERO_BC, ptr_array
+    assert _create(L, flags=DIRAC_ZERO_BC)[0] == 0
+    assert _create(L, ndim=2, n=(8, 8, 1), flags=DIRAC_ZERO_BC)[0] == 0
+    assert _create(L, flags=DIRAC_ZERO_BC | DIRAC_SLAB_Z)[0] == -1
+    rc, c = _create(L, flags=DIRAC_ZERO_BC)
+    assert L.dirac_set_links(c, ptr_array([256] * 24)) == -6
+    assert b"DIRAC_ZERO_BC" in L.dirac_last_error(c)
+    fake = ptr_array([256] * 8)
+    assert L.dirac_bind_state(c, fake, fake) == 0
+    nb = ctypes.c_size_t()
+    assert L.dirac_scratch_bytes(c, ctypes.byref(nb)) == 0
+    assert L.dirac_bind_scratch(c, ctypes.c_void_p(256), nb.value) == 0
+    assert L.dirac_adjoint_vz(c, 1, fake, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -6
+    L.dirac_destroy(c)

@@ -178,6 +178,42 @@ def test_full_oracle_parity_128_fp64_1000_steps(P):
     assert abs(e[0] - eo[0]) <= 1e-13 * eo[2] and abs(e[0] - e0[0]) <= 1e-13 * abs(e0[0])
 
 
+@pytest.mark.timeout(1200)
+def test_full_oracle_parity_256_fp64_1000_steps(P, capfd):
+    """The 256^3 complex128 Klein-step workload exactly as stated: 1000 steps in the
+    benchmark's launch sequence (two-step launches, the in-step functional every
+    tenth step) against the oracle on every cell, with E_r of both.  The oracle
+    takes several minutes on the host cores; it prints its progress."""
+    n, steps, chunk = 256, 1000, 100
+    cfg = workloads.config_step3d(n, dtype=torch.complex128, device="cpu")
+    print("full parity 256^3, %d steps" % steps, flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex128, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    e0 = lat.norm()
+    for _ in range(steps // 10):
+        e = lat.step_norm(10)
+    e = e.cpu().numpy()
+    got = [t.cpu().numpy() for t in lat.state()]
+    del lat
+    free()
+    ol = oracle.Lattice3(n, n, n, cfg["dt"])
+    f = [np.ascontiguousarray(t.numpy()) for t in cfg["state"]]
+    del cfg["state"]
+    th = ol.theta_vz(cfg["m"], cfg["v_int"], cfg["v_half"])
+    import time
+    t0 = time.perf_counter()
+    for done in range(chunk, steps + 1, chunk):
+        ol.step(f, th, chunk)
+        with capfd.disabled():
+            print("  oracle 256^3: %d/%d steps, %.0f s" % (done, steps, time.perf_counter() - t0), flush=True)
+    rel = rel_l2(got, f)
+    eo = ol.energy(f)
+    print("256^3 x %d: rel L2 %.3e; E_r gpu %.15e oracle %.15e start %.15e" % (steps, rel, e[0], eo[0], e0[0]))
+    assert rel <= 1e-13
+    assert abs(e[0] - eo[0]) <= 1e-13 * eo[2] and abs(e[0] - e0[0]) <= 1e-13 * abs(e0[0])
+
+
 def test_sampled_oracle_parity_256_fp64(P):
     """Klein-step workload at 256^3 (fused kernel, bench launch configuration): after
     3 steps, sampled cells against the oracle run on a periodic sub-box of half-width
@@ -275,6 +311,63 @@ def test_sampled_oracle_parity_512_fp32_headline(P):
             assert abs(box[a][R, R, R] - got[a]) <= steps * 1e-6 * scale, (i, j, k, a)
             big += abs(got[a]) > 1e-2 * scale
     assert big >= 40       # the packet samples carry the comparison
+
+
+def test_sampled_oracle_reverse_512_fp32(P):
+    """The reversed step at the benchmark's size (512^3 complex64, Klein-step
+    V(z)) on the march kernels: 5 reversed steps from the packet, sampled cells
+    against the FP64 oracle's reversed steps from the same FP32 state on a
+    periodic sub-box of half-width 2*5+1 around each; and 5 forward steps bring
+    the state back."""
+    n, steps, R = 512, 5, 11
+    cfg = workloads.config_step3d(n, dtype=torch.complex64, device="cuda")
+    print("sampled reverse 512^3 fp32", flush=True)
+    lat = P.Lattice3D(n, n, n, dtype=torch.complex64, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    start = [t.clone() for t in cfg["state"]]
+    del cfg["state"]
+    g = np.random.default_rng(31)
+    c = (n // 2, n // 2, n // 4)
+    samples = [tuple(int(round(c[q] + 12.0 * g.standard_normal())) % n for q in range(3)) for _ in range(16)]
+    samples += [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(4)]
+    samples += [(c[0], c[1], c[2]), (0, 0, 0), (n - 1, n - 1, n - 1)]
+    B = 2 * R + 1
+
+    def boxes(arrays):
+        out = []
+        for (i, j, k) in samples:
+            ix = torch.arange(i - R, i + R + 1, device="cuda") % n
+            iy = torch.arange(j - R, j + R + 1, device="cuda") % n
+            iz = torch.arange(k - R, k + R + 1, device="cuda") % n
+            out.append([a.index_select(0, iz).index_select(1, iy).index_select(2, ix).cpu().numpy().astype(np.complex128)
+                        for a in arrays])
+        return out
+
+    before = boxes(lat.state())
+    lat.reverse(steps)
+    after = [[b[a][R, R, R] for a in range(8)] for b in boxes(lat.state())]
+    lat.step(steps)
+    back = rel_l2_t(lat.state(), start)
+    del lat, start
+    free()
+    assert back <= 2 * steps * 2e-6
+    ol = oracle.Lattice3(B, B, B, cfg["dt"])
+    scale = max(max(abs(v) for v in row) for row in after)
+    m, v_int, v_half = cfg["m"], cfg["v_int"], cfg["v_half"]
+    big = 0
+    for (i, j, k), box, got in zip(samples, before, after):
+        iz = (np.arange(k - R, k + R + 1)) % n
+        th = []
+        for a in range(8):
+            tab = v_int if workloads.OFF3[a][2] == 0.0 else v_half
+            sgn = 1.0 if a < 4 else -1.0
+            th.append(np.ascontiguousarray(0.5 * cfg["dt"] * (sgn * m + tab[iz])[:, None, None] * np.ones((1, B, B))))
+        ol.reverse(box, th, steps)
+        for a in range(8):
+            assert abs(box[a][R, R, R] - got[a]) <= steps * 1e-6 * scale, (i, j, k, a)
+            big += abs(got[a]) > 1e-2 * scale
+    assert big >= 30
 
 
 def test_sampled_oracle_parity_512_fp32_site(P):
@@ -501,6 +594,36 @@ def test_adjoint_fd_128_fp64(P):
         assert abs(fd - grad[q]) <= 1e-6 * scale
     del lat
     free()
+
+
+def test_adjoint_complex64_vs_complex128_128(P):
+    """The adjoint workload at its stated size (128^3, 400 steps): the complex64
+    gradient dL/dp against the complex128 one (itself checked against the
+    oracle's adjoint and finite differences), relative to the largest
+    component; and the loss and the reversal's rebuilt initial state."""
+    cfg = workloads.config_adjoint(128)
+    n, steps = cfg["n"], cfg["steps"]
+    print("adjoint complex64 vs complex128 at 128^3", flush=True)
+    H_int = torch.from_numpy(cfg["H_int"])
+    H_half = torch.from_numpy(cfg["H_half"])
+    res = {}
+    for dtype in (torch.complex128, torch.complex64):
+        st = workloads.packet3d(n, n, n, cfg["center"], cfg["sigma"], cfg["k0"], cfg["m"], cfg["dt"],
+                                dtype=dtype, device="cuda")
+        lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+        p = torch.tensor(cfg["p"], dtype=torch.float64, requires_grad=True)
+        loss = P.DiracLoss.apply(p, lat, st, cfg["m"], H_int, H_half, steps, cfg["z0"])
+        loss.backward()
+        res[dtype] = (float(loss), p.grad.numpy().copy(), rel_l2_t(lat.state(), st))
+        del lat, st
+        free()
+    l64, g64, r64 = res[torch.complex128]
+    l32, g32, r32 = res[torch.complex64]
+    err = np.abs(g32 - g64).max() / np.abs(g64).max()
+    print("loss %.9e / %.9e, grad rel err %.3e, rebuilt state %.2e / %.2e" % (l64, l32, err, r64, r32))
+    assert err <= 1e-3
+    assert abs(l32 - l64) <= 1e-5 * abs(l64)
+    assert r64 <= 1e-12 and r32 <= 1e-3
 
 
 def test_batched_full_config_matches_solo(P):

@@ -176,6 +176,36 @@ def test_3d_fp32_vs_oracle(P, kernel, nx, tile_y):
     assert abs(en[0] - eo[0]) <= 1e-5 * eo[2]
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("shape", [(37, 23), (130, 9), (1, 5)])
+def test_2d_observables_vs_oracle(P, dtype, shape):
+    """(2+1)D observables after some steps on a ragged lattice: region sum over
+    x_s >= x0 (x0 on an integer and on a half-integer site column, and outside),
+    first moments, norm and per-component sums, against the oracle's on the same
+    state (complex64 amplitudes widen exactly, both sides sum in FP64: only the
+    summation order differs)."""
+    tol = 1e-13
+    nx, ny = shape
+    print("2d observables %s %s" % (shape, dtype), flush=True)
+    g = np.random.default_rng(97)
+    f0 = rand_state((ny, nx), 4, 98)
+    lat = P.Lattice2D(nx, ny, dtype=dtype, dt=DT2)
+    lat.load(f0)
+    V = [np.ascontiguousarray(0.4 * g.standard_normal((ny, nx))) for _ in range(4)]
+    lat.set_fields(0.3, [torch.from_numpy(v.astype(np.float32 if dtype == torch.complex64 else np.float64))
+                         for v in V])
+    lat.step(9)
+    st = np_state(lat.state())
+    ol = oracle.Lattice2(nx, ny, DT2)
+    for x0 in (float(nx // 2), nx // 2 + 0.5, 0.0, nx + 1.0):
+        got = lat.observables(x0)
+        ref = ol.observe(st, x0)
+        # out[0..5] as the oracle's; out[6..8] are zero in 2D
+        for q in range(6):
+            assert abs(got[q] - ref[q]) <= tol * max(1.0, abs(ref[3]) * max(nx, ny)), (q, x0, got[q], ref[q])
+        assert got[6] == got[7] == got[8] == 0.0
+
+
 # --------------------------------------------------------------------------
 # Adjoint: GPU (reversal) vs oracle (stored states)
 # --------------------------------------------------------------------------
@@ -371,6 +401,26 @@ def test_fp32_site_coefficients(P):
     # theta -> -theta gives the conjugate record exactly (the reversed step uses this)
     gn = out_neg.cpu().numpy()
     assert np.array_equal(gn.real, out.cpu().numpy().real) and np.array_equal(gn.imag, -out.cpu().numpy().imag)
+
+
+def test_fp32_record_device_bits_equal_host(P):
+    """The complex64 record gamma(theta) of the per-site fields (device) and of the
+    V(z) tables (host) come from one source; both give the same bits over a
+    sweep of theta through both sides of |theta| = 1."""
+    import ctypes
+    g = np.random.default_rng(9)
+    th = np.ascontiguousarray(np.concatenate([np.linspace(-4.0, 4.0, 100001), g.uniform(-1.5, 1.5, 100000),
+                                              [0.0, 1e-8, -1e-8, 1.0, -1.0, 5e-4]]))
+    host = np.empty(2 * th.size, np.float32)
+    assert P.lib().dirac_coef_from_theta_host(host.ctypes.data_as(ctypes.c_void_p),
+                                              th.ctypes.data_as(ctypes.c_void_p), th.size) == 0
+    t = torch.from_numpy(th).cuda()
+    dev = torch.empty(th.size, dtype=torch.complex64, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert P.lib().dirac_coef_from_theta(ctypes.c_void_p(dev.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                         th.size, s) == 0
+    d = torch.view_as_real(dev).cpu().numpy().reshape(-1)
+    assert np.array_equal(d.view(np.uint32), host.view(np.uint32))
 
 
 @pytest.mark.parametrize("kernel", ["split", "fused", "fused2"])
@@ -934,3 +984,124 @@ def test_split_setters_and_adjoint_wrapper(P):
     for a, b in zip(outs[0][0] + outs[0][1], outs[1][0] + outs[1][1]):
         assert torch.equal(a, b)
     assert torch.equal(outs[0][2], outs[1][2]) and torch.equal(outs[0][3], outs[1][3])
+
+
+# --------------------------------------------------------------------------
+# Zero values outside the lattice (DIRAC_ZERO_BC): split kernels against the
+# oracle's zero-boundary mode, in both precisions, with V(z) tables and
+# per-site fields; the functional (both forms) and the reversed step.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 2e-5)])
+@pytest.mark.parametrize("mode", ["vz", "site"])
+@pytest.mark.parametrize("shape", [(70, 9, 12), (5, 130, 3), (1, 1, 4)])
+def test_3d_zero_bc_vs_oracle(P, dtype, tol, mode, shape):
+    nx, ny, nz = shape
+    steps = 25
+    print("3d zero bc %s %s %s" % (shape, mode, dtype), flush=True)
+    f0 = rand_state((nz, ny, nx), 8, 501)
+    lat = P.Lattice((nx, ny, nz), dtype=dtype, dt=DT3, zero_bc=True)
+    lat.load(f0)
+    f0_lat = np_state(lat.state())
+    ol = oracle.Lattice3(nx, ny, nz, DT3, zero_bc=True)
+    if mode == "vz":
+        v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+        lat.set_potential_z(0.5, v_int, v_half)
+        th = ol.theta_vz(0.5, v_int, v_half)
+    else:
+        g = np.random.default_rng(502)
+        V = [np.ascontiguousarray(0.5 * g.standard_normal((nz, ny, nx))) for _ in range(8)]
+        if dtype == torch.complex64:
+            V = [v.astype(np.float32) for v in V]
+        lat.set_fields(0.3, [torch.from_numpy(v) for v in V])
+        th = [np.ascontiguousarray(0.5 * DT3 * ((1.0 if a < 4 else -1.0) * 0.3 + V[a].astype(np.float64)))
+              for a in range(8)]
+    e0 = lat.norm()
+    eo0 = ol.energy(f0_lat)
+    # complex64 lattices evaluate the functional (in FP64) with the r_j of their
+    # FP32 steps, rounded to float: ~1e-8 relative to the oracle's FP64 r_j
+    rtol0 = 1e-12 if dtype == torch.complex128 else 1e-8
+    assert abs(e0[0] - eo0[0]) <= rtol0 * eo0[2] and abs(e0[1] - eo0[1]) <= rtol0 * eo0[2]
+    lat.step(steps)
+    f = [a.copy() for a in f0_lat]
+    ol.step(f, th, steps)
+    assert rel_l2(np_state(lat.state()), f) <= tol * (1 if dtype == torch.complex128 else steps)
+    e1 = lat.norm()
+    etol = 1e-13 if dtype == torch.complex128 else 1e-5
+    assert abs(e1[0] - e0[0]) <= etol * abs(e0[0]) and abs(e1[1] - e1[0]) <= 1e-12 * e1[2]
+    lat.reverse(steps)
+    assert rel_l2(np_state(lat.state()), f0_lat) <= tol * (1 if dtype == torch.complex128 else 2 * steps)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 2e-5)])
+@pytest.mark.parametrize("shape", [(130, 37), (1, 9), (64, 4)])
+def test_2d_zero_bc_vs_oracle(P, dtype, tol, shape):
+    nx, ny = shape
+    steps = 30
+    print("2d zero bc %s %s" % (shape, dtype), flush=True)
+    f0 = rand_state((ny, nx), 4, 511)
+    g = np.random.default_rng(512)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)]
+    if dtype == torch.complex64:
+        V = [v.astype(np.float32) for v in V]
+    lat = P.Lattice((nx, ny), dtype=dtype, dt=DT2, zero_bc=True)
+    lat.load(f0)
+    f0_lat = np_state(lat.state())
+    lat.set_fields(0.4, [torch.from_numpy(v) for v in V])
+    th = [np.ascontiguousarray(0.5 * DT2 * ((1.0 if a < 2 else -1.0) * 0.4 + V[a].astype(np.float64)))
+          for a in range(4)]
+    ol = oracle.Lattice2(nx, ny, DT2, zero_bc=True)
+    e0 = lat.norm()
+    eo0 = ol.energy(f0_lat)
+    rtol0 = 1e-12 if dtype == torch.complex128 else 1e-8      # r_j rounded to float (see the 3D test)
+    assert abs(e0[0] - eo0[0]) <= rtol0 * eo0[2]
+    buf = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lat.step(steps - 1)
+    lat.step_norm(1, buf)
+    f = [a.copy() for a in f0_lat]
+    ol.step(f, th, steps)
+    assert rel_l2(np_state(lat.state()), f) <= tol * (1 if dtype == torch.complex128 else steps)
+    eo1 = ol.energy(f)
+    etol = 1e-13 if dtype == torch.complex128 else 1e-5
+    assert abs(float(buf[0]) - eo1[0]) <= etol * eo1[2] and abs(eo1[0] - eo0[0]) <= 1e-13 * eo0[2]
+    lat.reverse(steps)
+    assert rel_l2(np_state(lat.state()), f0_lat) <= tol * (1 if dtype == torch.complex128 else 2 * steps)
+
+
+# --------------------------------------------------------------------------
+# Reversed steps on the march kernels: one split reversed C,D half-step, the
+# forward march with r -> -r and theta -> -theta, one split reversed A,B
+# half-step.  The same helpers in the same order as the split reversed steps,
+# so the same bits; V(z) tables and per-site records, both precisions, odd and
+# even step counts, ragged tiles and z-chunks.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("mode", ["vz", "site"])
+@pytest.mark.parametrize("shape,steps", [((70, 9, 12), 7), ((130, 20, 11), 6), ((64, 8, 5), 1), ((6, 3, 4), 2)])
+def test_reverse_march_bitwise_equals_split(P, dtype, mode, shape, steps):
+    nx, ny, nz = shape
+    print("reverse march %s %s %s n=%d" % (shape, mode, dtype, steps), flush=True)
+    f0 = rand_state((nz, ny, nx), 8, 601)
+    g = np.random.default_rng(602)
+    V = [np.ascontiguousarray(0.5 * g.standard_normal((nz, ny, nx))) for _ in range(8)]
+    if dtype == torch.complex64:
+        V = [v.astype(np.float32) for v in V]
+    v_int, v_half = workloads.step_potential(nz, 1.5, nz / 2.0, 2.0)
+    out = []
+    for kernel in ("split", "auto", "fused"):
+        lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+        lat.set_kernel(kernel)
+        lat.load(f0)
+        if mode == "vz":
+            lat.set_potential_z(0.5, v_int, v_half)
+        else:
+            lat.set_fields(0.3, [torch.from_numpy(v) for v in V])
+        lat.reverse(steps)
+        out.append([t.clone() for t in lat.state()])
+        if kernel == "auto":
+            lat.step(steps)          # and forward again: back to the start up to rounding
+            tol = 1e-13 if dtype == torch.complex128 else 2e-5 * steps
+            assert rel_l2(np_state(lat.state()), np_state([torch.from_numpy(a).to(dtype) for a in f0])) <= tol
+        del lat
+    for kernel, st in zip(("auto", "fused"), out[1:]):
+        for a, b in zip(out[0], st):
+            assert torch.equal(a, b), kernel

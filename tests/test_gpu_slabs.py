@@ -94,3 +94,36 @@ def test_slab_refuses_steps_past_its_halo(P):
     assert lat.halo_steps == 2
     with pytest.raises(P.DiracError, match="at most 2 steps"):
         lat.step(3)
+
+
+def test_slab_step_norm_over_partial_cap(P):
+    """A slab cross-section whose two-step launch has more workgroups (1280 x 1024
+    complex128: 40 x 128 tiles of 32 x 8 cells) than the fixed partial count of
+    the standalone reductions (4608 pairs): the partial area is sized from the
+    lattice, so dirac_step_norm still advances both steps in one launch with the
+    functional summed in-step (a reduction after the launch would read stale
+    halo planes); the state stays bitwise equal to the whole periodic lattice
+    and the slabs' functional sums add up to the whole's."""
+    nx, ny, nz, slabs = 1280, 1024, 8, 2
+    print("slab step_norm over the partial cap", flush=True)
+    f0 = rand_state((nz, ny, nx), 8, 313)
+    whole = P.Lattice3D(nx, ny, nz, dtype=torch.complex128, dt=DT3)
+    whole.set_kernel("fused")
+    whole.set_potential_z(0.5)
+    whole.load(f0)
+    parts = P.SlabDecomposition(nx, ny, nz, slabs, dtype=torch.complex128, dt=DT3)
+    parts.set_potential_z(0.5)
+    parts.load(f0)
+    del f0
+    assert parts.halo_steps == 2
+    for _ in range(2):
+        ew = whole.step_norm(2)
+        es = sum(lat.step_norm(2) for lat in parts.parts)
+        parts.exchange()
+        torch.cuda.synchronize()
+        assert abs(float(es[0]) - float(ew[0])) <= 1e-12 * float(ew[1])
+        assert abs(float(es[1]) - float(ew[1])) <= 1e-12 * float(ew[1])
+    for a, b in zip(whole.state(), parts.state()):
+        assert torch.equal(a, b)
+    del whole, parts
+    torch.cuda.empty_cache()

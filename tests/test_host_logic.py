@@ -151,3 +151,36 @@ def test_checkpoint_round_trip_2d_slab_and_errors(tmp_path):
     save_file({"x": torch.zeros(1)}, path)
     with pytest.raises(ValueError, match="not a lattice checkpoint"):
         load_checkpoint(path, device="cpu")
+
+
+def test_fp32_record_on_the_host():
+    """The complex64 coefficient record gamma = 1 - alpha = 2 i theta/(1 + i theta)
+    of the time-averaged term (Eqs. ss1-ss4), as the host computes it for the
+    V(z) tables (the device records use the same source; their bits are
+    compared on the GPU): within 1e-6 of the exact value on both sides of
+    |theta| = 1, |1 - gamma| = 1 to a few 1e-8, conjugate under theta -> -theta."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_1309_3452_amd import _abi
+    L = _abi.lib()
+    g = np.random.default_rng(11)
+    th = np.ascontiguousarray(np.concatenate([g.uniform(-3.0, 3.0, 20000), [0.0, 1e-8, -1e-8, 1.0, -1.0, 0.3]]))
+    out = np.empty(2 * th.size, np.float32)
+    outn = np.empty_like(out)
+    assert L.dirac_coef_from_theta_host(out.ctypes.data_as(ctypes.c_void_p), th.ctypes.data_as(ctypes.c_void_p),
+                                        th.size) == 0
+    thn = np.ascontiguousarray(-th)
+    assert L.dirac_coef_from_theta_host(outn.ctypes.data_as(ctypes.c_void_p), thn.ctypes.data_as(ctypes.c_void_p),
+                                        th.size) == 0
+    gam = out[0::2].astype(np.float64) + 1j * out[1::2].astype(np.float64)
+    exact = 2j * th / (1.0 + 1j * th)
+    assert np.max(np.abs(gam - exact) / np.maximum(1.0, np.abs(exact))) <= 1.01e-6
+    unit = np.abs((1.0 - gam.real) ** 2 + gam.imag ** 2 - 1.0)
+    assert unit.max() <= 8e-8 and np.median(unit) <= 3e-9
+    assert np.array_equal(outn[0::2], out[0::2]) and np.array_equal(outn[1::2], -out[1::2])
+    assert L.dirac_coef_from_theta_host(None, th.ctypes.data_as(ctypes.c_void_p), 1) == -1
+    bad = np.array([np.nan])
+    assert L.dirac_coef_from_theta_host(out.ctypes.data_as(ctypes.c_void_p), bad.ctypes.data_as(ctypes.c_void_p),
+                                        1) == -4
