@@ -27,10 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP per FMA x 2.4 GHz (packed FP32, which would double it, is not used)
 FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# per amplitude update: S (3 differences, 2 products, 4 FMA) 16 FLOP + update (2 products, 6 FMA, 2 differences)
-# 16 FLOP; 16 amplitude updates per cell-step
-ALU_FLOP_PER_CELL_STEP = 16 * 32
+# per amplitude update: S (3 complex differences, 3 real scalings, 2 complex sums) 16 FLOP + the update
+# (two complex products and a difference) 16 FLOP; a cell holds 8 amplitudes, each updated once per step
+ALU_FLOP_PER_CELL_STEP = 8 * 32
 NORM_EVERY = 10
+ACCURACY_STEPS = 1000          # the norm-drift and phase-error horizon, independent of --steps
 
 
 def parse():
@@ -42,13 +43,15 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the untimed 1000-step accuracy passes (for profiler runs of the timed kernels)")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2"],
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
                     choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "links2d", "klein2d",
-                             "slab3d", "site3d"],
+                             "slab3d", "site3d", "reverse3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -135,11 +138,84 @@ def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel, keep=False):
                drift=abs(e_end[0] - e_start[0]) / abs(e_start[0]), drift_max=drift_series,
                plain_norm_change=abs(e_end[2] - e_start[2]) / e_start[2], steps_total=steps + warmup)
     if keep:
-        out["lat"] = lat          # the final state, for the FP32 / FP64 comparison
+        out["lat"] = lat          # reused by the accuracy pass
     else:
         del lat
         torch.cuda.empty_cache()
     return out
+
+
+def accuracy_pass(lat, n, dtype, steps=ACCURACY_STEPS):
+    """The headline packet from its initial state for `steps` steps in the
+    timed launch sequence (two-step launches, E_r in-step every NORM_EVERY
+    steps): the relative drift of E_r at the end and its largest excursion."""
+    import torch
+
+    import workloads
+    cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+    lat.load(cfg["state"])
+    del cfg
+    e0 = lat.norm()
+    G = 2
+    norms = torch.zeros((steps // NORM_EVERY + 1, 2), dtype=torch.float64, device="cuda")
+    done = 0
+    while done < steps:
+        g = min(G, steps - done)
+        if (done + g) % NORM_EVERY == 0:
+            lat.step_norm(g, norms[(done + g) // NORM_EVERY])
+        else:
+            lat.step(g)
+        done += g
+    e1 = lat.norm()
+    nr = norms[1:].cpu().numpy()
+    return {"E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]),
+            "E_r_rel_drift_max_every10": float(abs(nr[:, 0] - e0[0]).max() / abs(e0[0])),
+            "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
+
+
+def plane_wave_z(nx, ny, nz, kz, m, dt, dtype, t_shift=0.0):
+    """Eigen plane wave psi^(1) of Sect. 2.1 travelling along z (k = (0, 0, kz)):
+    every amplitude is its spinor component times exp(i (kz z_s - w t)) at its own
+    site and time sheet, with w from Eq. (pwdsip); built in FP64 on the device."""
+    import torch
+    Pz = 2.0 * math.sin(kz / 2.0)
+    X = math.sqrt((m * m + Pz * Pz) / (m * m + (2.0 / dt) ** 2))
+    w = 2.0 / dt * math.asin(X)
+    E, mk = 2.0 / dt * X, m * math.sqrt(1.0 - X * X)
+    spinor = [1.0, 0.0, Pz / (E + mk), 0.0]                 # A, B, C, D of psi^(1) with Px = Py = 0
+    zoff = [0.0, 0.0, 0.5, 0.5, 0.5, 0.5, 0.0, 0.0]           # z offsets of A0 A1 B0 B1 C0 C1 D0 D1
+    z = torch.arange(nz, dtype=torch.float64, device="cuda")
+    out = []
+    for a in range(8):
+        t = (-0.5 * dt if a < 4 else 0.0) + t_shift
+        col = spinor[a // 2] * torch.exp(1j * (kz * (z + zoff[a]) - w * t))
+        out.append(col.view(nz, 1, 1).expand(nz, ny, nx).to(dtype).contiguous())
+    return out, w
+
+
+def plane_wave_phase_error(dtype, nz=512, nxy=128, kz_index=46, m=0.5, steps=ACCURACY_STEPS):
+    """Phase of <psi_exact, psi> after `steps` steps of a plane wave at
+    kz = 2 pi kz_index / nz against the closed-form e^{-i w t} (Eq. pwdsip), and
+    its amplitude error.  x and y are uniform, so every cell computes the same
+    values and the error does not depend on nx, ny."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    kz = 2 * math.pi * kz_index / nz
+    st, w = plane_wave_z(nxy, nxy, nz, kz, m, workloads.DT3, dtype)
+    lat = P.Lattice3D(nxy, nxy, nz, dtype=dtype, dt=workloads.DT3)
+    lat.set_potential_z(m)
+    lat.load(st)
+    del st
+    lat.step(steps)
+    ex, _ = plane_wave_z(nxy, nxy, nz, kz, m, workloads.DT3, torch.complex128, t_shift=steps * workloads.DT3)
+    inner = sum(complex(torch.sum(torch.conj(b) * a.to(torch.complex128))) for a, b in zip(lat.state(), ex))
+    nrm = sum(float(torch.sum(torch.abs(b) ** 2)) for b in ex)
+    del lat, ex
+    torch.cuda.empty_cache()
+    return {"phase_error_rad": abs(math.atan2(inner.imag, inner.real)), "amplitude_error": abs(abs(inner) / nrm - 1.0),
+            "k_z": kz, "omega": w, "m": m, "steps": steps, "lattice": "%dx%dx%d" % (nxy, nxy, nz)}
 
 
 def compare_states(s32, s64):
@@ -181,24 +257,41 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline():
+def cpu_baseline(n=512, steps_all=3, steps_one=1):
+    """The FP64 oracle on the host cores, on the headline workload itself (n^3,
+    same packet, mass and V(z)): steps_all steps on all cores, then steps_one
+    step(s) on one thread; the input is built on the GPU and copied to host
+    memory before timing."""
     import numpy as np
+    import torch
 
     import oracle
     import workloads
-    n, nsteps = 128, 300
     ol = oracle.Lattice3(n, n, n, workloads.DT3)
     vi, vh = workloads.step_potential(n, 1.5, n / 2.0, 4.0)
     th = ol.theta_vz(0.5, vi, vh)
-    st = workloads.packet3d(n, n, n, (n / 2.0, n / 2.0, n / 4.0), 12.0, (0.0, 0.0, 0.56), 0.5, workloads.DT3)
-    f = [np.ascontiguousarray(t.numpy()) for t in st]
+    st = workloads.packet3d(n, n, n, (n / 2.0, n / 2.0, n / 4.0), 12.0, (0.0, 0.0, 0.56), 0.5, workloads.DT3,
+                            device="cuda")
+    f = [np.ascontiguousarray(t.cpu().numpy()) for t in st]
+    del st
+    torch.cuda.empty_cache()
+    cores = oracle.threads()
     t0 = time.perf_counter()
-    ol.step(f, th, nsteps)
-    dt = time.perf_counter() - t0
-    return {"value": n ** 3 * nsteps / dt, "unit": "site-updates/s", "cores": oracle.threads(), "kind": "oracle",
-            "cpu_model": cpu_model(),
-            "sample": "FP64 C oracle, same physics on a %d^3 lattice, %d steps (%.1f s); "
-                      "site-updates/s is per cell-step, independent of lattice size" % (n, nsteps, dt)}
+    ol.step(f, th, steps_all)
+    t_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        ol.step(f, th, steps_one)
+        t_one = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    cells = float(n) ** 3
+    return {"value": cells * steps_all / t_all, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "value_1thread": cells * steps_one / t_one, "cores_1thread": 1,
+            "sample": "FP64 C oracle on the headline workload (%d^3, m=0.5, V(z) step, same packet): %d steps on "
+                      "%d threads (%.1f s), then %d step(s) on 1 thread (%.1f s)"
+                      % (n, steps_all, cores, t_all, steps_one, t_one)}
 
 
 def _timed(fn, reps=1):
@@ -247,7 +340,7 @@ def bench_batched(steps):
         solo_ms += _timed(lambda: lat.step(steps))
     best = min(res, key=res.get)
     value = cells * steps / (res[best] * 1e-3)
-    alg = 96.0 * cells            # 4 complex64 amplitudes read + 4 written, 4 complex64 per-site records read, per cell-step
+    alg = 96.0 * cells            # 4 complex64 amplitudes read + 4 written, 4 complex64 per-site records read, per cell-pass
     # tuning candidates 8..14 of the batch library make two-step passes (mode 1 only;
     # the persistent mode makes one-step passes); a two-step pass moves each byte once
     spp = 2 if (best.startswith("mode1") and choice[0] >= 8) else 1
@@ -259,11 +352,13 @@ def bench_batched(steps):
                                    "m in [0,1], per-site coefficient records, complex64", "cells": cells, "best": best,
                        "tile_choice": choice},
             "variants_ms": res, "sequential_single_lattice_ms": solo_ms, "speedup_vs_sequential": solo_ms / res[best],
-            "roofline": {"bound": "hbm", "achieved": alg * steps / (res[best] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": alg * steps / (res[best] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "traffic": None, "alg_bytes_per_step": alg, "steps_per_pass": spp,
-                         "bus_bytes_per_step_min": alg / spp,
-                         "bus_frac_min": alg / spp * steps / (res[best] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+            # per pass (one launch) every amplitude is read and written once and every
+            # record read once: 96 B per cell and pass, whatever the steps per pass
+            "roofline": {"bound": "hbm", "achieved": alg * steps / spp / (res[best] * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg * steps / spp / (res[best] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": None, "alg_bytes_per_launch": alg, "steps_per_pass": spp,
+                         "effective_GBs_per_step_model": alg * steps / (res[best] * 1e-3) / 1e9}}
 
 
 def bench_adjoint(steps, dtype_name):
@@ -400,7 +495,9 @@ def bench_site3d(n, steps, dtype_name):
     # once (complex64 gamma or float64 theta, 8 B each)
     alg_step = (16 * b + 8 * 8) * cells
     ms = out["fused2"]
-    achieved = alg_step / (ms * 1e-3) / 1e9
+    # the two-step launch reads and writes each amplitude and reads each record
+    # once at least: alg_step bytes per launch (two steps)
+    achieved = alg_step / (2 * ms * 1e-3) / 1e9
     return {"metric": "site-updates/s, (3+1)D %d^3 with per-site potential records" % n,
             "value": cells / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
             "warmup": 2, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -411,9 +508,56 @@ def bench_site3d(n, steps, dtype_name):
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k3_fused2 per-site (two steps per launch)", "avg_launch_ms": 2 * ms,
-                         "alg_bytes_per_launch": 2 * alg_step},
+                         "alg_bytes_per_launch": alg_step,
+                         "effective_GBs_per_step_model": alg_step / (ms * 1e-3) / 1e9},
             "one_step_kernel_ms_per_step": out["fused"],
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
+
+
+def bench_reverse3d(n, steps, dtype_name):
+    """The reversed step on the n^3 headline workload: the forward default, the
+    reversed steps on the march kernels (the default) and on the split kernels."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    dtype = torch.complex64 if dtype_name == "f32" else torch.complex128
+    cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    torch.cuda.empty_cache()
+    e0 = lat.norm()
+    lat.step(2)
+    fwd = _timed(lambda: lat.step(steps)) / steps
+    lat.reverse(2)
+    rev = _timed(lambda: lat.reverse(steps)) / steps
+    lat.set_kernel("fused")
+    fwd1 = _timed(lambda: lat.step(steps)) / steps
+    lat.set_kernel("split")
+    rev_split = _timed(lambda: lat.reverse(steps // 4)) / (steps // 4)
+    lat.set_kernel("auto")
+    lat.step(steps // 4)
+    e1 = lat.norm()
+    cells = n ** 3
+    b = 8 if dtype_name == "f32" else 16
+    # per march launch: every amplitude read once and written once (two steps per launch)
+    alg = 16 * b * cells
+    return {"metric": "site-updates/s of the reversed step, (3+1)D %d^3" % n,
+            "value": cells / (rev * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+            "ms_per_step": rev, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype_name, "data": "synthetic",
+            "config": {"workload": "(3+1)D %d^3 headline Klein-step lattice, %d reversed steps per call: one split "
+                                   "reversed C,D half-step, the forward march with r, theta negated, one split "
+                                   "reversed A,B half-step" % (n, steps), "cells": cells},
+            "roofline": {"bound": "hbm", "achieved": alg / (2 * rev * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg / (2 * rev * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k3_fused2 with the reversed tables", "alg_bytes_per_launch": alg},
+            "forward_ms_per_step": fwd, "forward_one_step_kernel_ms_per_step": fwd1,
+            "reverse_split_ms_per_step": rev_split, "reverse_over_forward": rev / fwd,
+            "reverse_over_one_step_forward": rev / fwd1,
+            "E_r_rel_change_after_round_trips": abs(e1[0] - e0[0]) / abs(e0[0])}
 
 
 def bench_klein2d(phi_deg):
@@ -474,7 +618,8 @@ def bench_klein2d(phi_deg):
     variants["fused2_graph"] = _timed(lambda: graph.replay(), reps=3) / gsteps
     best = min(variants, key=variants.get)
     ms_step = variants[best]
-    alg = 96.0 * cells          # 4 complex64 amplitudes read + written, 4 complex64 coefficient records read
+    spp = 1 if best == "fused" else 2        # steps per launch (auto is the two-step march at this size)
+    alg = 96.0 * cells          # per launch: 4 complex64 amplitudes read + written, 4 complex64 coefficient records read
     return {"metric": "site-updates/s, (2+1)D Klein-step scattering %dx%d complex64" % (nx, ny),
             "value": cells / (ms_step * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": steps,
             "warmup": 4, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -483,9 +628,10 @@ def bench_klein2d(phi_deg):
                                    "sigma=30 at %g deg from the step normal, absorbing frame of width 32, "
                                    "per-site complex coefficient records" % (nx, ny, phi_deg), "cells": cells},
             "variants_ms_per_step": variants, "best": best,
-            "roofline": {"bound": "hbm", "achieved": alg / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                         "alg_bytes_per_step": alg},
+            "roofline": {"bound": "hbm", "achieved": alg / (spp * ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg / (spp * ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "alg_bytes_per_launch": alg, "steps_per_launch": spp,
+                         "effective_GBs_per_step_model": alg / (ms_step * 1e-3) / 1e9},
             "physics": {"transmitted_probability_t250": meas[0][0], "transmitted_probability_t350": meas[1][0],
                         "refraction_angle_deg": angle}}
 
@@ -564,7 +710,7 @@ def bench_slab3d(steps):
     e1 = sl.norm()
     cells = n * n * nzs
     plane = n * n * 8
-    alg = 128.0 * cells * k
+    alg = 128.0 * cells          # per launch: each amplitude read and written once
     ms = (k_ms + x_ms) / k
     return {"metric": "site-updates/s of one device's z-slab (512x512x64 of a 512^3 lattice over 8 devices), complex64",
             "value": cells / (ms * 1e-3), "unit": "site-updates/s", "n_gpus": 1, "steps": launches * k,
@@ -578,7 +724,8 @@ def bench_slab3d(steps):
             "roofline": {"bound": "hbm", "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k3_fused2<float> in z-slab mode" if k == 2 else "k3_fused<float> in z-slab mode",
-                         "steps_per_launch": k},
+                         "steps_per_launch": k, "alg_bytes_per_launch": alg,
+                         "effective_GBs_per_step_model": alg * k / (k_ms * 1e-3) / 1e9},
             "halo": {"bytes_per_face_filled": 8 * 2 * plane, "refills_per_step": 1.0 / k, "xgmi_link_GBs": 153.0,
                      "modeled_link_ms_per_face": 8 * 2 * plane / 153e9 * 1e3},
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0])}
@@ -665,6 +812,11 @@ def main():
             print(json.dumps(bench_site3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
             torch.cuda.empty_cache()
         return
+    if args.workload == "reverse3d":
+        for d in ("f32", "f64"):
+            print(json.dumps(bench_reverse3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
+            torch.cuda.empty_cache()
+        return
     if args.workload == "links3d":
         for d in ("f32", "f64"):
             print(json.dumps(bench_links3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
@@ -672,24 +824,34 @@ def main():
         return
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3
-    same = not args.no_fp64 and (args.fp64_steps or K) == K
-    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel, keep=same)
-    r64 = None
-    if not args.no_fp64:
-        r64 = run_gpu(n, torch.complex128, args.fp64_steps or K, W, 0, 0, args.kernel, keep=same)
-    packet = None
-    if same:
-        # the FP32 form against the FP64 path after the same steps from the same packet
-        l2, ph = compare_states(r32["lat"].state(), r64["lat"].state())
-        packet = {"rel_l2_fp32_vs_fp64": l2, "overlap_phase_rad": ph, "steps": K + W}
+    K64 = args.fp64_steps or K
+    r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel, keep=True)
+    G = r32["steps_per_launch"]
+    # accuracy over a fixed horizon, from the initial packet (untimed)
+    acc = not args.no_accuracy
+    acc32 = accuracy_pass(r32["lat"], n, torch.complex64) if acc else {}
+    r64 = acc64 = packet = None
+    if args.no_fp64:
+        del r32["lat"]
+        torch.cuda.empty_cache()
+    else:
+        r64 = run_gpu(n, torch.complex128, K64, W, 0, 0, args.kernel, keep=True)
+        if acc:
+            acc64 = accuracy_pass(r64["lat"], n, torch.complex128)
+            # both lattices now hold the packet after ACCURACY_STEPS steps
+            l2, ph = compare_states(r32["lat"].state(), r64["lat"].state())
+            packet = {"rel_l2_fp32_vs_fp64": l2, "overlap_phase_rad": ph, "steps": ACCURACY_STEPS}
         del r32["lat"], r64["lat"]
         torch.cuda.empty_cache()
+    pw32 = plane_wave_phase_error(torch.complex64) if acc else None
+    pw64 = plane_wave_phase_error(torch.complex128) if acc else None
     value = cells * K / r32["wall_s"]
-    G = r32["steps_per_launch"]
-    # algorithmic bytes per launch: 16 amplitudes x 8 B per cell-step (each amplitude
-    # read and written once per step) x the G steps one launch advances
-    alg_bytes = 128.0 * cells * G
-    achieved = alg_bytes / (r32["launch_ms"] * 1e-3) / 1e9
+    launch_s = r32["launch_ms"] * 1e-3
+    # algorithmic bytes of one launch: every amplitude of the state read once and
+    # written once (16 x 8 B per cell for complex64), whatever the number of steps
+    # the launch advances -- the least any launch can move
+    alg_bytes = 128.0 * cells
+    achieved = alg_bytes / launch_s / 1e9
     traffic = profiled_traffic("fp32", n, G)
     copy_gbs = copy_ceiling_gbs()
     kname = "k3_fused2<float> (two steps per launch" if G == 2 else "k3_fused<float> (one step per launch"
@@ -717,33 +879,50 @@ def main():
                      "kernel": kname + "; every fifth launch also sums E_r)" if G == 2 else kname + "; every tenth launch also sums E_r)",
                      "steps_per_launch": G,
                      "alg_bytes_per_launch": alg_bytes,
+                     "alg_unit": "cell-launch: 16 amplitudes x 8 B, each read once and written once per launch",
                      "avg_launch_ms": r32["launch_ms"],
-                     "hbm_frac": (traffic / (r32["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     # bus view from the committed counters: bytes that crossed HBM per launch over
+                     # the launch time, and their excess over the algorithmic bytes
+                     "hbm_GBs": (traffic / launch_s / 1e9) if traffic else None,
+                     "hbm_frac": (traffic / launch_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "traffic_over_alg": (traffic / alg_bytes) if traffic else None,
                      "kernel_source_sha": kernel_source_hash(G),
-                     "copy_ceiling_GBs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs,
-                     # the two-step kernel moves about half the algorithmic bytes across the bus and is
-                     # limited by VALU issue: its useful FP32 arithmetic (32 FLOP per amplitude update,
-                     # 16 updates per cell-step) against the non-packed FP32 vector peak
+                     "copy_ceiling_GBs": copy_gbs,
+                     "hbm_frac_of_copy_ceiling": (traffic / launch_s / 1e9 / copy_gbs) if traffic else None,
+                     # the rate a kernel moving 128 B per cell-step (one step per pass) would need
+                     # to match this one: an effective bandwidth, not a fraction of any peak
+                     "effective_GBs_per_step_model": 128.0 * cells * G / launch_s / 1e9,
+                     # useful FP32 arithmetic (32 FLOP per amplitude update, 8 updates per cell-step)
+                     # against the non-packed FP32 vector peak
                      "alu": {"flop_per_cell_step": ALU_FLOP_PER_CELL_STEP,
                              "achieved_TFLOPs": ALU_FLOP_PER_CELL_STEP * value / 1e12,
                              "peak_TFLOPs": FP32_NONPACKED_TFLOPS,
                              "frac": ALU_FLOP_PER_CELL_STEP * value / 1e12 / FP32_NONPACKED_TFLOPS}},
-        "norm_error": {"E_r_rel_drift_fp32": r32["drift"], "E_r_rel_drift_fp32_max_every10": r32["drift_max"],
-                       "steps_total": r32["steps_total"], "plain_norm_rel_change": r32["plain_norm_change"]},
+        "norm_error": {"steps": ACCURACY_STEPS if acc else None,
+                       "E_r_rel_drift_fp32": acc32.get("E_r_rel_drift"),
+                       "E_r_rel_drift_fp32_max_every10": acc32.get("E_r_rel_drift_max_every10"),
+                       "plain_norm_rel_change_fp32": acc32.get("plain_norm_rel_change"),
+                       "plane_wave_fp32": pw32, "plane_wave_fp64": pw64,
+                       "timed_run_E_r_rel_drift_fp32": r32["drift"], "timed_run_steps": r32["steps_total"]},
         "amplitude_updates_per_s": 8 * value,
     }
     if r64 is not None:
-        v64 = cells * (args.fp64_steps or K) / r64["wall_s"]
+        v64 = cells * K64 / r64["wall_s"]
         G64 = r64["steps_per_launch"]
-        a64 = 256.0 * cells * G64 / (r64["launch_ms"] * 1e-3) / 1e9
-        line["fp64"] = {"value": v64, "unit": "site-updates/s", "ms_per_step": r64["wall_s"] * 1e3 / (args.fp64_steps or K),
-                        "roofline_frac": a64 / HBM_PEAK_GBS, "achieved_GBs": a64, "avg_launch_ms": r64["launch_ms"],
-                        "steps_per_launch": G64, "E_r_rel_drift": r64["drift"]}
+        l64 = r64["launch_ms"] * 1e-3
+        a64 = 256.0 * cells / l64 / 1e9
+        t64 = profiled_traffic("fp64", n, G64)
+        line["fp64"] = {"value": v64, "unit": "site-updates/s", "ms_per_step": r64["wall_s"] * 1e3 / K64,
+                        "roofline_frac": a64 / HBM_PEAK_GBS, "achieved_GBs": a64,
+                        "alg_bytes_per_launch": 256.0 * cells, "avg_launch_ms": r64["launch_ms"],
+                        "traffic": t64, "hbm_frac": (t64 / l64 / 1e9 / HBM_PEAK_GBS) if t64 else None,
+                        "effective_GBs_per_step_model": 256.0 * cells * G64 / l64 / 1e9,
+                        "steps_per_launch": G64, "kernel_source_sha": kernel_source_hash(G64)}
         line["fp32_speedup_over_fp64"] = value / v64
-    if packet is not None:
+        line["norm_error"]["E_r_rel_drift_fp64"] = acc64["E_r_rel_drift"] if acc64 else None
         line["norm_error"]["packet_vs_fp64"] = packet
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)
 
 
