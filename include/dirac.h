@@ -334,6 +334,26 @@ int dirac_norm_device(dirac_ctx *ctx, void *dev_out, void *stream);
 int dirac_norm(dirac_ctx *ctx, double out[3], void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dirac_norm_device without bound scratch.  Same values, same bits: the same
+ * reduction kernels, whose partial sums go to a library-owned device array of
+ * DIRAC_STATIC_SCRATCH_BYTES bytes per GPU (held until the process ends)
+ * instead of the caller-bound scratch.  The reduction needs kReduceBlocks x 3
+ * doubles (24 KiB) whatever the lattice size; a layout that did not fit would
+ * be refused with DIRAC_E_SHAPE.  Allocates nothing (no hipMalloc, no
+ * allocating library call); the array's device address is looked up once per
+ * GPU on the first call there.  Every call on one GPU shares that array: calls
+ * that overlap in time on one GPU (other streams, other threads, other
+ * contexts) race and must be ordered by the caller.  Asynchronous on stream;
+ * writes 3 doubles to dev_out.  DIRAC_E_ARG for a null context or output,
+ * DIRAC_E_STATE without a bound state or for a batch context, DIRAC_E_HIP on a
+ * failed lookup or launch.
+ */
+#define DIRAC_STATIC_SCRATCH_BYTES 65536
+int dirac_norm_device_static(dirac_ctx *ctx, void *dev_out, void *stream);
+
+/*
  * n >= 1 steps (as dirac_step) whose last step also evaluates, on the state it
  * produces, the conserved functional (Lemma of Sect. 2.2, Eq. EPM; Sect. 3 in
  * 2D) in its C,D-summed form (dev_out[0], equal to dirac_norm's values) and

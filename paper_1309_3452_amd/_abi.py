@@ -32,6 +32,7 @@ EXPORTS = (
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
     "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields", "dirac_set_mass",
     "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune", "dirac_coef_from_theta_host",
+    "dirac_norm_device_static",
 )
 
 
@@ -73,6 +74,7 @@ def lib():
         "dirac_reverse": ([P, I64, P], I),
         "dirac_step_norm": ([P, I64, P, P], I),
         "dirac_norm_device": ([P, P, P], I),
+        "dirac_norm_device_static": ([P, P, P], I),
         "dirac_norm": ([P, ctypes.POINTER(D), P], I),
         "dirac_observables": ([P, D, ctypes.POINTER(D), P], I),
         "dirac_seed_region": ([P, D, PP, P], I),
