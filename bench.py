@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="lattice edge (cells)")
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--precision", default="both", choices=["both", "f64"],
+                    help="f64: time the complex128 step alone (for profiler runs of that kernel)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the untimed 1000-step accuracy passes (for profiler runs of the timed kernels)")
@@ -825,6 +827,23 @@ def main():
     n, K, W = args.n, args.steps, args.warmup
     cells = n ** 3
     K64 = args.fp64_steps or K
+    if args.precision == "f64":
+        r64 = run_gpu(n, torch.complex128, K64, W, 0, 0, args.kernel)
+        l64 = r64["launch_ms"] * 1e-3
+        v64 = cells * K64 / r64["wall_s"]
+        t64 = profiled_traffic("fp64", n, r64["steps_per_launch"])
+        print(json.dumps({"metric": "site-updates/s, (3+1)D %d^3 complex128 step" % n, "value": v64,
+                          "unit": "site-updates/s", "n_gpus": 1, "steps": K64, "warmup": W,
+                          "ms_per_step": r64["wall_s"] * 1e3 / K64, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "(3+1)D %d^3 headline physics, complex128" % n, "cells": cells},
+                          "roofline": {"bound": "hbm", "achieved": 256.0 * cells / l64 / 1e9, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": 256.0 * cells / l64 / 1e9 / HBM_PEAK_GBS,
+                                       "traffic": t64, "avg_launch_ms": r64["launch_ms"],
+                                       "alg_bytes_per_launch": 256.0 * cells,
+                                       "kernel_source_sha": kernel_source_hash(r64["steps_per_launch"])}}),
+              flush=True)
+        return
     r32 = run_gpu(n, torch.complex64, K, W, args.tile_y, args.zchunk, args.kernel, keep=True)
     G = r32["steps_per_launch"]
     # accuracy over a fixed horizon, from the initial packet (untimed)

@@ -25,7 +25,7 @@ __device__ __forceinline__ Coef<R> coef2(const HalfArgs<R> &a, int arr, int q, s
 }
 
 // WHICH == 0: u from v; WHICH == 1: v from the new u.
-template <typename R, bool SITE, int WHICH>
+template <typename R, bool SITE, int WHICH, bool ZB>
 __global__ __launch_bounds__(256) void k2_half(HalfArgs<R> a) {
     using C = cx<R>;
     const int nbx = (a.nx + kTX - 1) / kTX;
@@ -40,9 +40,8 @@ __global__ __launch_bounds__(256) void k2_half(HalfArgs<R> a) {
     C *f[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) f[q] = (C *)a.f[q];
-    // zero values outside the lattice: a neighbour across an edge reads as zero
-    const bool zb = a.zbc != 0;
-    const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
+    // zero values outside the lattice (ZB): a neighbour across an edge reads as zero
+    const bool oxm = !ZB || i > 0, oxp = !ZB || i < a.nx - 1, oym = !ZB || j > 0, oyp = !ZB || j < a.ny - 1;
     if constexpr (WHICH == 0) {
         St2<C> s = stencil_u<C, R>(a.rx, a.ry, f[2][c], ld_or0(f[2], xm, oxm), ld_or0(f[2], yp, oyp), f[3][c],
                                    ld_or0(f[3], ym, oym), ld_or0(f[3], xp, oxp));
@@ -62,7 +61,7 @@ __device__ __forceinline__ double re_conj_mul(double2 x, double2 s) { return x.x
 __device__ __forceinline__ double abs2(double2 x) { return x.x * x.x + x.y * x.y; }
 
 // E_r = ||u||^2 + ||v||^2 - Re sum_u conj(u) S_u(v)  (= ... + Re sum_v conj(v) S_v(u))
-template <typename R>
+template <typename R, bool ZB>
 __global__ __launch_bounds__(kReduceThreads) void k2_norm(ReduceArgs<R> a) {
     using C = cx<R>;
     __shared__ double lds[kNormVals * 16];
@@ -81,8 +80,7 @@ __global__ __launch_bounds__(kReduceThreads) void k2_norm(ReduceArgs<R> a) {
         double2 x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = to_d(f[q][c]);
-        const bool zb = a.zbc != 0;
-        const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
+        const bool oxm = !ZB || i > 0, oxp = !ZB || i < a.nx - 1, oym = !ZB || j > 0, oyp = !ZB || j < a.ny - 1;
         St2<double2> su = stencil_u<double2, double>(rx, ry, x[2], to_d(ld_or0(f[2], xm, oxm)),
                                                       to_d(ld_or0(f[2], yp, oyp)), x[3], to_d(ld_or0(f[3], ym, oym)),
                                                       to_d(ld_or0(f[3], xp, oxp)));
@@ -163,18 +161,26 @@ hipError_t launch_half2(const HalfArgs<R> &a, int which, bool site, hipStream_t 
     const int64_t nblk = (int64_t)((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     dim3 g((unsigned)nblk), b(kTX * kTY);
-    if (which == 0) {
-        if (site) hipLaunchKernelGGL((k2_half<R, true, 0>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k2_half<R, false, 0>), g, b, 0, s, a);
-    } else {
-        if (site) hipLaunchKernelGGL((k2_half<R, true, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k2_half<R, false, 1>), g, b, 0, s, a);
+#define H2(ZB)                                                                          \
+    if (which == 0) {                                                                   \
+        if (site) hipLaunchKernelGGL((k2_half<R, true, 0, ZB>), g, b, 0, s, a);         \
+        else hipLaunchKernelGGL((k2_half<R, false, 0, ZB>), g, b, 0, s, a);             \
+    } else {                                                                            \
+        if (site) hipLaunchKernelGGL((k2_half<R, true, 1, ZB>), g, b, 0, s, a);         \
+        else hipLaunchKernelGGL((k2_half<R, false, 1, ZB>), g, b, 0, s, a);             \
     }
+    if (a.zbc) {
+        H2(true)
+    } else {
+        H2(false)
+    }
+#undef H2
     return hipGetLastError();
 }
 
 template <typename R> hipError_t launch_norm2(const ReduceArgs<R> &a, hipStream_t s) {
-    hipLaunchKernelGGL((k2_norm<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    if (a.zbc) hipLaunchKernelGGL((k2_norm<R, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    else hipLaunchKernelGGL((k2_norm<R, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -41,7 +41,9 @@ __device__ __forceinline__ Coef<R> coef_at(const HalfArgs<R> &a, int arr, int q,
 }
 
 // which == 0: A,B from C,D (Eqs. ss1, ss2); which == 1: C,D from A,B (ss3, ss4).
-template <typename R, bool SITE, int WHICH>
+// ZB: zero values outside the lattice (a compile-time choice, so the periodic
+// instantiation keeps plain loads).
+template <typename R, bool SITE, int WHICH, bool ZB>
 __global__ __launch_bounds__(256) void k3_half(HalfArgs<R> a) {
     using C = cx<R>;
     const int nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
@@ -67,9 +69,8 @@ __global__ __launch_bounds__(256) void k3_half(HalfArgs<R> a) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) f[q] = (C *)a.f[q];
     // zero values outside the lattice: a neighbour across a face reads as zero
-    const bool zb = a.zbc != 0;
-    const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
-    const bool ozm = !zb || k > 0, ozp = !zb || k < a.nz - 1;
+    const bool oxm = !ZB || i > 0, oxp = !ZB || i < a.nx - 1, oym = !ZB || j > 0, oyp = !ZB || j < a.ny - 1;
+    const bool ozm = !ZB || k > 0, ozp = !ZB || k < a.nz - 1;
     if constexpr (WHICH == 0) {
         St3<C> s = stencil_ab<C, R>(a.rx, a.ry, a.rz,
                                      f[4][c], ld_or0(f[4], zm, ozm), ld_or0(f[4], xp, oxp), ld_or0(f[4], yp, oyp),
@@ -130,7 +131,7 @@ __host__ __device__ inline MarchMap march_map(int nx, int ny, int nz) {
 // Per-workgroup partial sums of (E_r, E_r summed on the C,D sites, plain norm), FP64:
 //   E_r   = sum |X|^2 - Re sum_{A,B} conj(X) S_X(C,D)
 //   E_r'  = sum |X|^2 + Re sum_{C,D} conj(X) S_X(A,B)
-template <typename R>
+template <typename R, bool ZB>
 __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
     using C = cx<R>;
     __shared__ double lds[kNormVals * 16];
@@ -159,18 +160,17 @@ __global__ __launch_bounds__(kReduceThreads) void k3_norm(ReduceArgs<R> a) {
         const uint32_t ym = (uint32_t)wrap_dec(j, a.ny) * a.nx + i, yp = (uint32_t)wrap_inc(j, a.ny) * a.nx + i;
         // storage planes: periodic wrap, or in z-slab mode the interior offset by the halo
         auto zpl = [&](int pl) { return a.zh ? pl + a.zh : (pl < 0 ? pl + a.nz : pl >= a.nz ? pl - a.nz : pl); };
-        // zero values outside the lattice: neighbours across a face read as zero
-        const bool zb = a.zbc != 0;
-        const bool oxm = !zb || i > 0, oxp = !zb || i < a.nx - 1, oym = !zb || j > 0, oyp = !zb || j < a.ny - 1;
+        // zero values outside the lattice (ZB): neighbours across a face read as zero
+        const bool oxm = !ZB || i > 0, oxp = !ZB || i < a.nx - 1, oym = !ZB || j > 0, oyp = !ZB || j < a.ny - 1;
         const size_t Pb = (size_t)zpl(z0 - 1) * plane, P0 = (size_t)zpl(z0) * plane;
-        const bool ob = !zb || z0 > 0;
+        const bool ob = !ZB || z0 > 0;
         double2 cm0 = to_d(ld_or0(f[4], Pb + c, ob)), cm1 = to_d(ld_or0(f[5], Pb + c, ob));      // C(k-1)
         double2 bm0 = to_d(ld_or0(f[2], Pb + c, ob)), bm1 = to_d(ld_or0(f[3], Pb + c, ob));      // B(k-1)
         double2 a0 = to_d(f[0][P0 + c]), a1 = to_d(f[1][P0 + c]), d0 = to_d(f[6][P0 + c]), d1 = to_d(f[7][P0 + c]);
         for (int k = z0; k < z1; ++k) {
             const size_t Pk = (size_t)zpl(k) * plane;
             const size_t Pn = (size_t)zpl(k + 1) * plane;
-            const bool on = !zb || k + 1 < a.nz;
+            const bool on = !ZB || k + 1 < a.nz;
             const double2 an0 = to_d(ld_or0(f[0], Pn + c, on)), an1 = to_d(ld_or0(f[1], Pn + c, on));
             const double2 dn0 = to_d(ld_or0(f[6], Pn + c, on)), dn1 = to_d(ld_or0(f[7], Pn + c, on));
             const double2 b0 = to_d(f[2][Pk + c]), b1 = to_d(f[3][Pk + c]);
@@ -355,18 +355,26 @@ hipError_t launch_half3(const HalfArgs<R> &a, int which, bool site, hipStream_t 
     const int64_t nblk = (int64_t)((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY) * a.nz;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     dim3 g((unsigned)nblk), b(kTX * kTY);
-    if (which == 0) {
-        if (site) hipLaunchKernelGGL((k3_half<R, true, 0>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k3_half<R, false, 0>), g, b, 0, s, a);
-    } else {
-        if (site) hipLaunchKernelGGL((k3_half<R, true, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k3_half<R, false, 1>), g, b, 0, s, a);
+#define H3(ZB)                                                                          \
+    if (which == 0) {                                                                   \
+        if (site) hipLaunchKernelGGL((k3_half<R, true, 0, ZB>), g, b, 0, s, a);         \
+        else hipLaunchKernelGGL((k3_half<R, false, 0, ZB>), g, b, 0, s, a);             \
+    } else {                                                                            \
+        if (site) hipLaunchKernelGGL((k3_half<R, true, 1, ZB>), g, b, 0, s, a);         \
+        else hipLaunchKernelGGL((k3_half<R, false, 1, ZB>), g, b, 0, s, a);             \
     }
+    if (a.zbc) {
+        H3(true)
+    } else {
+        H3(false)
+    }
+#undef H3
     return hipGetLastError();
 }
 
 template <typename R> hipError_t launch_norm3(const ReduceArgs<R> &a, hipStream_t s) {
-    hipLaunchKernelGGL((k3_norm<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    if (a.zbc) hipLaunchKernelGGL((k3_norm<R, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
+    else hipLaunchKernelGGL((k3_norm<R, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
 }
 
