@@ -426,6 +426,19 @@ int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const 
                        double dt, unsigned flags);
 
 /*
+ * As dirac_batch_create with a time step per lattice: dt[b] (host array of
+ * count doubles, each finite and > 0) for lattice b, so r_x = r_y = dt[b] in
+ * its steps and its functional (Sect. 3); the stability bound of Sect. 3 is
+ * checked per lattice.  The per-site coefficient records bound with
+ * dirac_batch_bind must be built with each lattice's own dt (theta =
+ * (dt[b]/2)(+-m + V)).  dirac_batch_create(..., dt, ...) is this call with every
+ * dt[b] = dt.  No HIP call; DIRAC_E_ARG for a null or non-positive dt,
+ * DIRAC_E_UNSTABLE for a lattice above the bound without ALLOW_UNSTABLE.
+ */
+int dirac_batch_create_dt(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype,
+                          const double *dt, unsigned flags);
+
+/*
  * Bind the buffers of every lattice: state[4*b + a], partner[4*b + a] and
  * coef[4*b + a] for array a (u0 u1 v0 v1) of lattice b -- device pointers in
  * the single-lattice layout; coef holds the per-site coefficient record of
@@ -438,8 +451,10 @@ int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[],
 
 /*
  * Advance every lattice by n steps.  mode 0: one persistent launch for all n
- * steps with per-lattice step barriers; mode 1: one launch per step over all
- * lattices (both replayed from a captured HIP graph when use_graph != 0).
+ * steps with a per-lattice barrier between passes; mode 1: one launch per pass
+ * over all lattices (both replayed from a captured HIP graph when use_graph !=
+ * 0).  A pass advances one step or, with the tuned tile candidate's two-step
+ * march (even nx for complex64), two; an odd remainder takes one one-step pass.
  * After an odd n the partner buffers hold the state (dirac_current).  Every
  * per-lattice wait of mode 0 is bounded: if one times out (a grid that is not
  * co-resident) every workgroup leaves, the call returns DIRAC_E_HIP, and the

@@ -32,7 +32,7 @@ EXPORTS = (
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
     "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields", "dirac_set_mass",
     "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune", "dirac_coef_from_theta_host",
-    "dirac_norm_device_static",
+    "dirac_norm_device_static", "dirac_batch_create_dt",
 )
 
 
@@ -84,6 +84,8 @@ def lib():
         "dirac_set_potential_z": ([P, P, P, I64], I),
         "dirac_autotune": ([P, ctypes.c_char_p], I),
         "dirac_batch_create": ([ctypes.POINTER(P), I64, ctypes.POINTER(I64), ctypes.POINTER(I64), I, D, U], I),
+        "dirac_batch_create_dt": ([ctypes.POINTER(P), I64, ctypes.POINTER(I64), ctypes.POINTER(I64), I,
+                                   ctypes.POINTER(D), U], I),
         "dirac_batch_bind": ([P, PP, PP, PP, P, ctypes.c_size_t], I),
         "dirac_batch_run": ([P, I64, I, I, P], I),
         "dirac_batch_norms": ([P, ctypes.POINTER(D), P], I),

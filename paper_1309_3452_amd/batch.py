@@ -13,25 +13,34 @@ from .lattice import _dtype_code, _stream_handle
 class BatchedLattices:
     """lattices: sequence of dicts with nx, ny, m, v_site (4 real arrays or None),
     optionally w_site (4 arrays: Im V, complex64 batches) and state (4 complex
-    arrays of shape (ny, nx)).  dt common, unit spacing."""
+    arrays of shape (ny, nx)).  dt: one time step for all lattices, or a
+    sequence with one per lattice; unit spacing."""
 
     def __init__(self, lattices, dtype=torch.complex64, dt=0.5, device="cuda"):
         self.device = torch.device(device)
         self.dtype = dtype
         self.real_dtype = torch.float32 if dtype == torch.complex64 else torch.float64
-        self.dt = float(dt)
         self.count = len(lattices)
+        per = hasattr(dt, "__len__")
+        self.dts = [float(d) for d in dt] if per else [float(dt)] * self.count
+        if len(self.dts) != self.count:
+            raise ValueError("one dt per lattice")
+        self.dt = self.dts[0]
         nx = (ctypes.c_int64 * self.count)(*[int(L["nx"]) for L in lattices])
         ny = (ctypes.c_int64 * self.count)(*[int(L["ny"]) for L in lattices])
         self.shapes = [(int(L["ny"]), int(L["nx"])) for L in lattices]
         ctx = ctypes.c_void_p()
-        check(lib().dirac_batch_create(ctypes.byref(ctx), self.count, nx, ny, _dtype_code(dtype), self.dt, 0))
+        if per:
+            dts = (ctypes.c_double * self.count)(*self.dts)
+            check(lib().dirac_batch_create_dt(ctypes.byref(ctx), self.count, nx, ny, _dtype_code(dtype), dts, 0))
+        else:
+            check(lib().dirac_batch_create(ctypes.byref(ctx), self.count, nx, ny, _dtype_code(dtype), self.dt, 0))
         self._ctx = ctx
         self.bufs = [[], []]
         self.theta = []
         self._fields = []
         code = _dtype_code(dtype)
-        for L, shp in zip(lattices, self.shapes):
+        for L, shp, dtb in zip(lattices, self.shapes, self.dts):
             st = [torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous().clone() for a in L["state"]]
             self.bufs[0].append(st)
             self.bufs[1].append([torch.zeros(shp, dtype=dtype, device=self.device) for _ in range(4)])
@@ -48,7 +57,7 @@ class BatchedLattices:
                 w = None if ws is None else torch.as_tensor(ws[a]).to(device=self.device, dtype=torch.float64).contiguous()
                 coef = torch.empty(shp, dtype=torch.complex64 if dtype == torch.complex64 else torch.float64,
                                    device=self.device)
-                check(lib().dirac_coef_from_fields(ctypes.c_void_p(coef.data_ptr()), code, self.dt, sgn * m,
+                check(lib().dirac_coef_from_fields(ctypes.c_void_p(coef.data_ptr()), code, dtb, sgn * m,
                                                    ctypes.c_void_p(v.data_ptr()) if v is not None else None,
                                                    ctypes.c_void_p(w.data_ptr()) if w is not None else None,
                                                    coef.numel(), _stream_handle()))

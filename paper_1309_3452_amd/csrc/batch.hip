@@ -5,10 +5,12 @@
 // workgroup's fused (2+1)D pass over its strip and chunk: one step (march2.h)
 // or two (march2x2.h), per the tuning candidate.
 //  mode 1: one launch per pass over all items of all lattices;
-//  mode 0: one persistent launch for all steps, one-step passes.  Each
-//          workgroup takes items round-robin; before starting step s of an
-//          item of lattice b it waits until all items of b have finished step
-//          s-1 (a per-lattice counter, release/acquire at device scope).  The
+//  mode 0: one persistent launch for all steps, in passes of one step or (the
+//          two-step candidates) two steps, an odd remainder then taking one
+//          one-step pass after it.  Each workgroup takes items round-robin;
+//          before starting pass s of an item of lattice b it waits until all
+//          items of b have finished pass s-1 (a per-lattice counter,
+//          release/acquire at device scope).  The
 //          wait is bounded: a workgroup that waits too long raises a
 //          device-wide abort flag and every workgroup leaves, so the launch
 //          always ends; the host then reports the failure.  The grid is sized
@@ -38,6 +40,7 @@ namespace {
 struct BatchLat {
     void *st[2][4];    // [0]: bound state buffers, [1]: partner buffers
     void *th[4];
+    double r;          // r_x = r_y = dt of this lattice (unit spacing)
     int nx, ny;
     int item0, nitems;
 };
@@ -104,7 +107,7 @@ BLayout blayout(const dirac_ctx *c) {
 }
 
 template <typename R>
-__device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity, int ly, R rx, R ry) {
+__device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity, int ly) {
     FusedArgs<R> a;
     for (int q = 0; q < 4; ++q) {
         a.in[q] = L.st[parity][q];
@@ -117,8 +120,8 @@ __device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity,
         a.th[q] = nullptr;
     }
     a.tab = nullptr;
-    a.rx = rx;
-    a.ry = ry;
+    a.rx = (R)L.r;
+    a.ry = (R)L.r;
     a.rz = (R)0;
     a.nx = L.nx;
     a.ny = L.ny;
@@ -134,33 +137,72 @@ __device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity,
 }
 
 template <typename R, int TXB>
-__global__ __launch_bounds__(TXB) void kb_step(const BatchLat *lats, const BatchItem *items, int ly, int parity,
-                                               R rx, R ry) {
+__global__ __launch_bounds__(TXB) void kb_step(const BatchLat *lats, const BatchItem *items, int ly, int parity) {
     __shared__ cx<R> uu[2][2][TXB + 2];
     const BatchItem w = items[blockIdx.x];
     const BatchLat &L = lats[w.lat];
-    FusedArgs<R> a = item_args<R>(L, parity, ly, rx, ry);
+    FusedArgs<R> a = item_args<R>(L, parity, ly);
     march2<R, true, TXB>(a, w.tx, w.yc, uu);
 }
 
 // Two steps per launch: every item's strip and chunk by march2x2.
 template <typename R, int TW>
-__global__ __launch_bounds__(TW + 64) void kb_step2(const BatchLat *lats, const BatchItem *items, int ly, int parity,
-                                                    R rx, R ry) {
+__global__ __launch_bounds__(TW + 64) void kb_step2(const BatchLat *lats, const BatchItem *items, int ly, int parity) {
     constexpr int W = TW + 4;
     __shared__ __align__(16) cx<R> sOld[2 + 4 * W + 2];
     __shared__ __align__(16) cx<R> sStage[2 * W];
     __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
     const BatchItem w = items[blockIdx.x];
     const BatchLat &L = lats[w.lat];
-    FusedArgs<R> a = item_args<R>(L, parity, ly, rx, ry);
+    FusedArgs<R> a = item_args<R>(L, parity, ly);
     march2x2<R, true, TW>(a, nullptr, w.tx, w.yc, sOld, sStage, sLev);
 }
 
+// Per-lattice step barrier of the persistent launches: before pass s of an
+// item of lattice lat, wait until all nl items of lat have finished pass s-1
+// (done[lat] >= s * nl).  Thread 0 polls with device-scope acquire loads; the
+// wait is bounded: past kSpinLimit polls it raises the abort flag, and a
+// raised flag makes every waiting workgroup leave.  Returns true to leave.
+__device__ __forceinline__ bool wait_lattice(unsigned *done, int lat, unsigned need, unsigned *abort_flag,
+                                             int *s_abort) {
+    if (threadIdx.x == 0) {
+        int ab = 0;
+        long spins = 0;
+        for (;;) {
+            unsigned v = __hip_atomic_load(&done[lat], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= need) break;
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ab = 1;
+                break;
+            }
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_abort = ab;
+    }
+    __syncthreads();
+    if (*s_abort) return true;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return false;
+}
+// After an item's pass: every thread's stores are done (barrier), then thread 0
+// releases them and counts the item.
+__device__ __forceinline__ void notify_lattice(unsigned *done, int lat) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&done[lat], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One persistent launch of nsteps one-step passes (march2 per item).
 template <typename R, int TXB>
 __global__ __launch_bounds__(TXB) void kb_persist(const BatchLat *lats, const BatchItem *items, int nitems, int ly,
-                                                  int parity0, int nsteps, unsigned *done, unsigned *abort_flag,
-                                                  R rx, R ry) {
+                                                  int parity0, int nsteps, unsigned *done, unsigned *abort_flag) {
     __shared__ cx<R> uu[2][2][TXB + 2];
     __shared__ int s_abort;
     for (int s = 0; s < nsteps; ++s) {
@@ -168,38 +210,35 @@ __global__ __launch_bounds__(TXB) void kb_persist(const BatchLat *lats, const Ba
         for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
             const BatchItem w = items[it];
             const BatchLat &L = lats[w.lat];
-            if (s > 0) {
-                if (threadIdx.x == 0) {
-                    const unsigned need = (unsigned)s * (unsigned)L.nitems;
-                    int ab = 0;
-                    long spins = 0;
-                    for (;;) {
-                        unsigned v = __hip_atomic_load(&done[w.lat], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        if (v >= need) break;
-                        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            ab = 1;
-                            break;
-                        }
-                        if (++spins > kSpinLimit) {
-                            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ab = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                    s_abort = ab;
-                }
-                __syncthreads();
-                if (s_abort) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            FusedArgs<R> a = item_args<R>(L, par, ly, rx, ry);
+            if (s > 0 && wait_lattice(done, w.lat, (unsigned)s * (unsigned)L.nitems, abort_flag, &s_abort)) return;
+            FusedArgs<R> a = item_args<R>(L, par, ly);
             march2<R, true, TXB>(a, w.tx, w.yc, uu);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_fetch_add(&done[w.lat], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            notify_lattice(done, w.lat);
+        }
+    }
+}
+
+// One persistent launch of npass two-step passes (march2x2 per item): the same
+// barrier per pass, each pass advancing two steps (its ring is two cells, all
+// within the lattice the barrier covers).
+template <typename R, int TW>
+__global__ __launch_bounds__(TW + 64) void kb_persist2(const BatchLat *lats, const BatchItem *items, int nitems,
+                                                       int ly, int parity0, int npass, unsigned *done,
+                                                       unsigned *abort_flag) {
+    constexpr int W = TW + 4;
+    __shared__ __align__(16) cx<R> sOld[2 + 4 * W + 2];
+    __shared__ __align__(16) cx<R> sStage[2 * W];
+    __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
+    __shared__ int s_abort;
+    for (int s = 0; s < npass; ++s) {
+        const int par = (parity0 + s) & 1;
+        for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+            const BatchItem w = items[it];
+            const BatchLat &L = lats[w.lat];
+            if (s > 0 && wait_lattice(done, w.lat, (unsigned)s * (unsigned)L.nitems, abort_flag, &s_abort)) return;
+            FusedArgs<R> a = item_args<R>(L, par, ly);
+            march2x2<R, true, TW>(a, nullptr, w.tx, w.yc, sOld, sStage, sLev);
+            notify_lattice(done, w.lat);
         }
     }
 }
@@ -208,14 +247,22 @@ __global__ void kb_zero_u32(unsigned *p, int n) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0u;
 }
 
-template <typename R> int persistent_grid(int txb, int *grid) {
+// Workgroups of a persistent launch that are resident at once (the grid is
+// sized to that so every per-lattice wait can be met).
+template <typename R> int persistent_grid(int txb, bool two, int *grid) {
     int nb = 0, dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) {
-        if (txb == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 64>, 64, 0);
-        else if (txb == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 128>, 128, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 256>, 256, 0);
+        if (two) {
+            if (txb == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist2<R, 64>, 128, 0);
+            else if (txb == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist2<R, 128>, 192, 0);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist2<R, 256>, 320, 0);
+        } else {
+            if (txb == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 64>, 64, 0);
+            else if (txb == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 128>, 128, 0);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_persist<R, 256>, 256, 0);
+        }
     }
     if (e != hipSuccess) return -1;
     *grid = nb * ncu;
@@ -235,6 +282,7 @@ int upload_batch(dirac_ctx *c, int q, hipStream_t s, int64_t *nitems_out) {
             L.st[1][a] = c->bpartner[(size_t)b * 4 + a];
             L.th[a] = c->btheta[(size_t)b * 4 + a];
         }
+        L.r = c->bdt[(size_t)b];
         L.nx = (int)c->bnx[(size_t)b];
         L.ny = (int)c->bny[(size_t)b];
         L.item0 = (int)items.size();
@@ -272,24 +320,23 @@ template <typename R> int enqueue_run(dirac_ctx *c, int q, int64_t nitems, int64
     unsigned *done = (unsigned *)(base + Ly.done);
     Cand k = kCands[q];
     if (k.spp == 2 && !two_step_ok(c)) k.spp = 1;
-    const R r = (R)c->dt;
     *flips = 0;
     if (n == 0) return DIRAC_OK;
     const dim3 g((unsigned)nitems);
     int par = parity0;
     auto one_step = [&]() -> int {
-        if (k.txb == 64) hipLaunchKernelGGL((kb_step<R, 64>), g, dim3(64), 0, s, lats, items, k.ly, par, r, r);
-        else if (k.txb == 128) hipLaunchKernelGGL((kb_step<R, 128>), g, dim3(128), 0, s, lats, items, k.ly, par, r, r);
-        else hipLaunchKernelGGL((kb_step<R, 256>), g, dim3(256), 0, s, lats, items, k.ly, par, r, r);
+        if (k.txb == 64) hipLaunchKernelGGL((kb_step<R, 64>), g, dim3(64), 0, s, lats, items, k.ly, par);
+        else if (k.txb == 128) hipLaunchKernelGGL((kb_step<R, 128>), g, dim3(128), 0, s, lats, items, k.ly, par);
+        else hipLaunchKernelGGL((kb_step<R, 256>), g, dim3(256), 0, s, lats, items, k.ly, par);
         BCHK(c, hipGetLastError());
         par ^= 1;
         ++*flips;
         return DIRAC_OK;
     };
     auto two_steps = [&]() -> int {
-        if (k.txb == 64) hipLaunchKernelGGL((kb_step2<R, 64>), g, dim3(128), 0, s, lats, items, k.ly, par, r, r);
-        else if (k.txb == 128) hipLaunchKernelGGL((kb_step2<R, 128>), g, dim3(192), 0, s, lats, items, k.ly, par, r, r);
-        else hipLaunchKernelGGL((kb_step2<R, 256>), g, dim3(320), 0, s, lats, items, k.ly, par, r, r);
+        if (k.txb == 64) hipLaunchKernelGGL((kb_step2<R, 64>), g, dim3(128), 0, s, lats, items, k.ly, par);
+        else if (k.txb == 128) hipLaunchKernelGGL((kb_step2<R, 128>), g, dim3(192), 0, s, lats, items, k.ly, par);
+        else hipLaunchKernelGGL((kb_step2<R, 256>), g, dim3(320), 0, s, lats, items, k.ly, par);
         BCHK(c, hipGetLastError());
         par ^= 1;
         ++*flips;
@@ -308,28 +355,43 @@ template <typename R> int enqueue_run(dirac_ctx *c, int q, int64_t nitems, int64
         }
         return DIRAC_OK;
     }
-    // mode 0: one persistent launch of one-step passes over all n steps
+    // mode 0: one persistent launch; two-step passes for the two-step candidates
+    // (an odd remainder then takes one one-step pass after it), else one-step passes
     {
+        const bool two = k.spp == 2 && n >= 2;
+        const int64_t npass = two ? n / 2 : n;
         int grid = 0;
-        if (persistent_grid<R>(k.txb, &grid) || grid < 1)
+        if (persistent_grid<R>(k.txb, two, &grid) || grid < 1)
             return bfail(c, DIRAC_E_HIP, "could not size the persistent grid");
         if ((int64_t)grid > nitems) grid = (int)nitems;
         hipLaunchKernelGGL(kb_zero_u32, dim3(1), dim3(256), 0, s, done, (int)c->count + 1);
         BCHK(c, hipGetLastError());
         unsigned *abort_flag = done + c->count;
-        if (k.txb == 64)
-            hipLaunchKernelGGL((kb_persist<R, 64>), dim3(grid), dim3(64), 0, s, lats, items, (int)nitems, k.ly,
-                               par, (int)n, done, abort_flag, r, r);
-        else if (k.txb == 128)
-            hipLaunchKernelGGL((kb_persist<R, 128>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
-                               par, (int)n, done, abort_flag, r, r);
-        else
-            hipLaunchKernelGGL((kb_persist<R, 256>), dim3(grid), dim3(256), 0, s, lats, items, (int)nitems, k.ly,
-                               par, (int)n, done, abort_flag, r, r);
+        if (two) {
+            if (k.txb == 64)
+                hipLaunchKernelGGL((kb_persist2<R, 64>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
+                                   par, (int)npass, done, abort_flag);
+            else if (k.txb == 128)
+                hipLaunchKernelGGL((kb_persist2<R, 128>), dim3(grid), dim3(192), 0, s, lats, items, (int)nitems,
+                                   k.ly, par, (int)npass, done, abort_flag);
+            else
+                hipLaunchKernelGGL((kb_persist2<R, 256>), dim3(grid), dim3(320), 0, s, lats, items, (int)nitems,
+                                   k.ly, par, (int)npass, done, abort_flag);
+        } else {
+            if (k.txb == 64)
+                hipLaunchKernelGGL((kb_persist<R, 64>), dim3(grid), dim3(64), 0, s, lats, items, (int)nitems, k.ly,
+                                   par, (int)npass, done, abort_flag);
+            else if (k.txb == 128)
+                hipLaunchKernelGGL((kb_persist<R, 128>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
+                                   par, (int)npass, done, abort_flag);
+            else
+                hipLaunchKernelGGL((kb_persist<R, 256>), dim3(grid), dim3(256), 0, s, lats, items, (int)nitems, k.ly,
+                                   par, (int)npass, done, abort_flag);
+        }
         BCHK(c, hipGetLastError());
-        par ^= (int)(n & 1);
-        *flips += n;
-        rest = 0;
+        par ^= (int)(npass & 1);
+        *flips += npass;
+        rest = two ? (n & 1) : 0;
     }
     for (; rest > 0; --rest) {
         int rc = one_step();
@@ -443,18 +505,20 @@ void cache_store(const char *path, const std::string &key, const int v[2]) {
 
 extern "C" {
 
-int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype, double dt,
-                       unsigned flags) {
+int dirac_batch_create_dt(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype,
+                          const double *dt, unsigned flags) {
     if (!out) return DIRAC_E_ARG;
     *out = nullptr;
-    if (count < 1 || count > (1 << 20) || !nx || !ny) return DIRAC_E_ARG;
+    if (count < 1 || count > (1 << 20) || !nx || !ny || !dt) return DIRAC_E_ARG;
     if (dtype != DIRAC_C64 && dtype != DIRAC_C128) return DIRAC_E_ARG;
     if ((flags & ~DIRAC_ALLOW_UNSTABLE) != 0) return DIRAC_E_ARG;
-    if (!isfinite(dt) || dt <= 0.0) return DIRAC_E_ARG;
-    if (2.0 * dt * dt > 1.0 + 1e-12 && !(flags & DIRAC_ALLOW_UNSTABLE)) return DIRAC_E_UNSTABLE;
+    for (int64_t b = 0; b < count; ++b)
+        if (!isfinite(dt[b]) || dt[b] <= 0.0) return DIRAC_E_ARG;
     for (int64_t b = 0; b < count; ++b)
         if (nx[b] < 1 || ny[b] < 1 || nx[b] > (1 << 24) || ny[b] > (1 << 24) || nx[b] * ny[b] > (1LL << 31))
             return DIRAC_E_SHAPE;
+    for (int64_t b = 0; b < count; ++b)
+        if (2.0 * dt[b] * dt[b] > 1.0 + 1e-12 && !(flags & DIRAC_ALLOW_UNSTABLE)) return DIRAC_E_UNSTABLE;
     dirac_ctx *c = new (std::nothrow) dirac_ctx();
     if (!c) return DIRAC_E_ARG;
     c->is_batch = true;
@@ -462,14 +526,24 @@ int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const 
     c->count = count;
     c->bnx.assign(nx, nx + count);
     c->bny.assign(ny, ny + count);
+    c->bdt.assign(dt, dt + count);
     c->dtype = dtype;
-    c->dt = dt;
-    c->rx = c->ry = dt;
+    c->dt = dt[0];
+    c->rx = c->ry = dt[0];
     c->flags = flags;
     c->batch_scratch_need = blayout(c).total;
     c->tune_choice = -1;
     *out = c;
     return DIRAC_OK;
+}
+
+int dirac_batch_create(dirac_ctx **out, int64_t count, const int64_t *nx, const int64_t *ny, int dtype, double dt,
+                       unsigned flags) {
+    if (!out) return DIRAC_E_ARG;
+    *out = nullptr;
+    if (count < 1 || count > (1 << 20)) return DIRAC_E_ARG;
+    const std::vector<double> dts((size_t)count, dt);
+    return dirac_batch_create_dt(out, count, nx, ny, dtype, dts.data(), flags);
 }
 
 int dirac_batch_bind(dirac_ctx *c, void *const state[], void *const partner[], void *const theta[], void *scratch,
@@ -561,7 +635,7 @@ int dirac_batch_norms(dirac_ctx *c, double *out, void *stream) {
             ReduceArgs<float> a;
             memset(&a, 0, sizeof a);
             for (int q = 0; q < 4; ++q) a.f[q] = buf[(size_t)b * 4 + q];
-            a.rx = a.ry = (float)c->dt;
+            a.rx = a.ry = (float)c->bdt[(size_t)b];
             a.nx = (int)c->bnx[(size_t)b];
             a.ny = (int)c->bny[(size_t)b];
             a.nz = 1;
@@ -571,7 +645,7 @@ int dirac_batch_norms(dirac_ctx *c, double *out, void *stream) {
             ReduceArgs<double> a;
             memset(&a, 0, sizeof a);
             for (int q = 0; q < 4; ++q) a.f[q] = buf[(size_t)b * 4 + q];
-            a.rx = a.ry = c->dt;
+            a.rx = a.ry = c->bdt[(size_t)b];
             a.nx = (int)c->bnx[(size_t)b];
             a.ny = (int)c->bny[(size_t)b];
             a.nz = 1;

@@ -48,6 +48,7 @@ struct dirac_ctx {
     bool is_batch = false;
     int64_t count = 0;
     std::vector<int64_t> bnx, bny;
+    std::vector<double> bdt;      // per-lattice time step (r_x = r_y = dt, unit spacing)
     std::vector<void *> bstate, bpartner, btheta;
     size_t batch_scratch_need = 0;
     int tune_choice = -1;

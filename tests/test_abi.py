@@ -155,6 +155,17 @@ def test_batch_create_validation(L):
     bad = (ctypes.c_int64 * 2)(64, 0)
     assert L.dirac_batch_create(ctypes.byref(c), 2, nx, bad, 1, 0.6, 0) == -2
     assert L.dirac_batch_create(ctypes.byref(c), 0, nx, ny, 1, 0.6, 0) == -1
+    # a time step per lattice, each checked against the (2+1)D bound r <= 1/sqrt(2)
+    D2 = ctypes.c_double * 2
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, D2(0.6, 0.3), 0) == 0
+    L.dirac_destroy(c)
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, D2(0.6, 0.75), 0) == -3
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, D2(0.6, 0.75), 1) == 0
+    L.dirac_destroy(c)
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, D2(0.6, -0.1), 0) == -1
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, D2(float("nan"), 0.1), 0) == -1
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, ny, 2, None, 0) == -1
+    assert L.dirac_batch_create_dt(ctypes.byref(c), 2, nx, bad, 2, D2(0.6, 0.3), 0) == -2
 
 
 def test_status_strings(L):

@@ -448,6 +448,41 @@ def test_3d_site_fields_fp32_vs_oracle(P, kernel):
     assert rel_l2(np_state(lat.state()), f0_32) <= 60 * 1e-6
 
 
+@pytest.mark.parametrize("mode", [1, 0])
+def test_batched_per_lattice_dt_vs_oracle(P, mode):
+    """Lattices with their own time steps (dirac_batch_create_dt): each against
+    the oracle with its dt (FP64); the same dt everywhere gives the bits of the
+    single-dt batch."""
+    print("batched per-lattice dt mode=%d" % mode, flush=True)
+    sizes = [(64, 64), (96, 130), (17, 250), (1, 7)]
+    dts = [DT2, 0.5, 0.3, 0.61]
+    g = np.random.default_rng(87)
+    lats = []
+    for (nx, ny) in sizes:
+        lats.append(dict(nx=nx, ny=ny, m=float(g.uniform(0, 1)),
+                         v_site=[np.ascontiguousarray(0.5 * g.standard_normal((ny, nx))) for _ in range(4)],
+                         state=rand_state((ny, nx), 4, int(g.integers(1 << 30)))))
+    B = P.BatchedLattices(lats, dtype=torch.complex128, dt=dts)
+    steps = 24
+    B.run(steps, mode=mode, graph=False)
+    norms = B.norms()
+    for b, (L, dt) in enumerate(zip(lats, dts)):
+        ol = oracle.Lattice2(L["nx"], L["ny"], dt)
+        th = [np.ascontiguousarray(0.5 * dt * ((1.0 if a < 2 else -1.0) * L["m"] + L["v_site"][a])) for a in range(4)]
+        f = [a.copy() for a in L["state"]]
+        ol.step(f, th, steps)
+        assert rel_l2(np_state(B.state(b)), f) <= 1e-13, b
+        eo = ol.energy(f)
+        assert abs(norms[b][0] - eo[0]) <= 1e-12 * eo[2], b
+    one = P.BatchedLattices(lats, dtype=torch.complex128, dt=DT2)
+    same = P.BatchedLattices(lats, dtype=torch.complex128, dt=[DT2] * len(lats))
+    one.run(steps, mode=mode, graph=False)
+    same.run(steps, mode=mode, graph=False)
+    for b in range(len(lats)):
+        for x, y in zip(one.state(b), same.state(b)):
+            assert torch.equal(x, y), b
+
+
 def test_batched_fp32_site_vs_oracle(P):
     sizes = [(64, 64), (96, 130), (17, 250), (1, 7)]
     g = np.random.default_rng(83)
