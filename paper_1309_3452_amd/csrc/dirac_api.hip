@@ -125,12 +125,15 @@ size_t tab_bytes_of(const dirac_ctx *c) {
 
 // scratch layout
 // Per-workgroup partials of the in-step functional (two doubles each): every
-// z-march launch has at most ceil(nx/32) ceil(ny/4) tile columns (its tiles are
-// at least 32 x 4 cells) times at most nz chunks, so the area is sized for that
-// and an in-step reduction is never refused for lack of slots.  The standalone
-// reductions use kReduceBlocks x kObsVals doubles of the same area.
+// z-march launch has at most nz chunks per tile column, and its tiles are at
+// least 32 x 4 or 16 x 16 cells, so the area is sized for the larger tile
+// count of the two and an in-step reduction is never refused for lack of
+// slots.  The standalone reductions use kReduceBlocks x kObsVals doubles of the
+// same area.
 size_t step_partials(const dirac_ctx *c) {
-    return (size_t)((c->nx + 31) / 32) * (size_t)((c->ny + 3) / 4) * (size_t)c->nz;
+    const size_t t1 = (size_t)((c->nx + 31) / 32) * (size_t)((c->ny + 3) / 4);
+    const size_t t2 = (size_t)((c->nx + 15) / 16) * (size_t)((c->ny + 15) / 16);
+    return (t1 > t2 ? t1 : t2) * (size_t)c->nz;
 }
 size_t partial_doubles(const dirac_ctx *c) {
     const size_t red = (size_t)kReduceBlocks * kObsVals, stp = 2 * step_partials(c);

@@ -28,6 +28,7 @@
 // value, with the same operation order, so the result is bitwise that of two
 // one-step launches.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -158,8 +159,9 @@ template <> struct SiteRec<double> {
 };
 
 // SITE: 0 = V(z) tables, 1 = per-site records, 2 = per-site records with
-// theta -> -theta (the reversed step's sequence).
-template <typename R, int TW, int TY, int NT, bool NORM, int SITE>
+// theta -> -theta (the reversed step's sequence).  ROT: the old C,D planes in
+// three rotating LDS sets (below) instead of a staging area copied forward.
+template <typename R, int TW, int TY, int NT, bool NORM, int SITE, bool ROT>
 __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int W = TW + 4, H = TY + 4, RN = W * H;
@@ -168,17 +170,27 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     static_assert(RN <= NT - (NT == 1024 ? 192 : 0), "one region cell per thread");
     static_assert((W / CPL) <= 64, "one wave instruction per region row");
     static_assert(PAD % 2 == 0 && W % 2 == 0 && RN % 2 == 0, "16-byte alignment of the LDS rows");
-    // LDS (RN cells per array).  The asynchronous copies land only in sStage,
-    // which the stencils never read, so the compiler need not wait for them
-    // before the stencils' LDS reads; the staged planes move into sOld at the
-    // end of the iteration.
-    //   sOld:   0-1 C(p), 2-3 D(p), 4-5 D(p+1)
-    //   sStage: 0-1 C(p+1), 2-3 D(p+2) in flight
-    //   sLev:   0-3 level-1 A0 A1 B0 B1, 4-7 level-2 C0 C1 D0 D1, 8-11 level-3 A0 A1 B0 B1
-    __shared__ __align__(16) C sOld[PAD + 6 * RN + PAD];
-    __shared__ __align__(16) C sStage[4 * RN];
+    // LDS (RN cells per array), in one of two layouts.
+    // ROT == false: the asynchronous copies land only in a staging area that
+    // the stencils never read, so the compiler need not wait for them before
+    // the stencils' LDS reads; the staged planes move up at the end of the
+    // iteration, and the next plane's copies are issued after that.
+    //   sA: 0-1 C(p), 2-3 D(p), 4-5 D(p+1);  sB: 0-1 C(p+1), 2-3 D(p+2) in flight
+    // ROT == true: three sets sA, sB, sC, set q holding the C of plane q and
+    // the D of plane q+1 (0-1 C0 C1, 2-3 D0 D1), in rotation: plane p's set is
+    // number (p - ps) mod 3.  Iteration p reads C(p), D(p+1) from its set and
+    // D(p) from the previous one; after its first barrier the previous set is
+    // free and receives C(p+2), D(p+3), which then land during the whole next
+    // iteration (no copies between LDS arrays, no idle memory pipe while the
+    // level planes are written).  The loop is unrolled by three so that every
+    // access names its set statically: the compiler then sees that the copies
+    // in flight never alias what the stencils read.
+    //   sLev: 0-3 level-1 A0 A1 B0 B1, 4-7 level-2 C0 C1 D0 D1, 8-11 level-3 A0 A1 B0 B1
+    __shared__ __align__(16) C sA[ROT ? PAD + 4 * RN + PAD : PAD + 6 * RN + PAD];
+    __shared__ __align__(16) C sB[ROT ? PAD + 4 * RN + PAD : 4 * RN];
+    __shared__ __align__(16) C sC[ROT ? PAD + 4 * RN + PAD : 2];
     __shared__ __align__(16) C sLev[PAD + 12 * RN + PAD];
-    auto old_ = [&](int k) -> C * { return sOld + PAD + k * RN; };
+    auto old_ = [&](int k) -> C * { return sA + PAD + k * RN; };
     auto lev = [&](int k) -> C * { return sLev + PAD + k * RN; };
 
     int tx, ty, zc;
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     // the region cell of this thread: (xr, yr) relative to the tile origin
     int xr, yr;
     const int r = region_slot<TW, TY, NT>(t, xr, yr);
-    const int i = (yr + 2) * W + xr + 2;              // LDS index of the cell
+    int i = (yr + 2) * W + xr + 2;                    // LDS index of the cell
     const bool in1 = r >= 0 && xr < w + 2 && yr < h + 2;                       // levels 1 (ring 2)
     const bool in2 = in1 && xr >= -1 && xr <= w && yr >= -1 && yr <= h;        // levels 2, 3 (ring 1)
     const bool in4 = in1 && xr >= 0 && xr < w && yr >= 0 && yr < h;            // level 4 (tile)
@@ -255,7 +267,8 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
 #pragma unroll
     for (int j = 0; j < NJ; ++j) croff[j] = (uint32_t)wrapn(y0 + cy0 + WPA * j - 2, ny) * (uint32_t)nx * CS;
     // kc, kd: stored indices of the C and the D plane (C skipped if !with_c,
-    // either skipped if not stored); dst: this wave's LDS array
+    // either skipped if not stored); dst: this wave's LDS array (array ck of
+    // the destination)
     auto copy_rows = [&](int kc, int kd, bool with_c, C *dst) {
         if (ck < 2 ? (!with_c || !valid(kc)) : !valid(kd)) return;
         const char *base = (const char *)csrc + pofs(ck < 2 ? kc : kd);
@@ -285,39 +298,19 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
     // stored indices of planes p-3 .. p+2 along the march, advanced by one per plane
     int km3 = zh == 0 ? wrapn(ps - 3, nz) : ps - 3 + zh;
     int km2 = next_k(km3), km1 = next_k(km2), k0 = next_k(km1);
-    int kp1 = next_k(k0), kp2 = next_k(kp1);
-    {
-        // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
-        copy_rows(k0, k0, true, old_(ck));
-        copy_rows(k0, kp1, false, old_(2 + ck));
-        const size_t Pm = pofs(km1), P0 = pofs(k0);
-        if (in1 && valid(km1)) {
-            cprev[0] = ld_pl(in[4], Pm, go);
-            cprev[1] = ld_pl(in[5], Pm, go);
-        }
-        if (in1 && valid(k0)) {
+    int kp1 = next_k(k0), kp2 = next_k(kp1), kp3 = next_k(kp2);
+    // own-cell prefetch: the old A,B of plane p+1
+    auto load_ab_next = [&]() __attribute__((always_inline)) {
+        if (in1 && valid(kp1)) {
+            const size_t Pn = pofs(kp1);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pab[q] = ld_pl(in[q], P0, go);
+            for (int q = 0; q < 4; ++q) pabn[q] = ld_pl(in[q], Pn, go);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-
-    for (int p = ps; p <= pe; ++p) {
-        // keep the per-lane offset opaque, so that addresses stay a wave-uniform
-        // plane base plus a 32-bit lane offset instead of hoisted 64-bit pairs
-        asm volatile("" : "+v"(go));
-        const bool more = p < pe;
-        if (more) {
-            // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
-            copy_rows(kp1, kp2, true, sStage + ck * RN);
-            if (in1 && valid(kp1)) {
-                const size_t Pn = pofs(kp1);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) pabn[q] = ld_pl(in[q], Pn, go);
-            }
-        }
-
+    };
+    // the four levels of plane p; oc0, oc1: the LDS arrays of the old C of
+    // plane p, od0, od1 of its D, on0, on1 of the D of plane p+1
+    auto levels = [&](int p, const C *oc0, const C *oc1, const C *od0, const C *od1, const C *on0,
+                      const C *on1) __attribute__((always_inline)) {
         // level 1: A,B of plane p after step 1
         if (in1) {
             Coef<R> kq[4];
@@ -330,9 +323,7 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                 kq[0] = kq[1] = tcoef(tab, tstride, 0, tk(k0));
                 kq[2] = kq[3] = tcoef(tab, tstride, 1, tk(k0));
             }
-            const C *C0 = old_(0), *C1 = old_(1);
-            const C *D0 = old_(2), *D1 = old_(3);
-            const C *D0n = old_(4), *D1n = old_(5);
+            const C *C0 = oc0, *C1 = oc1, *D0 = od0, *D1 = od1, *D0n = on0, *D1n = on1;
             cown[0] = C0[i];
             cown[1] = C1[i];
             down[0] = D0[i];
@@ -470,12 +461,10 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                 }
             }
         }
-
-        // all LDS reads of this iteration done, all copies landed
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        // this iteration's level outputs become the LDS planes of the next one;
-        // the staged old planes move up
+    };
+    // after the first barrier: this iteration's level outputs become the LDS
+    // planes of the next one
+    auto store_levels = [&]() __attribute__((always_inline)) {
         if (in1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -484,15 +473,9 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
                 lev(8 + q)[i] = ab2[q];
             }
         }
-        if (more && r >= 0) {
-            old_(0)[i] = sStage[i];
-            old_(1)[i] = sStage[RN + i];
-            old_(2)[i] = old_(4)[i];
-            old_(3)[i] = old_(5)[i];
-            old_(4)[i] = sStage[2 * RN + i];
-            old_(5)[i] = sStage[3 * RN + i];
-        }
-        // advance the z windows
+    };
+    // advance the z windows
+    auto advance = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             ab1h2[q] = ab1h1[q];
@@ -505,13 +488,116 @@ __global__ __launch_bounds__(NT) void k3_fused2(FusedArgs<R> a, const R *__restr
         cprev[1] = cown[1];
         dprev[0] = down[0];
         dprev[1] = down[1];
-        km3 = km2;
-        km2 = km1;
-        km1 = k0;
-        k0 = kp1;
-        kp1 = kp2;
-        kp2 = next_k(kp2);
-        __syncthreads();
+    };
+
+    if constexpr (!ROT) {
+        {
+            // old C(ps), D(ps), D(ps+1) regions; C(ps-1) and A,B(ps) at the own cell
+            copy_rows(k0, k0, true, old_(ck));
+            copy_rows(k0, kp1, false, old_(2 + ck));
+            const size_t Pm = pofs(km1), P0 = pofs(k0);
+            if (in1 && valid(km1)) {
+                cprev[0] = ld_pl(in[4], Pm, go);
+                cprev[1] = ld_pl(in[5], Pm, go);
+            }
+            if (in1 && valid(k0)) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pab[q] = ld_pl(in[q], P0, go);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+
+        for (int p = ps; p <= pe; ++p) {
+            // keep the per-lane offset opaque, so that addresses stay a wave-uniform
+            // plane base plus a 32-bit lane offset instead of hoisted 64-bit pairs
+            asm volatile("" : "+v"(go));
+            const bool more = p < pe;
+            if (more) {
+                // prefetch: C(p+1), D(p+2) regions; A,B(p+1) at the own cell
+                copy_rows(kp1, kp2, true, sB + ck * RN);
+                load_ab_next();
+            }
+            levels(p, old_(0), old_(1), old_(2), old_(3), old_(4), old_(5));
+            // all LDS reads of this iteration done, all copies landed
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            store_levels();
+            // the staged old planes move up
+            if (more && r >= 0) {
+                old_(0)[i] = sB[i];
+                old_(1)[i] = sB[RN + i];
+                old_(2)[i] = old_(4)[i];
+                old_(3)[i] = old_(5)[i];
+                old_(4)[i] = sB[2 * RN + i];
+                old_(5)[i] = sB[3 * RN + i];
+            }
+            advance();
+            km3 = km2;
+            km2 = km1;
+            km1 = k0;
+            k0 = kp1;
+            kp1 = kp2;
+            kp2 = next_k(kp2);
+            __syncthreads();
+        }
+    } else {
+        {
+            // sets of planes ps-1 (its D only: D(ps)), ps and ps+1; C(ps-1) and
+            // A,B(ps) at the own cell
+            copy_rows(km1, k0, false, sC + PAD + ck * RN);
+            copy_rows(k0, kp1, true, sA + PAD + ck * RN);
+            copy_rows(kp1, kp2, true, sB + PAD + ck * RN);
+            const size_t Pm = pofs(km1), P0 = pofs(k0);
+            if (in1 && valid(km1)) {
+                cprev[0] = ld_pl(in[4], Pm, go);
+                cprev[1] = ld_pl(in[5], Pm, go);
+            }
+            if (in1 && valid(k0)) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pab[q] = ld_pl(in[q], P0, go);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        // plane p in set phase PH = (p - ps) mod 3
+        auto plane = [&](auto PH, int p) __attribute__((always_inline)) {
+            constexpr int ph = decltype(PH)::value;
+            C *const Sr = ph == 0 ? sA : ph == 1 ? sB : sC;      // C(p), D(p+1)
+            C *const Sp = ph == 0 ? sC : ph == 1 ? sA : sB;      // D(p); then receives C(p+2), D(p+3)
+            // the per-lane offsets opaque: addresses stay a wave-uniform base plus
+            // a lane offset, and LDS addresses are formed where they are used
+            // rather than hoisted out of the loop (one per set, phase and 64 KiB
+            // window would not fit the register file)
+            asm volatile("" : "+v"(go), "+v"(i));
+            if (p < pe) load_ab_next();
+            levels(p, Sr + PAD, Sr + PAD + RN, Sp + PAD + 2 * RN, Sp + PAD + 3 * RN, Sr + PAD + 2 * RN,
+                   Sr + PAD + 3 * RN);
+            // all LDS reads of this iteration done, the next set landed
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (p + 2 <= pe) copy_rows(kp2, kp3, true, Sp + PAD + ck * RN);
+            store_levels();
+            advance();
+            km3 = km2;
+            km2 = km1;
+            km1 = k0;
+            k0 = kp1;
+            kp1 = kp2;
+            kp2 = kp3;
+            kp3 = next_k(kp3);
+            // the level planes written: a barrier that waits only for this wave's
+            // LDS operations, so that the copies just issued stay in flight (the
+            // language's workgroup barrier waits for every memory access)
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        };
+        for (int p = ps; p <= pe; p += 3) {
+            plane(std::integral_constant<int, 0>(), p);
+            if (p + 1 > pe) break;
+            plane(std::integral_constant<int, 1>(), p + 1);
+            if (p + 2 > pe) break;
+            plane(std::integral_constant<int, 2>(), p + 2);
+        }
     }
 
     if constexpr (NORM) {
@@ -600,16 +686,11 @@ int pick_chunks(int64_t tiles, int nz, int fill) {
 
 bool fused3x2_supported(int nx, bool fp32, bool site) { (void)site; return !fp32 || nx % 2 == 0; }
 
-template <typename R>
-hipError_t launch_fused3x2(const FusedArgs<R> &a0, bool site, hipStream_t s, int *nblocks_out) {
-    FusedArgs<R> a = a0;
-    if ((!site && a.tab == nullptr) || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
-    if (site)
-        for (int q = 0; q < 8; ++q)
-            if (a.th[q] == nullptr) return hipErrorInvalidValue;
-    // plane byte offsets are 32-bit inside the kernel
-    if ((uint64_t)a.nx * (uint64_t)a.ny * sizeof(cx<R>) >= (1ull << 32)) return hipErrorInvalidValue;
-    constexpr int TW = sizeof(R) == 4 ? 64 : 32, TY = 8, NT = sizeof(R) == 4 ? 1024 : 512;
+namespace {
+// One launch of the two-step kernel with tile TW x TY and NT threads; px: the
+// XCD patch width of its tile order.
+template <typename R, int TW, int TY, int NT, bool ROT, bool SITE>
+hipError_t launch_x2(FusedArgs<R> a, int px, hipStream_t s, int *nblocks_out) {
     a.ntx = (a.nx + TW - 1) / TW;
     a.nty = (a.ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)a.ntx * a.nty;
@@ -618,27 +699,50 @@ hipError_t launch_fused3x2(const FusedArgs<R> &a0, bool site, hipStream_t s, int
         a.zchunk = (a.nz + nzc - 1) / nzc;
     }
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
-    // the ~32 workgroups one XCD runs at a time: with complex64 tiles (64 x 8
-    // cells) whole tile rows keep every x-neighbour resident and measured
-    // fastest; with complex128 tiles (32 x 8) whole tile rows form a band only
-    // 16 cells tall at 512^3, and patches of 4 x 8 tiles measured ~2% faster
-    a.px = sizeof(R) == 4 ? 0 : 4;
+    a.px = px;
     const int64_t nblk = tiles * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     if (nblocks_out) *nblocks_out = (int)nblk;
     const bool norm = a.npart != nullptr;
     if (norm && nblk > a.npart_cap) return hipErrorInvalidValue;
-    if (norm && site && a.rev) return hipErrorInvalidValue;     // no functional on reversed steps
+    if (norm && SITE && a.rev) return hipErrorInvalidValue;     // no functional on reversed steps
     const dim3 g((unsigned)nblk), b(NT);
-    if (site) {
-        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 1>), g, b, 0, s, a, a.tab);
-        else if (a.rev) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 2>), g, b, 0, s, a, a.tab);
-        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 1>), g, b, 0, s, a, a.tab);
+    if constexpr (SITE) {
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 1, ROT>), g, b, 0, s, a, a.tab);
+        else if (a.rev) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 2, ROT>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 1, ROT>), g, b, 0, s, a, a.tab);
     } else {
-        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 0>), g, b, 0, s, a, a.tab);
-        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 0>), g, b, 0, s, a, a.tab);
+        if (norm) hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, true, 0, ROT>), g, b, 0, s, a, a.tab);
+        else hipLaunchKernelGGL((k3_fused2<R, TW, TY, NT, false, 0, ROT>), g, b, 0, s, a, a.tab);
     }
     return hipGetLastError();
+}
+}  // namespace
+
+// Tiles: complex64 64 x 8 cells (1024 threads); complex128 32 x 8 with
+// per-site records, 16 x 16 with tables (512 threads).  The XCD patch: with complex64 tiles whole tile rows keep every x-neighbour
+// resident and measured fastest; with complex128 tiles whole tile rows form a
+// band only 16 cells tall at 512^3, and patches of 4 x 8 tiles measured ~2%
+// faster.  With V(z) tables the old C,D planes rotate through three LDS sets
+// (ROT), which leaves room for it only with complex128 tiles of 16 x 16 (at
+// 512^3: 7.44 against 7.73 ms per launch; complex64 3.70 against 4.29).  The
+// per-site kernels keep the staging layout: with rotation their register
+// footprint spills (complex64: 11.2 against 6.8 ms per launch).
+template <typename R>
+hipError_t launch_fused3x2(const FusedArgs<R> &a, bool site, hipStream_t s, int *nblocks_out) {
+    if ((!site && a.tab == nullptr) || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
+    if (site)
+        for (int q = 0; q < 8; ++q)
+            if (a.th[q] == nullptr) return hipErrorInvalidValue;
+    // plane byte offsets are 32-bit inside the kernel
+    if ((uint64_t)a.nx * (uint64_t)a.ny * sizeof(cx<R>) >= (1ull << 32)) return hipErrorInvalidValue;
+    if constexpr (sizeof(R) == 4) {
+        if (site) return launch_x2<R, 64, 8, 1024, false, true>(a, 0, s, nblocks_out);
+        return launch_x2<R, 64, 8, 1024, true, false>(a, 0, s, nblocks_out);
+    } else {
+        if (site) return launch_x2<R, 32, 8, 512, false, true>(a, 4, s, nblocks_out);
+        return launch_x2<R, 16, 16, 512, true, false>(a, 4, s, nblocks_out);
+    }
 }
 
 bool fused2x2_supported(int nx, bool fp32) { return !fp32 || nx % 2 == 0; }
