@@ -723,11 +723,13 @@ hipError_t launch_x2(FusedArgs<R> a, int px, hipStream_t s, int *nblocks_out) {
 // per-site records, 16 x 16 with tables (512 threads).  The XCD patch: with complex64 tiles whole tile rows keep every x-neighbour
 // resident and measured fastest; with complex128 tiles whole tile rows form a
 // band only 16 cells tall at 512^3, and patches of 4 x 8 tiles measured ~2%
-// faster.  With V(z) tables the old C,D planes rotate through three LDS sets
-// (ROT), which leaves room for it only with complex128 tiles of 16 x 16 (at
-// 512^3: 7.44 against 7.73 ms per launch; complex64 3.70 against 4.29).  The
-// per-site kernels keep the staging layout: with rotation their register
-// footprint spills (complex64: 11.2 against 6.8 ms per launch).
+// faster.  The old C,D planes rotate through three LDS sets (ROT) in the
+// complex64 kernels (at 512^3: 3.45 against 4.29 ms per launch with V(z)
+// tables, 6.23 against 6.84 with per-site records) and the complex128 ones
+// with tables, whose three sets fit only with tiles of 16 x 16 (7.65 against
+// 7.82 ms).  The complex128 per-site kernel, bound by the divisions that turn
+// its theta records into coefficients, keeps the staging layout and its 32 x 8
+// tiles (rotated with 16 x 16 tiles: 8.67 against 8.44 ms per step).
 template <typename R>
 hipError_t launch_fused3x2(const FusedArgs<R> &a, bool site, hipStream_t s, int *nblocks_out) {
     if ((!site && a.tab == nullptr) || (sizeof(R) == 4 && a.nx % 2 != 0)) return hipErrorInvalidValue;
@@ -737,7 +739,7 @@ hipError_t launch_fused3x2(const FusedArgs<R> &a, bool site, hipStream_t s, int 
     // plane byte offsets are 32-bit inside the kernel
     if ((uint64_t)a.nx * (uint64_t)a.ny * sizeof(cx<R>) >= (1ull << 32)) return hipErrorInvalidValue;
     if constexpr (sizeof(R) == 4) {
-        if (site) return launch_x2<R, 64, 8, 1024, false, true>(a, 0, s, nblocks_out);
+        if (site) return launch_x2<R, 64, 8, 1024, true, true>(a, 0, s, nblocks_out);
         return launch_x2<R, 64, 8, 1024, true, false>(a, 0, s, nblocks_out);
     } else {
         if (site) return launch_x2<R, 32, 8, 512, false, true>(a, 4, s, nblocks_out);
