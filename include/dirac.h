@@ -455,11 +455,15 @@ int dirac_batch_bind(dirac_ctx *ctx, void *const state[], void *const partner[],
  * over all lattices (both replayed from a captured HIP graph when use_graph !=
  * 0).  A pass advances one step or, with the tuned tile candidate's two-step
  * march (even nx for complex64), two; an odd remainder takes one one-step pass.
- * After an odd n the partner buffers hold the state (dirac_current).  Every
- * per-lattice wait of mode 0 is bounded: if one times out (a grid that is not
- * co-resident) every workgroup leaves, the call returns DIRAC_E_HIP, and the
- * lattices are left stepped unevenly across both buffer sets -- the bound
- * state is then invalid and must be reloaded.
+ * After an odd n the partner buffers hold the state (dirac_current).  Mode 0
+ * needs its whole grid resident at once: the first mode-0 call for a kernel in
+ * a process measures that grid by census-only launches (synchronous; no state
+ * touched), and every persistent launch opens with a census that leaves
+ * before any step if not all workgroups arrived.  Every per-lattice wait of
+ * mode 0 is bounded.  If a wait times out, or a launch's census closes, every
+ * workgroup leaves, the call returns DIRAC_E_HIP, and the lattices may be left
+ * stepped unevenly across both buffer sets -- the bound state is then invalid
+ * and must be reloaded.  Mode 0 calls synchronise with the stream.
  */
 int dirac_batch_run(dirac_ctx *ctx, int64_t n, int mode, int use_graph, void *stream);
 

@@ -13,8 +13,14 @@
 //          release/acquire at device scope).  The
 //          wait is bounded: a workgroup that waits too long raises a
 //          device-wide abort flag and every workgroup leaves, so the launch
-//          always ends; the host then reports the failure.  The grid is sized
-//          to the co-resident occupancy so all workgroups run at once.
+//          always ends; the host then reports the failure.  The waits need
+//          every workgroup of the grid resident at once, so the launch opens
+//          with a census (each workgroup counts in and waits, bounded, for the
+//          rest; if they do not all arrive the census closes and every
+//          workgroup leaves before touching any state), and the grid is the
+//          largest one a census-only launch found resident, measured once per
+//          process and kernel, starting from the occupancy calculator's bound
+//          (which the device did not always reach with 3- and 5-wave blocks).
 // Both modes can be captured once into a HIP graph and replayed.  The tile
 // shape (strip width x chunk height) is chosen by timing candidates
 // (dirac_batch_autotune), with an optional JSON cache keyed by device and
@@ -24,6 +30,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +67,11 @@ const Cand kCands[] = {{64, 16, 1},  {64, 32, 1},  {128, 16, 1}, {128, 32, 1}, {
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 constexpr int kDefaultCand = 10;
 constexpr long kSpinLimit = 1L << 22;
+// counter words of a persistent launch after the per-lattice ones: the abort
+// flag, the census word and the census's closing count
+constexpr int kDoneExtra = 3;
+constexpr unsigned kClosed = 1u << 30;     // census word: closed
+constexpr long kCensusSpin = 1L << 18;
 
 int bfail(dirac_ctx *c, int code, const char *fmt, ...) {
     if (c) {
@@ -100,7 +113,7 @@ BLayout blayout(const dirac_ctx *c) {
     L.lats = 0;
     L.items = al256((size_t)c->count * sizeof(BatchLat));
     L.done = L.items + al256((size_t)maxi * sizeof(BatchItem));
-    L.partial = L.done + al256((size_t)(c->count + 1) * sizeof(unsigned));
+    L.partial = L.done + al256((size_t)(c->count + kDoneExtra) * sizeof(unsigned));
     L.result = L.partial + al256((size_t)kReduceBlocks * kNormVals * sizeof(double));
     L.total = L.result + al256((size_t)c->count * kNormVals * sizeof(double));
     return L;
@@ -189,6 +202,44 @@ __device__ __forceinline__ bool wait_lattice(unsigned *done, int lat, unsigned n
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return false;
 }
+// Census at the start of a persistent launch: every workgroup adds one to the
+// census word and waits (bounded) until the whole grid has arrived, so no item
+// starts unless the grid is co-resident.  A workgroup whose wait runs out
+// closes the census by a compare-and-swap that sets kClosed on the count it
+// last saw (which fails if anyone arrived meanwhile: it then waits again) and
+// stores that count; a workgroup that sees the bit, on arrival or while
+// waiting, leaves.  Every wait ends: arrivals are at most the grid.  Returns
+// true to leave.
+__device__ __forceinline__ bool census(unsigned *word, unsigned *closed_at, int *s_abort) {
+    if (threadIdx.x == 0) {
+        int ab = 0;
+        const unsigned old = __hip_atomic_fetch_add(word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old & kClosed) ab = 1;
+        long spins = 0;
+        while (!ab) {
+            const unsigned v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v & kClosed) {
+                ab = 1;
+                break;
+            }
+            if (v >= gridDim.x) break;
+            if (++spins > kCensusSpin) {
+                unsigned expect = v;
+                if (__hip_atomic_compare_exchange_strong(word, &expect, v | kClosed, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(closed_at, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                    break;
+                }
+                spins = 0;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_abort = ab;
+    }
+    __syncthreads();
+    return *s_abort != 0;
+}
 // After an item's pass: every thread's stores are done (barrier), then thread 0
 // releases them and counts the item.
 __device__ __forceinline__ void notify_lattice(unsigned *done, int lat) {
@@ -205,6 +256,7 @@ __global__ __launch_bounds__(TXB) void kb_persist(const BatchLat *lats, const Ba
                                                   int parity0, int nsteps, unsigned *done, unsigned *abort_flag) {
     __shared__ cx<R> uu[2][2][TXB + 2];
     __shared__ int s_abort;
+    if (census(abort_flag + 1, abort_flag + 2, &s_abort)) return;
     for (int s = 0; s < nsteps; ++s) {
         const int par = (parity0 + s) & 1;
         for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -230,6 +282,7 @@ __global__ __launch_bounds__(TW + 64) void kb_persist2(const BatchLat *lats, con
     __shared__ __align__(16) cx<R> sStage[2 * W];
     __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
     __shared__ int s_abort;
+    if (census(abort_flag + 1, abort_flag + 2, &s_abort)) return;
     for (int s = 0; s < npass; ++s) {
         const int par = (parity0 + s) & 1;
         for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -247,8 +300,10 @@ __global__ void kb_zero_u32(unsigned *p, int n) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0u;
 }
 
-// Workgroups of a persistent launch that are resident at once (the grid is
-// sized to that so every per-lattice wait can be met).
+// Upper bound on the workgroups of a persistent launch resident at once, from
+// the occupancy calculator.  (Measured: with blocks of 3 or 5 waves the device
+// did not always hold that many, so the grid actually used comes from a census,
+// below.)
 template <typename R> int persistent_grid(int txb, bool two, int *grid) {
     int nb = 0, dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -269,6 +324,56 @@ template <typename R> int persistent_grid(int txb, bool two, int *grid) {
     return 0;
 }
 
+// One persistent launch of the kernel for (R, txb, two) on grid g; npass 0
+// runs the census only and touches no state.
+template <typename R>
+void launch_persist(int txb, bool two, int g, hipStream_t s, const BatchLat *lats, const BatchItem *items,
+                    int nitems, int ly, int par, int npass, unsigned *done, unsigned *abort_flag) {
+    if (two) {
+        if (txb == 64)
+            hipLaunchKernelGGL((kb_persist2<R, 64>), dim3(g), dim3(128), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+        else if (txb == 128)
+            hipLaunchKernelGGL((kb_persist2<R, 128>), dim3(g), dim3(192), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+        else
+            hipLaunchKernelGGL((kb_persist2<R, 256>), dim3(g), dim3(320), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+    } else {
+        if (txb == 64)
+            hipLaunchKernelGGL((kb_persist<R, 64>), dim3(g), dim3(64), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+        else if (txb == 128)
+            hipLaunchKernelGGL((kb_persist<R, 128>), dim3(g), dim3(128), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+        else
+            hipLaunchKernelGGL((kb_persist<R, 256>), dim3(g), dim3(256), 0, s, lats, items, nitems, ly, par, npass,
+                               done, abort_flag);
+    }
+}
+
+// Co-resident grid of each persistent kernel, measured once per process and
+// device: census-only launches (no state touched), starting from the
+// occupancy bound and retrying with the census's closing count until one
+// passes.
+std::mutex g_resident_mu;
+std::map<int, int> g_resident;
+int resident_key(bool fp32, int txb, bool two) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return (fp32 ? 1 : 0) | (two ? 2 : 0) | (txb << 2) | (dev << 12);
+}
+template <typename R> int resident_cached(int txb, bool two, int *grid) {
+    std::lock_guard<std::mutex> lk(g_resident_mu);
+    auto it = g_resident.find(resident_key(sizeof(R) == 4, txb, two));
+    if (it == g_resident.end()) return -1;
+    *grid = it->second;
+    return 0;
+}
+void resident_forget(bool fp32, int txb, bool two) {
+    std::lock_guard<std::mutex> lk(g_resident_mu);
+    g_resident.erase(resident_key(fp32, txb, two));
+}
 // Upload lattice descriptors and the item list of candidate q.
 int upload_batch(dirac_ctx *c, int q, hipStream_t s, int64_t *nitems_out) {
     const BLayout Ly = blayout(c);
@@ -302,6 +407,32 @@ int upload_batch(dirac_ctx *c, int q, hipStream_t s, int64_t *nitems_out) {
 
 // Two-step passes move whole rows in 16-byte units with a per-unit x wrap,
 // which needs an even row length for complex64: otherwise one-step passes.
+template <typename R> int calibrate_resident(dirac_ctx *c, int txb, bool two, hipStream_t s, int *grid) {
+    if (resident_cached<R>(txb, two, grid) == 0) return DIRAC_OK;
+    int g = 0;
+    if (persistent_grid<R>(txb, two, &g) || g < 1) return bfail(c, DIRAC_E_HIP, "could not size the persistent grid");
+    const BLayout Ly = blayout(c);
+    unsigned *done = (unsigned *)((char *)c->scratch + Ly.done);
+    unsigned *abort_flag = done + c->count;
+    for (int attempt = 0; attempt < 16 && g >= 1; ++attempt) {
+        hipLaunchKernelGGL(kb_zero_u32, dim3(1), dim3(256), 0, s, done, (int)c->count + kDoneExtra);
+        BCHK(c, hipGetLastError());
+        launch_persist<R>(txb, two, g, s, nullptr, nullptr, 0, 1, 0, 0, done, abort_flag);
+        BCHK(c, hipGetLastError());
+        unsigned w[2] = {0u, 0u};
+        BCHK(c, hipMemcpyAsync(w, abort_flag + 1, sizeof w, hipMemcpyDeviceToHost, s));
+        BCHK(c, hipStreamSynchronize(s));
+        if (!(w[0] & kClosed)) {
+            std::lock_guard<std::mutex> lk(g_resident_mu);
+            g_resident[resident_key(sizeof(R) == 4, txb, two)] = g;
+            *grid = g;
+            return DIRAC_OK;
+        }
+        g = (int)w[1] >= 1 && (int)w[1] < g ? (int)w[1] : g - 1;
+    }
+    return bfail(c, DIRAC_E_HIP, "persistent kernel: no co-resident grid found");
+}
+
 bool two_step_ok(const dirac_ctx *c) {
     if (c->dtype != DIRAC_C64) return true;
     for (int64_t b = 0; b < c->count; ++b)
@@ -360,34 +491,15 @@ template <typename R> int enqueue_run(dirac_ctx *c, int q, int64_t nitems, int64
     {
         const bool two = k.spp == 2 && n >= 2;
         const int64_t npass = two ? n / 2 : n;
+        // the co-resident grid (measured here unless the caller did so before a capture)
         int grid = 0;
-        if (persistent_grid<R>(k.txb, two, &grid) || grid < 1)
-            return bfail(c, DIRAC_E_HIP, "could not size the persistent grid");
+        int rc = calibrate_resident<R>(c, k.txb, two, s, &grid);
+        if (rc) return rc;
         if ((int64_t)grid > nitems) grid = (int)nitems;
-        hipLaunchKernelGGL(kb_zero_u32, dim3(1), dim3(256), 0, s, done, (int)c->count + 1);
+        hipLaunchKernelGGL(kb_zero_u32, dim3(1), dim3(256), 0, s, done, (int)c->count + kDoneExtra);
         BCHK(c, hipGetLastError());
         unsigned *abort_flag = done + c->count;
-        if (two) {
-            if (k.txb == 64)
-                hipLaunchKernelGGL((kb_persist2<R, 64>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
-                                   par, (int)npass, done, abort_flag);
-            else if (k.txb == 128)
-                hipLaunchKernelGGL((kb_persist2<R, 128>), dim3(grid), dim3(192), 0, s, lats, items, (int)nitems,
-                                   k.ly, par, (int)npass, done, abort_flag);
-            else
-                hipLaunchKernelGGL((kb_persist2<R, 256>), dim3(grid), dim3(320), 0, s, lats, items, (int)nitems,
-                                   k.ly, par, (int)npass, done, abort_flag);
-        } else {
-            if (k.txb == 64)
-                hipLaunchKernelGGL((kb_persist<R, 64>), dim3(grid), dim3(64), 0, s, lats, items, (int)nitems, k.ly,
-                                   par, (int)npass, done, abort_flag);
-            else if (k.txb == 128)
-                hipLaunchKernelGGL((kb_persist<R, 128>), dim3(grid), dim3(128), 0, s, lats, items, (int)nitems, k.ly,
-                                   par, (int)npass, done, abort_flag);
-            else
-                hipLaunchKernelGGL((kb_persist<R, 256>), dim3(grid), dim3(256), 0, s, lats, items, (int)nitems, k.ly,
-                                   par, (int)npass, done, abort_flag);
-        }
+        launch_persist<R>(k.txb, two, grid, s, lats, items, (int)nitems, k.ly, par, (int)npass, done, abort_flag);
         BCHK(c, hipGetLastError());
         par ^= (int)(npass & 1);
         *flips += npass;
@@ -405,13 +517,40 @@ int enqueue(dirac_ctx *c, int q, int64_t nitems, int64_t n, int mode, int parity
                                  : enqueue_run<double>(c, q, nitems, n, mode, parity0, s, flips);
 }
 
-int check_abort(dirac_ctx *c, hipStream_t s) {
+// The persistent kernel's strip width and steps per pass for candidate q and n steps.
+void mode0_config(const dirac_ctx *c, int q, int64_t n, int *txb, bool *two) {
+    Cand k = kCands[q];
+    if (k.spp == 2 && !two_step_ok(c)) k.spp = 1;
+    *txb = k.txb;
+    *two = k.spp == 2 && n >= 2;
+}
+
+// Measure the co-resident grid of mode 0's kernel before a stream capture
+// (the measurement synchronises, which a capture does not allow).
+int prepare_mode0(dirac_ctx *c, int q, int64_t n, hipStream_t s) {
+    int txb = 0, grid = 0;
+    bool two = false;
+    mode0_config(c, q, n, &txb, &two);
+    return c->dtype == DIRAC_C64 ? calibrate_resident<float>(c, txb, two, s, &grid)
+                                 : calibrate_resident<double>(c, txb, two, s, &grid);
+}
+
+int check_abort(dirac_ctx *c, int q, int64_t n, hipStream_t s) {
     const BLayout Ly = blayout(c);
-    unsigned flag = 0;
-    BCHK(c, hipMemcpyAsync(&flag, (char *)c->scratch + Ly.done + (size_t)c->count * sizeof(unsigned),
-                           sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    unsigned w[3] = {0u, 0u, 0u};       // abort flag, census word, census closing count
+    BCHK(c, hipMemcpyAsync(w, (char *)c->scratch + Ly.done + (size_t)c->count * sizeof(unsigned), sizeof w,
+                           hipMemcpyDeviceToHost, s));
     BCHK(c, hipStreamSynchronize(s));
-    if (flag) return bfail(c, DIRAC_E_HIP, "persistent kernel: a per-lattice barrier timed out (grid not co-resident?)");
+    if (w[1] & kClosed) {
+        // the device held fewer workgroups than measured: measure again next time
+        int txb = 0;
+        bool two = false;
+        mode0_config(c, q, n, &txb, &two);
+        resident_forget(c->dtype == DIRAC_C64, txb, two);
+        return bfail(c, DIRAC_E_HIP, "persistent kernel: only %u workgroups were resident (census closed); the state "
+                     "is invalid", w[2]);
+    }
+    if (w[0]) return bfail(c, DIRAC_E_HIP, "persistent kernel: a per-lattice barrier timed out; the state is invalid");
     return DIRAC_OK;
 }
 
@@ -583,7 +722,7 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
         rc = enqueue(c, q, nitems, n, mode, c->cur, s, &flips);
         if (rc) return rc;
         if (mode == 0) {
-            rc = check_abort(c, s);
+            rc = check_abort(c, q, n, s);
             if (rc) return rc;
         }
         if (flips & 1) c->cur = 1 - c->cur;
@@ -594,6 +733,10 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
             int64_t nitems = 0;
             int rc = upload_batch(c, q, c->graph_stream, &nitems);
             if (rc) return rc;
+            if (mode == 0) {
+                rc = prepare_mode0(c, q, n, c->graph_stream);
+                if (rc) return rc;
+            }
             BCHK(c, hipStreamBeginCapture(c->graph_stream, hipStreamCaptureModeRelaxed));
             int64_t flips = 0;
             rc = enqueue(c, q, nitems, n, mode, c->cur, c->graph_stream, &flips);
@@ -613,7 +756,7 @@ int dirac_batch_run(dirac_ctx *c, int64_t n, int mode, int use_graph, void *stre
         }
         BCHK(c, hipGraphLaunch(c->graph_exec, s));
         if (mode == 0) {
-            int rc = check_abort(c, s);
+            int rc = check_abort(c, q, n, s);
             if (rc) return rc;
         }
         if (c->graph_flips & 1) c->cur = 1 - c->cur;
@@ -691,7 +834,7 @@ int dirac_batch_autotune(dirac_ctx *c, const char *cache_path, int *chosen_out, 
                 if (flips & 1) c->cur = 1 - c->cur;
                 BCHK(c, hipEventRecord(e1, s));
                 BCHK(c, hipEventSynchronize(e1));
-                if (mode == 0 && check_abort(c, s)) {   // candidate unusable here
+                if (mode == 0 && check_abort(c, q, timed, s)) {   // candidate unusable here
                     aborted = true;
                     continue;
                 }

@@ -650,6 +650,34 @@ def test_batched_full_config_matches_solo(P):
     free()
 
 
+@pytest.mark.parametrize("cand", [9, 12])
+def test_persistent_many_items_per_workgroup(P, cand, tmp_path):
+    """The 64-lattice batch in the persistent mode with 32-row chunks: several items per
+    workgroup and pass, so every workgroup of the grid must be resident at once (these
+    tile shapes timed out before the grid came from a census).  Bitwise equal to one
+    launch per pass."""
+    import json
+    lats = workloads.config_batched(device="cuda")
+    print("persistent many items cand=%d" % cand, flush=True)
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    cells = sum(L["nx"] * L["ny"] for L in lats)
+    key = "%s/c64/n%d/cells%d/max%dx%d" % (arch, len(lats), cells, max(L["nx"] for L in lats),
+                                          max(L["ny"] for L in lats))
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({key: [cand, cand]}))
+    res = []
+    for mode in (1, 0):
+        B = P.BatchedLattices(lats, dtype=torch.complex64, dt=workloads.DT2)
+        assert B.autotune(str(cache)) == (cand, cand)
+        B.run(20, mode=mode)
+        res.append([t.clone() for b in range(B.count) for t in B.state(b)])
+        del B
+    for x, y in zip(*res):
+        assert torch.equal(x, y)
+    free()
+
+
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 def test_kernels_bitwise_equal(P, dtype):
     """Split and fused kernels, and fused tilings, give identical bits (the same

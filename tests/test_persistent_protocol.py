@@ -17,6 +17,14 @@ The model is sequentially consistent: it checks the protocol's logic
 which the kernels take as acquire on each poll and release after each
 item's stores at device scope.
 
+The kernels open with a census: each workgroup adds one to an arrival
+counter and waits (bounded) until the whole grid has arrived.  A workgroup
+whose census wait runs out closes the census by a compare-and-swap that sets a
+high bit on the count it last saw, which fails if anyone arrived meanwhile;
+late and waiting workgroups that see the bit leave.  No item starts unless the
+whole grid is resident, so a grid too large for the device fails with the
+state untouched, and the host retries with the closing count.
+
 Also modelled: a pass-major job queue (one claim counter over all
 (pass, item) jobs in order), a variant that was tried on the GPU and ran past
 its time limit.  In this model it is live for any residency: a claimed job
@@ -52,6 +60,8 @@ class Machine:
         self.ended = set()          # (pass, item) finished
         self.started = set()
         self.claim = 0
+        self.arrive = 0
+        self.closed_at = None
 
     # -- safety: an item of lattice b starts pass s only after every item of b ended pass s-1
     def check_start(self, s, it):
@@ -84,8 +94,37 @@ class Machine:
         self.done[self.items[it]] += 1        # release fetch_add
         yield
 
-    def round_robin(self, w):
+    CLOSED = 1 << 30
+
+    def census(self):
+        """Arrive, then wait until all G arrived; True to leave (census closed)."""
+        old = self.arrive                     # atomic fetch_add
+        self.arrive += 1
+        yield
+        if old & self.CLOSED:
+            return True
+        spins = 0
+        while True:
+            v = self.arrive                   # atomic load
+            if v & self.CLOSED:
+                return True
+            if v >= self.G:
+                return False
+            spins += 1
+            if spins > SPIN:
+                if self.arrive == v:          # compare-and-swap v -> v | CLOSED
+                    self.arrive = v | self.CLOSED
+                    self.closed_at = v
+                    return True
+                spins = 0                     # someone arrived: wait again
+            yield
+
+    def round_robin(self, w, with_census=False):
         """The kernels' protocol: pass-major, items w, w + G, ... each pass."""
+        if with_census:
+            left = yield from self.census()
+            if left:
+                return "closed"
         for s in range(self.npass):
             for it in range(w, len(self.items), self.G):
                 b = self.items[it]
@@ -199,3 +238,25 @@ def test_model_catches_a_missing_wait():
         for seed in range(50):
             m = Machine(items, npass=2, G=3, R=3, rng=random.Random(seed))
             m.run(no_wait)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_census_admits_only_a_co_resident_grid_and_the_retry_finishes(seed):
+    rng = random.Random(5000 + seed)
+    items = layout(rng, rng.randint(1, 6), 6)
+    R = rng.randint(1, len(items))            # workgroups the device holds at once
+    G = rng.randint(1, len(items))            # grid the host tries first
+    tries = 0
+    while True:
+        tries += 1
+        m = Machine(items, npass=3, G=G, R=R, rng=rng)
+        res = m.run(lambda w: m.round_robin(w, with_census=True))
+        if set(res.values()) == {"closed"}:
+            # closed: every workgroup left before any item started, the state is untouched
+            assert G > R and not m.started and m.closed_at is not None and m.closed_at <= R
+            G = m.closed_at                   # the host's retry
+            continue
+        assert set(res.values()) == {"done"} and not m.abort and G <= R
+        assert m.ended == {(s, it) for s in range(3) for it in range(len(items))}
+        break
+    assert tries <= 2
