@@ -62,10 +62,15 @@ def parse():
 
 
 def kernel_source_hash(steps_per_launch=1):
+    """Hash of the kernel sources' code (comments and blank space removed), so
+    that a profile stays attached to the code it measured."""
     h = hashlib.sha256()
     for f in ("fused2.hip" if steps_per_launch == 2 else "fused.hip", "stencil3.h", "device.h", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1309_3452_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1309_3452_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(line.strip() for line in text.split("\n") if line.strip()).encode())
     return h.hexdigest()[:16]
 
 

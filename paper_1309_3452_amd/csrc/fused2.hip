@@ -1,5 +1,5 @@
-// Two time steps per launch ((3+1)D, V(z) coefficient tables): temporal
-// blocking of the z-march, so each amplitude is read once and written once
+// Two time steps per launch ((3+1)D, V(z) coefficient tables or per-site
+// records): temporal blocking of the z-march, so each amplitude is read once and written once
 // per two steps of Sect. 2 (Eqs. ss1-ss4).
 //
 // A workgroup owns an x-y tile of TW x TY cells and a chunk [z0, z1) of
@@ -17,12 +17,14 @@
 // ping-pongs between two buffers exactly as in the one-step kernel.
 //
 // LDS holds, as (TW + 4) x (TY + 4) regions (cell (x, y) of the tile at
-// (y + 2)(TW + 4) + x + 2): the old C of plane p, D of planes p and p+1 (the
-// z-neighbour of B), the next C and D planes in flight, and one plane of each
+// (y + 2)(TW + 4) + x + 2): the old C of plane p and D of planes p and p+1
+// (the z-neighbour of B), the next planes in flight, and one plane of each
 // level's output.  The old C,D region rows (ring columns included) are copied
-// global -> LDS asynchronously, one plane ahead.  Each thread owns one region
-// cell of every level: its z-neighbours and previous values X- stay in
-// registers or are re-read from the level planes in LDS.
+// global -> LDS asynchronously, either through a staging area or into three
+// sets that rotate (the kernel's ROT layout, described at its LDS arrays).
+// Each thread owns one region cell of every level: its z-neighbours and
+// previous values X- stay in registers or are re-read from the level planes
+// in LDS.
 //
 // The same stencil and update helpers as the other kernels evaluate every
 // value, with the same operation order, so the result is bitwise that of two
