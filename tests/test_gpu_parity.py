@@ -1140,3 +1140,41 @@ def test_reverse_march_bitwise_equals_split(P, dtype, mode, shape, steps):
     for kernel, st in zip(("auto", "fused"), out[1:]):
         for a, b in zip(out[0], st):
             assert torch.equal(a, b), kernel
+
+
+# --------------------------------------------------------------------------
+# Two-step kernel on random small shapes and z-chunk lengths: every plane count
+# modulo the rotating layout's three LDS sets, chunks of one to a few planes,
+# rings that wrap onto tiny lattices, odd step counts.  Bits equal the split
+# kernels' (same expressions in the same order).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("site", [False, True])
+def test_two_step_random_shapes_bitwise_vs_split(P, dtype, site):
+    g = np.random.default_rng(4242 + (2 if site else 0) + (1 if dtype == torch.complex64 else 0))
+    for case in range(10):
+        nx = 2 * int(g.integers(1, 80))              # even: the complex64 two-step kernel needs it
+        ny = int(g.integers(1, 28))
+        nz = int(g.integers(1, 19))
+        zc = int(g.integers(0, 5))                   # 0: the launcher's choice
+        steps = int(g.integers(2, 8))
+        print("two-step random %s site=%s case %d: %dx%dx%d zchunk %d steps %d"
+              % (dtype, site, case, nx, ny, nz, zc, steps), flush=True)
+        f0 = rand_state((nz, ny, nx), 8, int(g.integers(1 << 30)))
+        V = [np.ascontiguousarray(0.4 * g.standard_normal((nz, ny, nx))) for _ in range(8)]
+        v_int, v_half = workloads.step_potential(nz, 1.2, nz / 2.0, 2.0)
+        outs = []
+        for kernel in ("split", "fused2"):
+            lat = P.Lattice3D(nx, ny, nz, dtype=dtype, dt=DT3)
+            lat.set_kernel(kernel, 0, zc)
+            if site:
+                lat.set_fields(0.3, [torch.from_numpy(v.astype(np.float32 if dtype == torch.complex64 else np.float64))
+                                     for v in V])
+            else:
+                lat.set_potential_z(0.5, v_int, v_half)
+            lat.load(f0)
+            lat.step(steps)
+            outs.append([t.clone() for t in lat.state()])
+            del lat
+        for x, y in zip(outs[0], outs[1]):
+            assert torch.equal(x, y), (nx, ny, nz, zc, steps)
