@@ -255,13 +255,23 @@ def copy_ceiling_gbs(nbytes=4 << 30, reps=5):
 
 
 def cpu_model():
+    """The host CPU's model name with its family, model and stepping numbers
+    (a virtualised host may report only a generic name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                k = k.strip()
+                if k in ("model name", "cpu family", "model", "stepping", "vendor_id") and k not in info:
+                    info[k] = v.strip()
+            elif info:
+                break
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    extra = ", ".join("%s %s" % (k, info[k]) for k in ("vendor_id", "cpu family", "model", "stepping") if k in info)
+    return "%s (%s)" % (name, extra) if extra else name
 
 
 def cpu_baseline(n=512, steps_all=3, steps_one=1):
