@@ -53,7 +53,7 @@ def parse():
                     help="auto = fused2 (two steps per launch) where it applies")
     ap.add_argument("--workload", default="step3d",
                     choices=["step3d", "batched2d", "adjoint3d", "plane2d", "links3d", "links2d", "klein2d",
-                             "slab3d", "site3d", "reverse3d"],
+                             "slab3d", "site3d", "reverse3d", "norm3d"],
                     help="step3d (default): the 512^3 FP32-vs-FP64 headline; the others print their own line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy (3 times): the reference dispatch "
@@ -472,6 +472,41 @@ def bench_links3d(n, steps, dtype_name):
             "E_r_rel_drift": abs(e1[0] - e0[0]) / abs(e0[0]), "plain_norm_rel_change": abs(e1[2] - e0[2]) / e0[2]}
 
 
+def bench_norm3d(n, reps, dtype_name):
+    """The conserved-functional reduction alone on the n^3 headline lattice (asynchronous
+    device-output calls back to back: the LDS-staged z-march plus the final sum of its
+    fixed 1024 partials)."""
+    import torch
+
+    import paper_1309_3452_amd as P
+    import workloads
+    dtype = torch.complex64 if dtype_name == "f32" else torch.complex128
+    cfg = workloads.config_step3d(n, dtype=dtype, device="cuda")
+    lat = P.Lattice3D(n, n, n, dtype=dtype, dt=cfg["dt"])
+    lat.set_potential_z(cfg["m"], cfg["v_int"], cfg["v_half"])
+    lat.load(cfg["state"])
+    del cfg["state"]
+    torch.cuda.empty_cache()
+    e = lat.norm()
+    lat.norm_device()
+    ms = _timed(lambda: lat.norm_device(), reps)
+    cells = n ** 3
+    b = 8 if dtype_name == "f32" else 16
+    alg = 8 * b * cells                    # each of the eight arrays read once
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {"metric": "cells/s of the conserved-functional reduction, (3+1)D %d^3" % n,
+            "value": cells / (ms * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype_name, "data": "synthetic",
+            "config": {"workload": "(3+1)D %d^3 periodic lattice of the headline workload, E_r in both "
+                                   "forms and the plain norm, FP64 sums" % n, "cells": cells},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k3_norm_lds + k_final_sum per call", "avg_call_ms": ms,
+                         "alg_bytes_per_call": alg},
+            "E_r": e[0], "E_r_cd_form": e[1], "plain_norm": e[2]}
+
+
 def bench_site3d(n, steps, dtype_name):
     """(3+1)D n^3 step with per-site coefficient records (a potential V(x, y, z)):
     the one-step and the two-step z-march kernels on the same lattice."""
@@ -833,6 +868,10 @@ def main():
         for d in ("f32", "f64"):
             print(json.dumps(bench_reverse3d(args.n, 100 if d == "f32" else 50, d)), flush=True)
             torch.cuda.empty_cache()
+        return
+    if args.workload == "norm3d":
+        for d in ("f32", "f64"):
+            print(json.dumps(bench_norm3d(args.n, 50, d)), flush=True)
         return
     if args.workload == "links3d":
         for d in ("f32", "f64"):

@@ -15,6 +15,7 @@
 //   S_D1 = -rz(B1 - B1[k-1]) + rx(A1 - A1[i-1]) + i ry(A0[j+1] - A0)
 #include "device.h"
 #include "internal.h"
+#include "norm3.h"
 #include "stencil3.h"
 
 namespace dirac {
@@ -373,6 +374,7 @@ hipError_t launch_half3(const HalfArgs<R> &a, int which, bool site, hipStream_t 
 }
 
 template <typename R> hipError_t launch_norm3(const ReduceArgs<R> &a, hipStream_t s) {
+    if (norm3_staged_supported(a.nx, sizeof(R) == 4)) return launch_norm3_staged<R>(a, s);
     if (a.zbc) hipLaunchKernelGGL((k3_norm<R, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     else hipLaunchKernelGGL((k3_norm<R, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();

@@ -1,0 +1,53 @@
+"""The (3+1)D conserved-functional reduction against the oracle's.
+
+The reduction stages each plane of the eight arrays in LDS per x-y tile
+(64 x 16 cells for complex64, 32 x 16 for complex128) and marches z in
+chunks; the shapes below give ragged tiles in x and y, several z chunks, more
+tiles than workgroups (several tiles per workgroup), lattices smaller than one
+tile whose ring wraps onto itself, and odd row lengths (complex64 then takes
+the unstaged reduction), with periodic and zero values outside the lattice.
+dt = 1/4 is exact in both precisions, so both sides evaluate the same
+functional of the same values and differ only in the order of the FP64 sums.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DT = 0.25
+
+SHAPES = [(70, 20, 22), (64, 16, 7), (130, 9, 5), (2, 1, 1), (4, 3, 2), (6, 40, 1), (33, 17, 3),
+          (2048, 544, 2)]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1309_3452_amd as P
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.lib()
+    return P
+
+
+@pytest.mark.parametrize("zero_bc", [False, True])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_3d_norm_vs_oracle(P, shape, dtype, zero_bc):
+    nx, ny, nz = shape
+    print("norm3 %s %s zero_bc=%s" % (shape, dtype, zero_bc), flush=True)
+    g = np.random.default_rng(7000 + nx + 3 * ny + 7 * nz)
+    f0 = [np.ascontiguousarray(g.standard_normal((nz, ny, nx)) + 1j * g.standard_normal((nz, ny, nx)))
+          for _ in range(8)]
+    lat = P.Lattice((nx, ny, nz), dtype=dtype, dt=DT, zero_bc=zero_bc)
+    lat.load(f0)
+    # the values the lattice holds (rounded to complex64 where it stores them so)
+    f = [t.detach().cpu().numpy().astype(np.complex128) for t in lat.state()]
+    e = lat.norm()
+    eo = oracle.Lattice3(nx, ny, nz, DT, zero_bc=zero_bc).energy(f)
+    assert abs(e[2] - eo[2]) <= 1e-13 * eo[2]
+    for q in range(2):
+        assert abs(e[q] - eo[q]) <= 1e-12 * eo[2], (q, e, eo)
+    # the two forms of the functional agree exactly in exact arithmetic
+    assert abs(e[0] - e[1]) <= 1e-12 * eo[2]
