@@ -89,6 +89,22 @@ def profiled_traffic(dtype_tag, n, steps_per_launch=1):
     return float(t.group(1))
 
 
+def profiled_valu_busy(n, steps_per_launch):
+    """Vector-ALU busy fraction of the FP32 march kernel from the committed SQ
+    counter summary, if it was taken on the current kernel source; else None."""
+    if steps_per_launch != 2:
+        return None
+    path = os.path.join(ROOT, "profiles", "fused3dx2_fp32_%d_sq.md" % n)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
+    v = re.search(r"valu_busy:\s*([0-9.eE+-]+)", text)
+    if not m or not v or m.group(1) != kernel_source_hash(2):
+        return None
+    return float(v.group(1))
+
+
 def run_gpu(n, dtype, steps, warmup, tile_y, zchunk, kernel, keep=False):
     import torch
 
@@ -967,6 +983,9 @@ def main():
                      "effective_GBs_per_step_model": 128.0 * cells * G / launch_s / 1e9,
                      # useful FP32 arithmetic (32 FLOP per amplitude update, 8 updates per cell-step)
                      # against the non-packed FP32 vector peak
+                     # instruction view from the committed SQ counters: the share of time the
+                     # vector ALUs issue (ring recomputation and bookkeeping included)
+                     "valu_busy": profiled_valu_busy(n, G),
                      "alu": {"flop_per_cell_step": ALU_FLOP_PER_CELL_STEP,
                              "achieved_TFLOPs": ALU_FLOP_PER_CELL_STEP * value / 1e12,
                              "peak_TFLOPs": FP32_NONPACKED_TFLOPS,
