@@ -491,6 +491,18 @@ int dirac_batch_autotune(dirac_ctx *ctx, const char *cache_path, int *chosen_out
  * single-lattice context (its knobs are dirac_set_kernel's). */
 int dirac_autotune(dirac_ctx *ctx, const char *cache_path);
 
+/*
+ * Measurement utility, not a step of the method: a plain streaming copy of
+ * `bytes` bytes from src to dst (device pointers, 8-byte aligned, not
+ * overlapping; bytes a multiple of 8), each byte read once and written once.
+ * It is the reference dispatch for the device's copy bandwidth and for scaling
+ * the memory byte counters next to the library's kernels.  Context-free,
+ * asynchronous on stream, allocates nothing.  DIRAC_E_ARG for null pointers, a
+ * negative or unaligned size or address, or overlapping ranges; DIRAC_E_HIP on
+ * launch failure.
+ */
+int dirac_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

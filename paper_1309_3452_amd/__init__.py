@@ -7,7 +7,7 @@ into it.  Importing is cheap; the library is loaded on first use and its
 absence raises ImportError.
 """
 from ._abi import DiracError, lib  # noqa: F401
-from .lattice import Lattice, Lattice2D, Lattice3D  # noqa: F401
+from .lattice import Lattice, Lattice2D, Lattice3D, stream_copy  # noqa: F401
 from .batch import BatchedLattices  # noqa: F401
 from .autograd import DiracLoss, potential_gradient  # noqa: F401
 from .slabs import SlabDecomposition  # noqa: F401
@@ -16,4 +16,4 @@ from .watch import DriftError, run_watched  # noqa: F401
 
 __all__ = ["Lattice", "Lattice2D", "Lattice3D", "BatchedLattices", "DiracLoss", "potential_gradient",
            "SlabDecomposition", "DiracError", "lib", "save_checkpoint", "load_checkpoint", "DriftError",
-           "run_watched"]
+           "run_watched", "stream_copy"]

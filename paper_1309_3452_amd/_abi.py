@@ -32,7 +32,7 @@ EXPORTS = (
     "dirac_batch_norms", "dirac_batch_autotune", "dirac_coef_from_theta", "dirac_set_potential_im_z",
     "dirac_coef_from_theta_c", "dirac_set_links", "dirac_coef_from_fields", "dirac_set_mass",
     "dirac_set_potential_z", "dirac_adjoint", "dirac_autotune", "dirac_coef_from_theta_host",
-    "dirac_norm_device_static", "dirac_batch_create_dt",
+    "dirac_norm_device_static", "dirac_batch_create_dt", "dirac_stream_copy",
 )
 
 
@@ -91,6 +91,7 @@ def lib():
         "dirac_batch_norms": ([P, ctypes.POINTER(D), P], I),
         "dirac_batch_autotune": ([P, ctypes.c_char_p, ctypes.POINTER(I), P], I),
         "dirac_coef_from_theta": ([P, P, I64, P], I),
+        "dirac_stream_copy": ([P, P, I64, P], I),
         "dirac_coef_from_theta_host": ([P, P, I64], I),
         "dirac_coef_from_theta_c": ([P, P, P, I64, P], I),
         "dirac_set_potential_im_z": ([P, P, P, I64], I),

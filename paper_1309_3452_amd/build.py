@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdirac.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["dirac_api.hip", "kernels3d.hip", "kernels2d.hip", "fused.hip", "fused2.hip", "adjoint.hip", "batch.hip", "gauge.hip",
-           "noalloc.hip", "norm3.hip"]
+           "noalloc.hip", "norm3.hip", "probe.hip"]
 ARCH = os.environ.get("DIRAC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -292,6 +292,20 @@ class Lattice:
         return dvi, dvh
 
 
+def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> torch.Tensor:
+    """dst <- src by the library's plain streaming copy (dirac_stream_copy): the
+    reference for the device's copy bandwidth.  Contiguous device tensors of the
+    same byte size (a multiple of 8), asynchronous on the current stream."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("stream_copy takes contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: tensors of different byte sizes")
+    check(lib().dirac_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                  _stream_handle()))
+    return dst
+
+
 def Lattice3D(nx, ny, nz, **kw):
     return Lattice((nx, ny, nz), **kw)
 

@@ -220,3 +220,15 @@ def test_zero_bc_flag_validation(L):
     assert L.dirac_bind_scratch(c, ctypes.c_void_p(256), nb.value) == 0
     assert L.dirac_adjoint_vz(c, 1, fake, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -6
     L.dirac_destroy(c)
+
+
+def test_stream_copy_validation(L):
+    """dirac_stream_copy rejects bad arguments before any HIP call."""
+    P = ctypes.c_void_p
+    assert L.dirac_stream_copy(None, P(4096), 64, None) == -1
+    assert L.dirac_stream_copy(P(4096), None, 64, None) == -1
+    assert L.dirac_stream_copy(P(4096), P(8192), -8, None) == -1
+    assert L.dirac_stream_copy(P(4096), P(8192), 12, None) == -1          # not a multiple of 8
+    assert L.dirac_stream_copy(P(4100), P(8192), 64, None) == -1          # unaligned
+    assert L.dirac_stream_copy(P(4096), P(4096 + 32), 64, None) == -1     # overlapping
+    assert L.dirac_stream_copy(P(4096), P(8192), 0, None) == 0            # nothing to copy
