@@ -64,17 +64,17 @@ __device__ __forceinline__ float2 update(float2 xm, float2 s, const Coef<float> 
     return mk2(xm.x - re, xm.y - im);
 }
 
-// Cayley coefficients from a per-site theta.  FP64: the IEEE formula
-//   d = 1 + th^2, alpha = ((1 - th^2)/d, -(2 th)/d), beta = (1/d, -th/d)
-// with every operation rounded separately (contraction off, IEEE division),
-// so the coefficients are the same bits on any IEEE host.
+// Cayley coefficients from a per-site theta.  FP64: with one IEEE division,
+//   r = 1/(1 + th^2), alpha = ((1 - th^2) r, -(2 th) r), beta = (r, -th r)
+// with every operation rounded separately (contraction off), so the
+// coefficients are the same bits on any IEEE host.
 __device__ __forceinline__ Coef<double> coef_theta(double th) {
 #pragma clang fp contract(off)
     double t2 = th * th;
-    double d = 1.0 + t2;
+    double r = 1.0 / (1.0 + t2);
     Coef<double> k;
-    k.c1 = mk2((1.0 - t2) / d, -((2.0 * th) / d));
-    k.c2 = mk2(1.0 / d, -(th / d));
+    k.c1 = mk2((1.0 - t2) * r, -((2.0 * th) * r));
+    k.c2 = mk2(r, -(th * r));
     return k;
 }
 // FP32: evaluated in FP64 and rounded; gamma_re is re-derived from the rounded
