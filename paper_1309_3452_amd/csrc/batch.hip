@@ -173,17 +173,23 @@ __global__ __launch_bounds__(TW + 64) void kb_step2(const BatchLat *lats, const 
 
 // Per-lattice step barrier of the persistent launches: before pass s of an
 // item of lattice lat, wait until all nl items of lat have finished pass s-1
-// (done[lat] >= s * nl).  Thread 0 polls with device-scope acquire loads; the
-// wait is bounded: past kSpinLimit polls it raises the abort flag, and a
-// raised flag makes every waiting workgroup leave.  Returns true to leave.
+// (done[lat] >= s * nl).  Thread 0 polls with device-scope relaxed loads and,
+// once the count is reached, makes one device-scope acquire fence before the
+// workgroup barrier (an acquire on every poll would invalidate the caches on
+// every spin); the wait is bounded: past kSpinLimit polls it raises the abort
+// flag, and a raised flag makes every waiting workgroup leave.  Returns true
+// to leave.
 __device__ __forceinline__ bool wait_lattice(unsigned *done, int lat, unsigned need, unsigned *abort_flag,
                                              int *s_abort) {
     if (threadIdx.x == 0) {
         int ab = 0;
         long spins = 0;
         for (;;) {
-            unsigned v = __hip_atomic_load(&done[lat], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            if (v >= need) break;
+            unsigned v = __hip_atomic_load(&done[lat], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= need) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                break;
+            }
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ab = 1;
                 break;
@@ -198,9 +204,7 @@ __device__ __forceinline__ bool wait_lattice(unsigned *done, int lat, unsigned n
         *s_abort = ab;
     }
     __syncthreads();
-    if (*s_abort) return true;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return false;
+    return *s_abort != 0;
 }
 // Census at the start of a persistent launch: every workgroup adds one to the
 // census word and waits (bounded) until the whole grid has arrived, so no item
@@ -241,13 +245,10 @@ __device__ __forceinline__ bool census(unsigned *word, unsigned *closed_at, int 
     return *s_abort != 0;
 }
 // After an item's pass: every thread's stores are done (barrier), then thread 0
-// releases them and counts the item.
+// counts the item with a device-scope release, which publishes them.
 __device__ __forceinline__ void notify_lattice(unsigned *done, int lat) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&done[lat], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[lat], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One persistent launch of nsteps one-step passes (march2 per item).
