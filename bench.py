@@ -515,6 +515,9 @@ def bench_norm3d(n, reps, dtype_name):
     e = lat.norm()
     lat.norm_device()
     ms = _timed(lambda: lat.norm_device(), reps)
+    # the observables reduction of the same state (synchronous calls: host copy-out included)
+    obs = lat.observables(n / 2.0)
+    obs_ms = _timed(lambda: lat.observables(n / 2.0), reps)
     cells = n ** 3
     b = 8 if dtype_name == "f32" else 16
     alg = 8 * b * cells                    # each of the eight arrays read once
@@ -529,7 +532,9 @@ def bench_norm3d(n, reps, dtype_name):
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k3_norm_lds + k_final_sum per call", "avg_call_ms": ms,
                          "alg_bytes_per_call": alg},
-            "E_r": e[0], "E_r_cd_form": e[1], "plain_norm": e[2]}
+            "E_r": e[0], "E_r_cd_form": e[1], "plain_norm": e[2],
+            "observables": {"ms_per_call": obs_ms, "GBs_read_once": alg / (obs_ms * 1e-3) / 1e9,
+                            "kernel": "k3_obs (synchronous call)", "P_z_ge_half": obs[0], "plain_norm": obs[4]}}
 
 
 def bench_site3d(n, steps, dtype_name):

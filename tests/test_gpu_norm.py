@@ -51,3 +51,26 @@ def test_3d_norm_vs_oracle(P, shape, dtype, zero_bc):
         assert abs(e[q] - eo[q]) <= 1e-12 * eo[2], (q, e, eo)
     # the two forms of the functional agree exactly in exact arithmetic
     assert abs(e[0] - e[1]) <= 1e-12 * eo[2]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_3d_observables_vs_oracle(P, shape, dtype):
+    """The observables reduction (region probability beyond z0, first moments,
+    plain norm, per-component norms) against the oracle's on the same values;
+    complex64 lattices with even rows read two cells per 16-byte load, odd rows
+    one cell per load."""
+    nx, ny, nz = shape
+    print("obs3 %s %s" % (shape, dtype), flush=True)
+    g = np.random.default_rng(7100 + nx + 3 * ny + 7 * nz)
+    f0 = [np.ascontiguousarray(g.standard_normal((nz, ny, nx)) + 1j * g.standard_normal((nz, ny, nx)))
+          for _ in range(8)]
+    lat = P.Lattice((nx, ny, nz), dtype=dtype, dt=DT)
+    lat.load(f0)
+    f = [t.detach().cpu().numpy().astype(np.complex128) for t in lat.state()]
+    ol = oracle.Lattice3(nx, ny, nz, DT)
+    for z0 in (nz / 2.0, nz / 2.0 + 0.25, 0.0):
+        ob = lat.observables(z0)
+        oo = ol.observe(f, z0)
+        for q in range(9):
+            assert abs(ob[q] - oo[q]) <= 1e-12 * max(abs(oo[q]), oo[4]), (z0, q, ob[q], oo[q])
