@@ -201,17 +201,31 @@ __global__ __launch_bounds__(256) void k3_half_links(HalfArgs<R> a, LinkPtrs L) 
 template <int TW, int TY> constexpr int fl_threads() { return TW * TY + 64 * ((2 * TW + 2 * TY + 63) / 64); }
 
 template <typename R, bool SITE, int TW, int TY, int WPE>
-__global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(FusedArgs<R> a, LinkPtrs L) {
+__global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(FusedArgs<R> a, LinkPtrs L,
+                                                                             const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int LW = TW + 2, LN = LW * (TY + 2);
     __shared__ C sE[2][8][LN];      // exports of A,B(p), slot p & 1
 
     int lb = blockIdx.x;
     if ((gridDim.x & 7) == 0) lb = (lb & 7) * (gridDim.x >> 3) + (lb >> 3);   // one run of tiles per XCD
-    const int tx = lb % a.ntx;
-    lb /= a.ntx;
-    const int ty = lb % a.nty;
-    const int zc = lb / a.nty;
+    // the ~32 tiles an XCD runs at once: whole tile rows (px = 0) or a patch of
+    // px x 32/px tiles, whose halo rows and columns stay in that XCD's L2
+    int tx, ty, zc;
+    const int PX = a.px > 0 ? a.px : 1, PY = a.px > 0 ? 32 / a.px : 1;
+    if (a.px > 0 && a.ntx % PX == 0 && a.nty % PY == 0) {
+        const int within = lb % (PX * PY), patch = lb / (PX * PY);
+        const int npx = a.ntx / PX, npy = a.nty / PY;
+        tx = (patch % npx) * PX + within % PX;
+        const int rest = patch / npx;
+        ty = (rest % npy) * PY + within / PX;
+        zc = rest / npy;
+    } else {
+        tx = lb % a.ntx;
+        lb /= a.ntx;
+        ty = lb % a.nty;
+        zc = lb / a.nty;
+    }
     const int x0 = tx * TW, y0 = ty * TY;
     const int w = min(TW, a.nx - x0), h = min(TY, a.ny - y0);
     const int z0 = zc * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
@@ -253,16 +267,15 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
     for (int q = 0; q < 24; ++q) lk[q] = (const C *)L.u[q];
     const R rx = a.rx, ry = a.ry, rz = a.rz;
     const C zero = mk2((R)0, (R)0);
-    auto coef = [&](int arr, int cls, int pk, size_t idx) -> Coef<R> {
-        if constexpr (SITE) {
-            return coef_site_at<R>(a.th[arr], idx, (R)1);
-        } else {
-            const R *e = a.tab + ((size_t)cls * a.nz + pk) * 4;
-            Coef<R> k;
-            k.c1 = mk2(e[0], e[1]);
-            k.c2 = mk2(e[2], e[3]);
-            return k;
-        }
+    // V(z) table entry of class cls at plane pk: the address is the same for the
+    // whole workgroup, and the table is read-only here, so these are scalar loads
+    // that never hold up the vector memory counter
+    auto tcoef = [&](int cls, int pk) -> Coef<R> {
+        const R *e = tab + ((size_t)cls * a.nz + pk) * 4;
+        Coef<R> k;
+        k.c1 = mk2(e[0], e[1]);
+        k.c2 = mk2(e[2], e[3]);
+        return k;
     };
 
     // carried along the march: old C(p-1), D(p), D(p-1) at the cell; the own
@@ -280,9 +293,20 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
     }
 
     for (int p = z0 - 1; p <= z1; ++p) {
-        const int pk = wrapn(p, a.nz);
+        const int pk = wrapn(p, a.nz), pm = wrapn(p - 1, a.nz);
         const size_t P = (size_t)pk * plane, Pn = (size_t)wrapn(p + 1, a.nz) * plane;
         C E[8], Qn[12], zpn[2], zmn[2], cc0 = zero, cc1 = zero, dn0 = zero, dn1 = zero;
+        Coef<R> kt[4];      // classes A, B at plane p and C, D at plane p - 1 (tables only)
+        if constexpr (!SITE) {
+            kt[0] = tcoef(0, pk);
+            kt[1] = tcoef(1, pk);
+            kt[2] = tcoef(2, pm);
+            kt[3] = tcoef(3, pm);
+        }
+        auto coef = [&](int arr, int cls, size_t idx) -> Coef<R> {
+            if constexpr (SITE) return coef_site_at<R>(a.th[arr], idx, (R)1);
+            else return kt[cls];
+        };
 #pragma unroll
         for (int q = 0; q < 8; ++q) E[q] = zero;
 #pragma unroll
@@ -331,7 +355,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             };
             if (nA0) {
                 ld0();
-                const C na0 = update(xo[0], ab_row0(u, cc0, cm0, dc0, nb[0], dc1, nb[1], rx, ry, rz), coef(0, 0, pk, ci));
+                const C na0 = update(xo[0], ab_row0(u, cc0, cm0, dc0, nb[0], dc1, nb[1], rx, ry, rz), coef(0, 0, ci));
                 if (store) out[0][ci] = na0;
                 E[3] = pr(u[TXM], na0);
                 E[7] = pr(u[TYM], na0);
@@ -343,7 +367,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             if (nA1) {
                 ld1();
                 const C *v = u + 6;
-                const C na1 = update(xo[1], ab_row1(v, cc1, cm1, nb[2], dc1, nb[3], dc0, rx, ry, rz), coef(1, 0, pk, ci));
+                const C na1 = update(xo[1], ab_row1(v, cc1, cm1, nb[2], dc1, nb[3], dc0, rx, ry, rz), coef(1, 0, ci));
                 if (store) out[1][ci] = na1;
                 E[1] = pr(v[TXP], na1);
                 E[5] = pr(v[TYP], na1);
@@ -355,7 +379,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             if (nB0) {
                 ld2();
                 const C *v = u + 12;
-                const C nb0 = update(xo[2], ab_row2(v, dn0, dc0, nb[4], cc0, cc1, nb[5], rx, ry, rz), coef(2, 1, pk, ci));
+                const C nb0 = update(xo[2], ab_row2(v, dn0, dc0, nb[4], cc0, cc1, nb[5], rx, ry, rz), coef(2, 1, ci));
                 if (store) out[2][ci] = nb0;
                 E[0] = pr(v[TXP], nb0);
                 E[6] = pr(v[TYM], nb0);
@@ -367,7 +391,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             if (nB1) {
                 ld3();
                 const C *v = u + 18;
-                const C nb1 = update(xo[3], ab_row3(v, dn1, dc1, cc1, nb[6], nb[7], cc0, rx, ry, rz), coef(3, 1, pk, ci));
+                const C nb1 = update(xo[3], ab_row3(v, dn1, dc1, cc1, nb[6], nb[7], cc0, rx, ry, rz), coef(3, 1, ci));
                 if (store) out[3][ci] = nb1;
                 E[2] = pr(v[TXM], nb1);
                 E[4] = pr(v[TYP], nb1);
@@ -384,7 +408,6 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             for (int q = 0; q < 8; ++q) sE[p & 1][q][li] = E[q];
         }
         if (tile && p - 1 >= z0 && p - 1 < z1) {
-            const int pm = wrapn(p - 1, a.nz);
             const size_t cm = (size_t)pm * plane + c2;
             const C(*e)[LN] = sE[(p - 1) & 1];
             const C T[24] = {zpn[0], Q[0], Q[1], e[0][li - 1], Q[2], e[4][li - LW],
@@ -392,10 +415,13 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
                              Q[6], zm2[0], e[3][li + 1], Q[7], Q[8], e[5][li - LW],
                              Q[9], zm2[1], Q[10], e[1][li - 1], e[7][li + LW], Q[11]};
             const St3<C> s = cd_rows(T, rx, ry, rz);
-            out[4][cm] = update(cm0, s.s0, coef(4, 2, pm, cm));
-            out[5][cm] = update(cm1, s.s1, coef(5, 2, pm, cm));
-            out[6][cm] = update(dm0, s.s2, coef(6, 3, pm, cm));
-            out[7][cm] = update(dm1, s.s3, coef(7, 3, pm, cm));
+            // all four coefficients before the first store (per-site records:
+            // the loads then need not wait for the stores)
+            const Coef<R> k4 = coef(4, 2, cm), k5 = coef(5, 2, cm), k6 = coef(6, 3, cm), k7 = coef(7, 3, cm);
+            out[4][cm] = update(cm0, s.s0, k4);
+            out[5][cm] = update(cm1, s.s1, k5);
+            out[6][cm] = update(dm0, s.s2, k6);
+            out[7][cm] = update(dm1, s.s3, k7);
         }
         // one barrier per plane: the exports of A,B(p) (slot p & 1) are visible to
         // the next plane's C,D, and this plane's reads of slot (p - 1) & 1 are done
@@ -552,7 +578,7 @@ __global__ __launch_bounds__(256) void k2_half_links(HalfArgs<R> a, LinkPtrs L) 
 // (used at once), u1's +y one the v0 row above (kept two rows), and u0's -x and
 // u1's +x ones the x neighbours (LDS).  Same helpers as the split kernels.
 template <typename R, bool SITE, int TW>
-__global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPtrs L) {
+__global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPtrs L, const R *__restrict__ tab) {
     using C = cx<R>;
     constexpr int LW = TW + 2;
     __shared__ C sE[2][2][LW];     // slot p & 1: [0] u0's -x coupling, [1] u1's +x coupling
@@ -589,16 +615,19 @@ __global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPt
     for (int q = 0; q < 8; ++q) lk[q] = (const C *)L.u[q];
     const R rx = a.rx, ry = a.ry;
     const C zero = mk2((R)0, (R)0);
-    auto coef = [&](int arr, int cls, size_t idx) -> Coef<R> {
-        if constexpr (SITE) {
-            return coef_site_at<R>(a.th[arr], idx, (R)1);
-        } else {
-            const R *e = a.tab + (size_t)cls * a.nz * 4;      // plane 0 of class cls
-            Coef<R> k;
-            k.c1 = mk2(e[0], e[1]);
-            k.c2 = mk2(e[2], e[3]);
-            return k;
+    // table entries (plane 0 of the u and v classes) read once, as scalar loads
+    Coef<R> kt[4];
+    if constexpr (!SITE) {
+#pragma unroll
+        for (int cls = 0; cls < 4; cls += 3) {
+            const R *e = tab + (size_t)cls * a.nz * 4;
+            kt[cls].c1 = mk2(e[0], e[1]);
+            kt[cls].c2 = mk2(e[2], e[3]);
         }
+    }
+    auto coef = [&](int arr, int cls, size_t idx) -> Coef<R> {
+        if constexpr (SITE) return coef_site_at<R>(a.th[arr], idx, (R)1);
+        else return kt[cls];
     };
     // carried: old v0 of rows p and p-1, old v1 of row p-1; own couplings of u(p-1);
     // the u1 +y couplings of u(p-1) and u(p-2)
@@ -646,8 +675,9 @@ __global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPt
             const C(*e)[LW] = sE[(p - 1) & 1];
             const C T[8] = {e[0][li + 1], Q[0], Q[1], up2, Q[2], e[1][li - 1], dn, Q[3]};
             const St2<C> s = v_rows(T, rx, ry);
-            out[2][cm] = update(v0m, s.s0, coef(2, 3, cm));
-            out[3][cm] = update(v1m, s.s1, coef(3, 3, cm));
+            const Coef<R> k2 = coef(2, 3, cm), k3 = coef(3, 3, cm);   // both loads before the stores
+            out[2][cm] = update(v0m, s.s0, k2);
+            out[3][cm] = update(v1m, s.s1, k3);
         }
         __syncthreads();
         v0m = v0c;
@@ -720,6 +750,11 @@ hipError_t launch_half_links(const HalfArgs<R> &a, const LinkPtrs &L, int ndim, 
     return hipGetLastError();
 }
 
+// tiles across the patch one XCD runs at once (0: whole tile rows); measured at
+// 512^3: complex64 fastest in whole rows (4 x 8 and 2 x 16 patches slower),
+// complex128 in 4 x 8 patches (about 4% faster than whole rows; 2 x 16, 8 x 4, 16 x 2 between)
+constexpr int kLinkPX32 = 0, kLinkPX64 = 4;
+
 template <typename R>
 hipError_t launch_fused_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool site, hipStream_t s) {
     FusedArgs<R> a = a0;
@@ -737,12 +772,13 @@ hipError_t launch_fused_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool si
         a.zchunk = (int)((a.nz + nzc - 1) / nzc);
     }
     a.nzc = (a.nz + a.zchunk - 1) / a.zchunk;
+    a.px = sizeof(R) == 4 ? kLinkPX32 : kLinkPX64;
     const int64_t nblk = tiles * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 g((unsigned)nblk), b(fl_threads<TW, TY>());
     constexpr int WPE = sizeof(R) == 4 ? 3 : 2;
-    if (site) hipLaunchKernelGGL((k3_fused_links<R, true, TW, TY, WPE>), g, b, 0, s, a, L);
-    else hipLaunchKernelGGL((k3_fused_links<R, false, TW, TY, WPE>), g, b, 0, s, a, L);
+    if (site) hipLaunchKernelGGL((k3_fused_links<R, true, TW, TY, WPE>), g, b, 0, s, a, L, a.tab);
+    else hipLaunchKernelGGL((k3_fused_links<R, false, TW, TY, WPE>), g, b, 0, s, a, L, a.tab);
     return hipGetLastError();
 }
 
@@ -763,8 +799,8 @@ hipError_t launch_fused2_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool s
     a.nzc = (a.ny + a.zchunk - 1) / a.zchunk;
     const int64_t nblk = (int64_t)a.ntx * a.nzc;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    if (site) hipLaunchKernelGGL((k2_fused_links<R, true, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L);
-    else hipLaunchKernelGGL((k2_fused_links<R, false, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L);
+    if (site) hipLaunchKernelGGL((k2_fused_links<R, true, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L, a.tab);
+    else hipLaunchKernelGGL((k2_fused_links<R, false, TW>), dim3((unsigned)nblk), dim3(TW + 64), 0, s, a, L, a.tab);
     return hipGetLastError();
 }
 

@@ -921,10 +921,13 @@ def test_links_reverse_and_step_norm(P, dim):
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 @pytest.mark.parametrize("site", [False, True])
 @pytest.mark.parametrize("shape,zchunk,steps", [((70, 20, 22), 0, 5), ((130, 9, 5), 2, 4), ((3, 2, 4), 0, 3),
-                                                 ((64, 8, 16), 5, 4), ((1, 1, 3), 0, 2), ((65, 9, 7), 3, 3)])
+                                                 ((64, 8, 16), 5, 4), ((1, 1, 3), 0, 2), ((65, 9, 7), 3, 3),
+                                                 ((128, 64, 6), 2, 3)])
 def test_fused_links_bitwise_equals_split(P, dtype, site, shape, zchunk, steps):
     """The z-march link kernel (one launch per step) gives the bits of the split
-    link kernels: ragged tiles, chunk boundaries, lattices smaller than the ring."""
+    link kernels: ragged tiles, chunk boundaries, lattices smaller than the ring;
+    128 x 64 complex128 (4 x 8 tiles of 32 x 8) takes the patch order of the
+    workgroups, one patch per z-chunk."""
     from closed_form import links_from_potential3, smooth_potential3
     nx, ny, nz = shape
     print("fused links %s %s site=%s zchunk=%d" % (shape, dtype, site, zchunk), flush=True)
