@@ -149,10 +149,20 @@ __device__ __forceinline__ FusedArgs<R> item_args(const BatchLat &L, int parity,
     return a;
 }
 
+// Item of block b in a launch of one block per item (n blocks).  Blocks are dealt
+// to the eight XCDs in turn (block b to XCD b mod 8); each XCD gets a contiguous
+// run of the item list instead, so strips side by side in x run at the same time
+// on one XCD and find each other's halo columns in its L2.  XCD x holds
+// n/8 + (x < n mod 8) blocks; a bijection for any n.
+__device__ __forceinline__ int item_of_block(int b, int n) {
+    const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + k;
+}
+
 template <typename R, int TXB>
 __global__ __launch_bounds__(TXB) void kb_step(const BatchLat *lats, const BatchItem *items, int ly, int parity) {
     __shared__ cx<R> uu[2][2][TXB + 2];
-    const BatchItem w = items[blockIdx.x];
+    const BatchItem w = items[item_of_block(blockIdx.x, gridDim.x)];
     const BatchLat &L = lats[w.lat];
     FusedArgs<R> a = item_args<R>(L, parity, ly);
     march2<R, true, TXB>(a, w.tx, w.yc, uu);
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(TW + 64) void kb_step2(const BatchLat *lats, const 
     __shared__ __align__(16) cx<R> sOld[2 + 4 * W + 2];
     __shared__ __align__(16) cx<R> sStage[2 * W];
     __shared__ __align__(16) cx<R> sLev[2 + 6 * W + 2];
-    const BatchItem w = items[blockIdx.x];
+    const BatchItem w = items[item_of_block(blockIdx.x, gridDim.x)];
     const BatchLat &L = lats[w.lat];
     FusedArgs<R> a = item_args<R>(L, parity, ly);
     march2x2<R, true, TW>(a, nullptr, w.tx, w.yc, sOld, sStage, sLev);
