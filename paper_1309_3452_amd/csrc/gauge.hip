@@ -20,6 +20,7 @@
 #include "stencil3.h"
 #include "march2.h"
 #include "gauge.h"
+#include "norm3.h"
 
 namespace dirac {
 
@@ -805,6 +806,7 @@ hipError_t launch_fused2_links(const FusedArgs<R> &a0, const LinkPtrs &L, bool s
 }
 
 template <typename R> hipError_t launch_norm_links(const ReduceArgs<R> &a, const LinkPtrs &L, int ndim, hipStream_t s) {
+    if (ndim == 3 && norm3_staged_supported(a.nx, sizeof(R) == 4)) return launch_norm3_links_staged<R>(a, L, s);
     if (ndim == 3) hipLaunchKernelGGL((k3_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
     else hipLaunchKernelGGL((k2_norm_links<R>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a, L);
     return hipGetLastError();

@@ -1,5 +1,6 @@
 // Conserved functional of the (3+1)D scheme (Lemma of Sect. 2) as an
-// LDS-staged z-march: per-workgroup partial sums of
+// LDS-staged z-march, without and with gauge links (Sect. 4; the second kernel
+// below): per-workgroup partial sums of
 //   E_r   = sum |X|^2 - Re sum_{A,B} conj(X) S_X(C,D)
 //   E_r'  = sum |X|^2 + Re sum_{C,D} conj(Y) S_Y(A,B)   (the same functional summed on the C,D sites)
 //   N     = sum |X|^2
@@ -236,10 +237,230 @@ __global__ __launch_bounds__(NormTile<R>::TW *NormTile<R>::TY) void k3_norm_lds(
     }
 }
 
-template <typename R> NormMap norm_map(int nx, int ny, int nz) {
+// ---- with gauge links (Sect. 4) ----
+// The same three sums with every neighbour value in S_X multiplied by its link
+// factor: an A,B row by the factor stored with its own array at the cell, a C,D
+// row by the conjugate of the factor stored at the A,B end of the half-link.
+// The amplitudes are staged as above (the link rows read the same neighbours on
+// the same sides).  Each cell loads its own 24 factors, and the 8 factors of
+// its x and y neighbours that its C,D rows need, straight from global memory;
+// they are read by no other cell's rows, so staging them would save nothing.
+// Across the plane boundary: S_B0 and S_B1 keep their x-y part, their +z factor
+// and their -z coupling, and take D at k+1 at the next plane; S_C0 and S_C1
+// keep their x-y part and their -z coupling and take the next plane's A times
+// that cell's own -z factor; the -z couplings of S_D0 and S_D1 (B at k-1 times
+// its +z factor) come up from the plane below.  Each per-cell term takes the
+// operations of the unstaged link reduction in the same order.
+template <typename R> struct LinkNormTile;
+template <> struct LinkNormTile<float> {
+    static constexpr int TW = 64, TY = 8, XL = 2;
+};
+template <> struct LinkNormTile<double> {
+    static constexpr int TW = 32, TY = 16, XL = 1;
+};
+
+// link factor index 6 a + t for A,B array a and neighbour term t
+enum { LZP = 0, LZM = 1, LXP = 2, LXM = 3, LYP = 4, LYM = 5 };
+
+// Two waves per SIMD is the occupancy the registers allow anyway; told so, the
+// compiler issues a plane's link loads together instead of moving each next to
+// its use (and waiting for it there) to save registers for an occupancy it
+// cannot reach: complex64 at 512^3 7.0 against 8.7 ms; the complex128 code is
+// the same either way.
+
+template <typename R>
+__global__ __launch_bounds__(LinkNormTile<R>::TW *LinkNormTile<R>::TY) __attribute__((amdgpu_waves_per_eu(2, 2))) void k3_norm_links_lds(ReduceArgs<R> a,
+                                                                                              LinkPtrs L, NormMap m) {
+    using C = cx<R>;
+    constexpr int TW = LinkNormTile<R>::TW, TY = LinkNormTile<R>::TY, XL = LinkNormTile<R>::XL, NT = TW * TY;
+    constexpr int CPL = 16 / (int)sizeof(C);
+    constexpr int W = TW + XL, H = TY + 1, RN = W * H;
+    constexpr int NW = NT / 64, WPA = NW / 8, NJ = (H + WPA - 1) / WPA;
+    static_assert(NW % 8 == 0, "whole waves per array");
+    static_assert(W / CPL <= 64, "one wave instruction per region row");
+    static_assert((W * sizeof(C)) % 16 == 0 && (RN * sizeof(C)) % 16 == 0, "16-byte aligned LDS rows");
+    __shared__ __align__(16) C sP[8 * RN];
+    __shared__ __align__(16) C sQ[8 * RN];
+    __shared__ double red[kNormVals * 16];
+
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int xr = t % TW, yr = t / TW;
+    const int i = yr * W + xr;
+    auto ofs = [](int q) { return (y_minus(q) ? W : 0) + (x_minus(q) ? XL : 0); };
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    constexpr uint32_t CS = sizeof(C);
+    const size_t rowbytes = (size_t)nx * CS, pbytes = rowbytes * ny, plane = (size_t)nx * ny;
+    const double rx = a.rx, ry = a.ry, rz = a.rz;
+    auto zpl = [&](int pl) { return pl < 0 ? pl + nz : pl >= nz ? pl - nz : pl; };
+    const int ck = wv / WPA, cy0 = wv % WPA;
+    const char *csrc = (const char *)a.f[ck];
+    const C *lk[24];
+#pragma unroll
+    for (int q = 0; q < 24; ++q) lk[q] = (const C *)L.u[q];
+    // link times value, and conjugate link times value, in FP64
+    auto lm = [](C u, double2 x) { return cmul(dbl(u), x); };
+    auto lc = [](C u, double2 x) { return cmul(cconj(dbl(u)), x); };
+
+    const int blk = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    double v[kNormVals] = {0.0, 0.0, 0.0};
+    for (int item = blk; item < m.items; item += gridDim.x) {
+        int r = item;
+        const int tx = r % m.ntx;
+        r /= m.ntx;
+        const int ty = r % m.nty;
+        const int zc = r / m.nty;
+        const int x0 = tx * TW, y0 = ty * TY;
+        const int w = min(TW, nx - x0), h = min(TY, ny - y0);
+        const int z0 = zc * m.zchunk, z1 = min(nz, z0 + m.zchunk);
+        const bool act = xr < w && yr < h;
+        const int gi = x0 + xr, gj = y0 + yr;
+        const size_t oc = (size_t)gj * nx + gi;
+        const size_t oxm = (size_t)gj * nx + (gi == 0 ? nx - 1 : gi - 1);
+        const size_t oxp = (size_t)gj * nx + (gi == nx - 1 ? 0 : gi + 1);
+        const size_t oym = (size_t)(gj == 0 ? ny - 1 : gj - 1) * nx + gi;
+        const size_t oyp = (size_t)(gj == ny - 1 ? 0 : gj + 1) * nx + gi;
+
+        const int ym = y_minus(ck) ? 1 : 0, xm = x_minus(ck) ? XL : 0;
+        const int rl = (w + XL) / CPL;
+        const uint32_t lxo = (uint32_t)wrapm(x0 - xm + lane * CPL, nx) * CS;
+        auto copy_plane = [&](int pl, C *set) __attribute__((always_inline)) {
+            const char *base = csrc + (size_t)zpl(pl) * pbytes;
+            C *dst = set + ck * RN;
+#pragma unroll 1
+            for (int j = 0; j < NJ; ++j) {
+                const int yy = cy0 + WPA * j;
+                int y = y0 - ym + yy;
+                y = y < 0 ? y + ny : y >= ny ? y - ny : y;
+                if (yy < h + 1 && lane < rl) g2lds16(base + (size_t)y * rowbytes + lxo, dst + yy * W);
+            }
+        };
+
+        // own values of plane p-1; the x-y parts of S_B0, S_B1, S_C0, S_C1 at
+        // plane p-1 (g), the +z factors of B0, B1 (zl) and the -z couplings of
+        // S_B0, S_B1 (zr) and of S_C0, S_C1 (tz) there; the -z couplings of
+        // S_D0, S_D1 at plane p (zd)
+        C pv[8], zl[2];
+        double2 g[4], zr[2], tz[2], zd[2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = mk2((R)0, (R)0);
+        zl[0] = zl[1] = mk2((R)0, (R)0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) zr[q] = tz[q] = zd[q] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = make_double2(0.0, 0.0);
+        if (act) {
+            const size_t o = (size_t)zpl(z0 - 1) * plane + oc;
+#pragma unroll
+            for (int q = 2; q < 6; ++q) pv[q] = ((const C *)a.f[q])[o];   // B, C of plane z0-1
+            zd[0] = lc(lk[12 + LZP][o], dbl(pv[2]));
+            zd[1] = lc(lk[18 + LZP][o], dbl(pv[3]));
+        }
+
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        copy_plane(z0, sP);
+        auto plane_step = [&](const C *S, C *Snext, int p) __attribute__((always_inline)) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (p < z1) copy_plane(p + 1, Snext);
+            if (!act) return;
+            const size_t P = (size_t)zpl(p) * plane, c = P + oc;
+            C cur[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cur[q] = S[q * RN + ofs(q) + i];
+            if (p > z0) {
+                // finish plane p-1: its +z neighbours are this plane's D (S_B) and
+                // this plane's A times its own -z factors (S_C)
+                const double2 s2 = add_z(-rz, csub(lm(zl[0], dbl(cur[6])), zr[0]), g[0]);
+                const double2 s3 = add_z(-rz, csub(lm(zl[1], dbl(cur[7])), zr[1]), g[1]);
+                const double2 t0 = add_z(rz, csub(lc(lk[0 + LZM][c], dbl(cur[0])), tz[0]), g[2]);
+                const double2 t1 = add_z(rz, csub(lc(lk[6 + LZM][c], dbl(cur[1])), tz[1]), g[3]);
+                v[0] -= re_cm(dbl(pv[2]), s2) + re_cm(dbl(pv[3]), s3);
+                v[1] += re_cm(dbl(pv[4]), t0) + re_cm(dbl(pv[5]), t1);
+            }
+            if (p < z1) {
+                C u[24];
+#pragma unroll
+                for (int q = 0; q < 24; ++q) u[q] = lk[q][c];
+                // factors of the x and y neighbours that the C,D couplings use
+                const C nB0xm = lk[12 + LXP][P + oxm], nB1ym = lk[18 + LYP][P + oym];
+                const C nB1xp = lk[18 + LXM][P + oxp], nB0yp = lk[12 + LYM][P + oyp];
+                const C nA0xp = lk[0 + LXM][P + oxp], nA1ym = lk[6 + LYP][P + oym];
+                const C nA1xm = lk[6 + LXP][P + oxm], nA0yp = lk[0 + LYM][P + oyp];
+                const double2 a0 = dbl(cur[0]), a1 = dbl(cur[1]), b0 = dbl(cur[2]), b1 = dbl(cur[3]);
+                const double2 c0 = dbl(cur[4]), c1 = dbl(cur[5]), d0 = dbl(cur[6]), d1 = dbl(cur[7]);
+                auto nb = [&](int q, int off) { return dbl(S[q * RN + ofs(q) + i + off]); };
+                // E_r: S_A0, S_A1 whole
+                const double2 sa0 = sterm3(rz, csub(lm(u[LZP], c0), lm(u[LZM], dbl(pv[4]))), rx,
+                                           csub(lm(u[LXP], d0), lm(u[LXM], nb(6, -1))), -ry,
+                                           csub(lm(u[LYP], d1), lm(u[LYM], nb(7, -W))));
+                const double2 sa1 = sterm3(rz, csub(lm(u[6 + LZP], c1), lm(u[6 + LZM], dbl(pv[5]))), rx,
+                                           csub(lm(u[6 + LXP], nb(7, 1)), lm(u[6 + LXM], d1)), -ry,
+                                           csub(lm(u[6 + LYP], nb(6, W)), lm(u[6 + LYM], d0)));
+                // S_B0, S_B1: x-y parts, the z part at the next plane
+                g[0] = xy_part(rx, csub(lm(u[12 + LXP], nb(4, 1)), lm(u[12 + LXM], c0)), ry,
+                               csub(lm(u[12 + LYP], c1), lm(u[12 + LYM], nb(5, -W))));
+                g[1] = xy_part(rx, csub(lm(u[18 + LXP], c1), lm(u[18 + LXM], nb(5, -1))), ry,
+                               csub(lm(u[18 + LYP], nb(4, W)), lm(u[18 + LYM], c0)));
+                zl[0] = u[12 + LZP];
+                zl[1] = u[18 + LZP];
+                zr[0] = lm(u[12 + LZM], d0);
+                zr[1] = lm(u[18 + LZM], d1);
+                // E_r': S_C0, S_C1 x-y parts and -z couplings
+                g[2] = xy_part(rx, csub(lc(u[12 + LXM], b0), lc(nB0xm, nb(2, -1))), -ry,
+                               csub(lc(u[18 + LYM], b1), lc(nB1ym, nb(3, -W))));
+                g[3] = xy_part(rx, csub(lc(nB1xp, nb(3, 1)), lc(u[18 + LXP], b1)), -ry,
+                               csub(lc(nB0yp, nb(2, W)), lc(u[12 + LYP], b0)));
+                tz[0] = lc(u[LZP], a0);
+                tz[1] = lc(u[6 + LZP], a1);
+                // S_D0, S_D1 whole (their -z couplings from the plane below)
+                const double2 sd0 = sterm3(-rz, csub(lc(u[12 + LZM], b0), zd[0]), rx,
+                                           csub(lc(nA0xp, nb(0, 1)), lc(u[LXP], a0)), ry,
+                                           csub(lc(u[6 + LYM], a1), lc(nA1ym, nb(1, -W))));
+                const double2 sd1 = sterm3(-rz, csub(lc(u[18 + LZM], b1), zd[1]), rx,
+                                           csub(lc(u[6 + LXM], a1), lc(nA1xm, nb(1, -1))), ry,
+                                           csub(lc(nA0yp, nb(0, W)), lc(u[LYP], a0)));
+                zd[0] = lc(u[12 + LZP], b0);
+                zd[1] = lc(u[18 + LZP], b1);
+                const double pp = sq(a0) + sq(a1) + sq(b0) + sq(b1) + sq(c0) + sq(c1) + sq(d0) + sq(d1);
+                v[0] += pp - (re_cm(a0, sa0) + re_cm(a1, sa1));
+                v[1] += pp + (re_cm(d0, sd0) + re_cm(d1, sd1));
+                v[2] += pp;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pv[q] = cur[q];
+            }
+        };
+        for (int p = z0;;) {
+            plane_step(sP, sQ, p);
+            if (++p > z1) break;
+            plane_step(sQ, sP, p);
+            if (++p > z1) break;
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < kNormVals; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < kNormVals; ++q) red[q * 16 + wv] = v[q];
+    __syncthreads();
+    if (t == 0) {
+        double *o = a.partial + (size_t)blockIdx.x * kNormVals;
+        for (int q = 0; q < kNormVals; ++q) {
+            double s = 0.0;
+            for (int u = 0; u < NW; ++u) s += red[q * 16 + u];
+            o[q] = s;
+        }
+    }
+}
+
+template <int TW, int TY> NormMap tile_map(int nx, int ny, int nz) {
     NormMap m;
-    m.ntx = (nx + NormTile<R>::TW - 1) / NormTile<R>::TW;
-    m.nty = (ny + NormTile<R>::TY - 1) / NormTile<R>::TY;
+    m.ntx = (nx + TW - 1) / TW;
+    m.nty = (ny + TY - 1) / TY;
     const int64_t tiles = (int64_t)m.ntx * m.nty;
     int64_t nzc = (kReduceBlocks + tiles - 1) / tiles;
     if (nzc > nz) nzc = nz;
@@ -248,6 +469,10 @@ template <typename R> NormMap norm_map(int nx, int ny, int nz) {
     m.nzc = (nz + m.zchunk - 1) / m.zchunk;
     m.items = (int)(tiles * m.nzc);
     return m;
+}
+
+template <typename R> NormMap norm_map(int nx, int ny, int nz) {
+    return tile_map<NormTile<R>::TW, NormTile<R>::TY>(nx, ny, nz);
 }
 
 }  // namespace
@@ -268,5 +493,17 @@ template <typename R> hipError_t launch_norm3_staged(const ReduceArgs<R> &a, hip
 
 template hipError_t launch_norm3_staged<float>(const ReduceArgs<float> &, hipStream_t);
 template hipError_t launch_norm3_staged<double>(const ReduceArgs<double> &, hipStream_t);
+
+template <typename R> hipError_t launch_norm3_links_staged(const ReduceArgs<R> &a, const LinkPtrs &L, hipStream_t s) {
+    constexpr int TW = LinkNormTile<R>::TW, TY = LinkNormTile<R>::TY;
+    if (!norm3_staged_supported(a.nx, sizeof(R) == 4) || a.zh || a.zbc) return hipErrorInvalidValue;
+    if ((int64_t)((a.nx + TW - 1) / TW) * ((a.ny + TY - 1) / TY) * a.nz > 0x7fffffff) return hipErrorInvalidValue;
+    const NormMap m = tile_map<TW, TY>(a.nx, a.ny, a.nz);
+    hipLaunchKernelGGL((k3_norm_links_lds<R>), dim3(kReduceBlocks), dim3(TW * TY), 0, s, a, L, m);
+    return hipGetLastError();
+}
+
+template hipError_t launch_norm3_links_staged<float>(const ReduceArgs<float> &, const LinkPtrs &, hipStream_t);
+template hipError_t launch_norm3_links_staged<double>(const ReduceArgs<double> &, const LinkPtrs &, hipStream_t);
 
 }  // namespace dirac

@@ -8,6 +8,8 @@ tile whose ring wraps onto itself, and odd row lengths (complex64 then takes
 the unstaged reduction), with periodic and zero values outside the lattice.
 dt = 1/4 is exact in both precisions, so both sides evaluate the same
 functional of the same values and differ only in the order of the FP64 sums.
+The same holds for the functional with gauge links (periodic lattices only;
+tiles of 64 x 8 cells for complex64, 32 x 16 for complex128).
 """
 import numpy as np
 import pytest
@@ -74,3 +76,32 @@ def test_3d_observables_vs_oracle(P, shape, dtype):
         oo = ol.observe(f, z0)
         for q in range(9):
             assert abs(ob[q] - oo[q]) <= 1e-12 * max(abs(oo[q]), oo[4]), (z0, q, ob[q], oo[q])
+
+
+LINK_SHAPES = [(70, 20, 22), (64, 8, 7), (130, 9, 5), (2, 1, 1), (4, 3, 2), (6, 40, 1), (33, 17, 3),
+               (96, 33, 4), (256, 24, 3)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("shape", LINK_SHAPES)
+def test_3d_norm_links_vs_oracle(P, shape, dtype):
+    """E_r with gauge links (Sect. 4) against the oracle's on the same values and
+    links: random unit factors, so every link of every term is tested; odd
+    complex64 rows take the unstaged reduction."""
+    nx, ny, nz = shape
+    print("norm3 links %s %s" % (shape, dtype), flush=True)
+    g = np.random.default_rng(7200 + nx + 3 * ny + 7 * nz)
+    tsh = (nz, ny, nx)
+    f0 = [np.ascontiguousarray(g.standard_normal(tsh) + 1j * g.standard_normal(tsh)) for _ in range(8)]
+    U = [np.ascontiguousarray(np.exp(1j * g.uniform(-np.pi, np.pi, tsh))) for _ in range(24)]
+    lat = P.Lattice((nx, ny, nz), dtype=dtype, dt=DT)
+    lat.load(f0)
+    lat.set_links([torch.from_numpy(u) for u in U])
+    f = [t.detach().cpu().numpy().astype(np.complex128) for t in lat.state()]
+    Uc = [u.astype(np.complex64).astype(np.complex128) for u in U] if dtype == torch.complex64 else U
+    e = lat.norm()
+    eo = oracle.Lattice3(nx, ny, nz, DT).energy_links(f, Uc)
+    assert abs(e[2] - eo[2]) <= 1e-13 * eo[2]
+    for q in range(2):
+        assert abs(e[q] - eo[q]) <= 1e-12 * eo[2], (q, e, eo)
+    assert abs(e[0] - e[1]) <= 1e-12 * eo[2]
