@@ -23,6 +23,7 @@
 #include "device.h"
 #include "internal.h"
 #include "stencil3.h"
+#include "ntstore.h"
 
 namespace dirac {
 
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
                 C yp_ = f[4 + q][c];
                 C ym_ = update(yp_, mk2(-ss[q].x, -ss[q].y), kr);
                 g[cls == 2 ? 1 : 0] += dtheta_term(l[4 + q][c], yp_, ym_, kf);
-                f[4 + q][c] = ym_;
+                st_nt(&f[4 + q][c], ym_);
             }
         } else if constexpr (SWEEP == 1) {
             // w = conj(beta2) lamY at every C,D value the A,B stencil reads
@@ -119,8 +120,8 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
                 C xp_ = f[q][c];
                 C xm_ = update(xp_, mk2(-ss[q].x, -ss[q].y), kr);
                 g[cls == 0 ? 0 : 1] += dtheta_term(lx, xp_, xm_, kf);
-                f[q][c] = xm_;
-                l[q][c] = cmulc(alpha_of(kf), lx);
+                st_nt(&f[q][c], xm_);
+                st_nt(&l[q][c], cmulc(alpha_of(kf), lx));
             }
         } else {
             // (sweep 2, and sweep 3's first half)
@@ -153,11 +154,11 @@ __global__ __launch_bounds__(256) void k3_adj(AdjArgs<R> a) {
                     C yp_ = f[4 + q][c];
                     C ym_ = update(yp_, mk2(-ss0[q].x, -ss0[q].y), kr);
                     g[cls == 2 ? 1 : 0] += dtheta_term(lyn[q], yp_, ym_, kf);
-                    f[4 + q][c] = ym_;
+                    st_nt(&f[4 + q][c], ym_);
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) l[4 + q][c] = lyn[q];
+            for (int q = 0; q < 4; ++q) st_nt(&l[4 + q][c], lyn[q]);
         }
     }
     if constexpr (SWEEP != 2) {

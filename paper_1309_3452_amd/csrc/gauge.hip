@@ -21,6 +21,7 @@
 #include "march2.h"
 #include "gauge.h"
 #include "norm3.h"
+#include "ntstore.h"
 
 namespace dirac {
 
@@ -172,16 +173,24 @@ __global__ __launch_bounds__(256) void k3_half_links(HalfArgs<R> a, LinkPtrs L) 
     }
     if constexpr (WHICH == 0) {
         const St3<C> s = links_ab<C, R, C>(fc, L, n, a.rx, a.ry, a.rz);
-        f[0][n.c] = update(f[0][n.c], s.s0, gcoef<R, SITE>(a, 0, 0, k, n.c));
-        f[1][n.c] = update(f[1][n.c], s.s1, gcoef<R, SITE>(a, 1, 0, k, n.c));
-        f[2][n.c] = update(f[2][n.c], s.s2, gcoef<R, SITE>(a, 2, 1, k, n.c));
-        f[3][n.c] = update(f[3][n.c], s.s3, gcoef<R, SITE>(a, 3, 1, k, n.c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o0 = f[0][n.c], o1 = f[1][n.c], o2 = f[2][n.c], o3 = f[3][n.c];
+        const Coef<R> k0 = gcoef<R, SITE>(a, 0, 0, k, n.c), k1 = gcoef<R, SITE>(a, 1, 0, k, n.c), k2 = gcoef<R, SITE>(a, 2, 1, k, n.c), k3 = gcoef<R, SITE>(a, 3, 1, k, n.c);
+        st_nt(&f[0][n.c], update(o0, s.s0, k0));
+        st_nt(&f[1][n.c], update(o1, s.s1, k1));
+        st_nt(&f[2][n.c], update(o2, s.s2, k2));
+        st_nt(&f[3][n.c], update(o3, s.s3, k3));
     } else {
         const St3<C> s = links_cd<C, R, C>(fc, L, n, a.rx, a.ry, a.rz);
-        f[4][n.c] = update(f[4][n.c], s.s0, gcoef<R, SITE>(a, 4, 2, k, n.c));
-        f[5][n.c] = update(f[5][n.c], s.s1, gcoef<R, SITE>(a, 5, 2, k, n.c));
-        f[6][n.c] = update(f[6][n.c], s.s2, gcoef<R, SITE>(a, 6, 3, k, n.c));
-        f[7][n.c] = update(f[7][n.c], s.s3, gcoef<R, SITE>(a, 7, 3, k, n.c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o4 = f[4][n.c], o5 = f[5][n.c], o6 = f[6][n.c], o7 = f[7][n.c];
+        const Coef<R> k4 = gcoef<R, SITE>(a, 4, 2, k, n.c), k5 = gcoef<R, SITE>(a, 5, 2, k, n.c), k6 = gcoef<R, SITE>(a, 6, 3, k, n.c), k7 = gcoef<R, SITE>(a, 7, 3, k, n.c);
+        st_nt(&f[4][n.c], update(o4, s.s0, k4));
+        st_nt(&f[5][n.c], update(o5, s.s1, k5));
+        st_nt(&f[6][n.c], update(o6, s.s2, k6));
+        st_nt(&f[7][n.c], update(o7, s.s3, k7));
     }
 }
 
@@ -357,7 +366,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             if (nA0) {
                 ld0();
                 const C na0 = update(xo[0], ab_row0(u, cc0, cm0, dc0, nb[0], dc1, nb[1], rx, ry, rz), coef(0, 0, ci));
-                if (store) out[0][ci] = na0;
+                if (store) st_nt(&out[0][ci], na0);
                 E[3] = pr(u[TXM], na0);
                 E[7] = pr(u[TYM], na0);
                 Qn[0] = pr(u[TZP], na0);
@@ -369,7 +378,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
                 ld1();
                 const C *v = u + 6;
                 const C na1 = update(xo[1], ab_row1(v, cc1, cm1, nb[2], dc1, nb[3], dc0, rx, ry, rz), coef(1, 0, ci));
-                if (store) out[1][ci] = na1;
+                if (store) st_nt(&out[1][ci], na1);
                 E[1] = pr(v[TXP], na1);
                 E[5] = pr(v[TYP], na1);
                 Qn[3] = pr(v[TZP], na1);
@@ -381,7 +390,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
                 ld2();
                 const C *v = u + 12;
                 const C nb0 = update(xo[2], ab_row2(v, dn0, dc0, nb[4], cc0, cc1, nb[5], rx, ry, rz), coef(2, 1, ci));
-                if (store) out[2][ci] = nb0;
+                if (store) st_nt(&out[2][ci], nb0);
                 E[0] = pr(v[TXP], nb0);
                 E[6] = pr(v[TYM], nb0);
                 Qn[1] = pr(v[TXM], nb0);
@@ -393,7 +402,7 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
                 ld3();
                 const C *v = u + 18;
                 const C nb1 = update(xo[3], ab_row3(v, dn1, dc1, cc1, nb[6], nb[7], cc0, rx, ry, rz), coef(3, 1, ci));
-                if (store) out[3][ci] = nb1;
+                if (store) st_nt(&out[3][ci], nb1);
                 E[2] = pr(v[TXM], nb1);
                 E[4] = pr(v[TYP], nb1);
                 Qn[2] = pr(v[TYM], nb1);
@@ -419,10 +428,10 @@ __global__ __launch_bounds__((fl_threads<TW, TY>()), WPE) void k3_fused_links(Fu
             // all four coefficients before the first store (per-site records:
             // the loads then need not wait for the stores)
             const Coef<R> k4 = coef(4, 2, cm), k5 = coef(5, 2, cm), k6 = coef(6, 3, cm), k7 = coef(7, 3, cm);
-            out[4][cm] = update(cm0, s.s0, k4);
-            out[5][cm] = update(cm1, s.s1, k5);
-            out[6][cm] = update(dm0, s.s2, k6);
-            out[7][cm] = update(dm1, s.s3, k7);
+            st_nt(&out[4][cm], update(cm0, s.s0, k4));
+            st_nt(&out[5][cm], update(cm1, s.s1, k5));
+            st_nt(&out[6][cm], update(dm0, s.s2, k6));
+            st_nt(&out[7][cm], update(dm1, s.s3, k7));
         }
         // one barrier per plane: the exports of A,B(p) (slot p & 1) are visible to
         // the next plane's C,D, and this plane's reads of slot (p - 1) & 1 are done
@@ -562,12 +571,20 @@ __global__ __launch_bounds__(256) void k2_half_links(HalfArgs<R> a, LinkPtrs L) 
     // 2D tables: u class 0, v class 3 (one plane)
     if constexpr (WHICH == 0) {
         const St2<C> s = links_u<C, R, C>(fc, L, n, a.rx, a.ry);
-        f[0][n.c] = update(f[0][n.c], s.s0, gcoef<R, SITE>(a, 0, 0, 0, n.c));
-        f[1][n.c] = update(f[1][n.c], s.s1, gcoef<R, SITE>(a, 1, 0, 0, n.c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o0 = f[0][n.c], o1 = f[1][n.c];
+        const Coef<R> k0 = gcoef<R, SITE>(a, 0, 0, 0, n.c), k1 = gcoef<R, SITE>(a, 1, 0, 0, n.c);
+        st_nt(&f[0][n.c], update(o0, s.s0, k0));
+        st_nt(&f[1][n.c], update(o1, s.s1, k1));
     } else {
         const St2<C> s = links_v<C, R, C>(fc, L, n, a.rx, a.ry);
-        f[2][n.c] = update(f[2][n.c], s.s0, gcoef<R, SITE>(a, 2, 3, 0, n.c));
-        f[3][n.c] = update(f[3][n.c], s.s1, gcoef<R, SITE>(a, 3, 3, 0, n.c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o2 = f[2][n.c], o3 = f[3][n.c];
+        const Coef<R> k2 = gcoef<R, SITE>(a, 2, 3, 0, n.c), k3 = gcoef<R, SITE>(a, 3, 3, 0, n.c);
+        st_nt(&f[2][n.c], update(o2, s.s0, k2));
+        st_nt(&f[3][n.c], update(o3, s.s1, k3));
     }
 }
 
@@ -651,7 +668,7 @@ __global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPt
 #pragma unroll
                 for (int q = 0; q < 4; ++q) u[q] = lk[q][ci];
                 const C nu0 = update(in[0][ci], u_row0(u, v0c, v0xm, v1c, v1m, rx, ry), coef(0, 0, ci));
-                if (store) out[0][ci] = nu0;
+                if (store) st_nt(&out[0][ci], nu0);
                 eL = pr(u[T2XM], nu0);
                 Qn[0] = pr(u[T2XP], nu0);
                 Qn[3] = pr(u[T2YP], nu0);
@@ -662,7 +679,7 @@ __global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPt
 #pragma unroll
                 for (int q = 0; q < 4; ++q) u[q] = lk[4 + q][ci];
                 const C nu1 = update(in[1][ci], u_row1(u, v1xp, v1c, v0n, v0c, rx, ry), coef(1, 0, ci));
-                if (store) out[1][ci] = nu1;
+                if (store) st_nt(&out[1][ci], nu1);
                 eR = pr(u[T2XP], nu1);
                 Qn[1] = pr(u[T2YM], nu1);
                 Qn[2] = pr(u[T2XM], nu1);
@@ -677,8 +694,8 @@ __global__ __launch_bounds__(TW + 64) void k2_fused_links(FusedArgs<R> a, LinkPt
             const C T[8] = {e[0][li + 1], Q[0], Q[1], up2, Q[2], e[1][li - 1], dn, Q[3]};
             const St2<C> s = v_rows(T, rx, ry);
             const Coef<R> k2 = coef(2, 3, cm), k3 = coef(3, 3, cm);   // both loads before the stores
-            out[2][cm] = update(v0m, s.s0, k2);
-            out[3][cm] = update(v1m, s.s1, k3);
+            st_nt(&out[2][cm], update(v0m, s.s0, k2));
+            st_nt(&out[3][cm], update(v1m, s.s1, k3));
         }
         __syncthreads();
         v0m = v0c;

@@ -4,6 +4,7 @@
 #include "device.h"
 #include "internal.h"
 #include "stencil3.h"
+#include "ntstore.h"
 
 namespace dirac {
 
@@ -45,13 +46,21 @@ __global__ __launch_bounds__(256) void k2_half(HalfArgs<R> a) {
     if constexpr (WHICH == 0) {
         St2<C> s = stencil_u<C, R>(a.rx, a.ry, f[2][c], ld_or0(f[2], xm, oxm), ld_or0(f[2], yp, oyp), f[3][c],
                                    ld_or0(f[3], ym, oym), ld_or0(f[3], xp, oxp));
-        f[0][c] = update(f[0][c], s.s0, coef2<R, SITE>(a, 0, 0, c));
-        f[1][c] = update(f[1][c], s.s1, coef2<R, SITE>(a, 1, 0, c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o0 = f[0][c], o1 = f[1][c];
+        const Coef<R> k0 = coef2<R, SITE>(a, 0, 0, c), k1 = coef2<R, SITE>(a, 1, 0, c);
+        st_nt(&f[0][c], update(o0, s.s0, k0));
+        st_nt(&f[1][c], update(o1, s.s1, k1));
     } else {
         St2<C> s = stencil_v<C, R>(a.rx, a.ry, f[0][c], ld_or0(f[0], xp, oxp), ld_or0(f[0], yp, oyp), f[1][c],
                                    ld_or0(f[1], ym, oym), ld_or0(f[1], xm, oxm));
-        f[2][c] = update(f[2][c], s.s0, coef2<R, SITE>(a, 2, 3, c));
-        f[3][c] = update(f[3][c], s.s1, coef2<R, SITE>(a, 3, 3, c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o2 = f[2][c], o3 = f[3][c];
+        const Coef<R> k2 = coef2<R, SITE>(a, 2, 3, c), k3 = coef2<R, SITE>(a, 3, 3, c);
+        st_nt(&f[2][c], update(o2, s.s0, k2));
+        st_nt(&f[3][c], update(o3, s.s1, k3));
     }
 }
 

@@ -17,6 +17,7 @@
 #include "internal.h"
 #include "norm3.h"
 #include "stencil3.h"
+#include "ntstore.h"
 
 namespace dirac {
 
@@ -78,20 +79,28 @@ __global__ __launch_bounds__(256) void k3_half(HalfArgs<R> a) {
                                      f[5][c], ld_or0(f[5], zm, ozm), ld_or0(f[5], ym, oym), ld_or0(f[5], xm, oxm),
                                      f[6][c], ld_or0(f[6], xm, oxm), ld_or0(f[6], yp, oyp), ld_or0(f[6], zp, ozp),
                                      f[7][c], ld_or0(f[7], ym, oym), ld_or0(f[7], xp, oxp), ld_or0(f[7], zp, ozp));
-        f[0][c] = update(f[0][c], s.s0, coef_at<R, SITE>(a, 0, 0, k, c));
-        f[1][c] = update(f[1][c], s.s1, coef_at<R, SITE>(a, 1, 0, k, c));
-        f[2][c] = update(f[2][c], s.s2, coef_at<R, SITE>(a, 2, 1, k, c));
-        f[3][c] = update(f[3][c], s.s3, coef_at<R, SITE>(a, 3, 1, k, c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o0 = f[0][c], o1 = f[1][c], o2 = f[2][c], o3 = f[3][c];
+        const Coef<R> k0 = coef_at<R, SITE>(a, 0, 0, k, c), k1 = coef_at<R, SITE>(a, 1, 0, k, c), k2 = coef_at<R, SITE>(a, 2, 1, k, c), k3 = coef_at<R, SITE>(a, 3, 1, k, c);
+        st_nt(&f[0][c], update(o0, s.s0, k0));
+        st_nt(&f[1][c], update(o1, s.s1, k1));
+        st_nt(&f[2][c], update(o2, s.s2, k2));
+        st_nt(&f[3][c], update(o3, s.s3, k3));
     } else {
         St3<C> s = stencil_cd<C, R>(a.rx, a.ry, a.rz,
                                      f[0][c], ld_or0(f[0], zp, ozp), ld_or0(f[0], xp, oxp), ld_or0(f[0], yp, oyp),
                                      f[1][c], ld_or0(f[1], zp, ozp), ld_or0(f[1], xm, oxm), ld_or0(f[1], ym, oym),
                                      f[2][c], ld_or0(f[2], zm, ozm), ld_or0(f[2], xm, oxm), ld_or0(f[2], yp, oyp),
                                      f[3][c], ld_or0(f[3], zm, ozm), ld_or0(f[3], xp, oxp), ld_or0(f[3], ym, oym));
-        f[4][c] = update(f[4][c], s.s0, coef_at<R, SITE>(a, 4, 2, k, c));
-        f[5][c] = update(f[5][c], s.s1, coef_at<R, SITE>(a, 5, 2, k, c));
-        f[6][c] = update(f[6][c], s.s2, coef_at<R, SITE>(a, 6, 3, k, c));
-        f[7][c] = update(f[7][c], s.s3, coef_at<R, SITE>(a, 7, 3, k, c));
+        // old values and coefficients before the first store: a load issued after a
+        // store would wait for it too
+        const C o4 = f[4][c], o5 = f[5][c], o6 = f[6][c], o7 = f[7][c];
+        const Coef<R> k4 = coef_at<R, SITE>(a, 4, 2, k, c), k5 = coef_at<R, SITE>(a, 5, 2, k, c), k6 = coef_at<R, SITE>(a, 6, 3, k, c), k7 = coef_at<R, SITE>(a, 7, 3, k, c);
+        st_nt(&f[4][c], update(o4, s.s0, k4));
+        st_nt(&f[5][c], update(o5, s.s1, k5));
+        st_nt(&f[6][c], update(o6, s.s2, k6));
+        st_nt(&f[7][c], update(o7, s.s3, k7));
     }
 }
 
