@@ -243,8 +243,10 @@ __global__ __launch_bounds__(NormTile<R>::TW *NormTile<R>::TY) void k3_norm_lds(
 // row by the conjugate of the factor stored at the A,B end of the half-link.
 // The amplitudes are staged as above (the link rows read the same neighbours on
 // the same sides).  Each cell loads its own 24 factors, and the 8 factors of
-// its x and y neighbours that its C,D rows need, straight from global memory;
-// they are read by no other cell's rows, so staging them would save nothing.
+// its x and y neighbours that its C,D rows need, straight from global memory:
+// a factor is read by at most two cells, its own and one x or y neighbour,
+// mostly in the same workgroup and plane, so the second read finds it in the
+// caches and staging would save little.
 // Across the plane boundary: S_B0 and S_B1 keep their x-y part, their +z factor
 // and their -z coupling, and take D at k+1 at the next plane; S_C0 and S_C1
 // keep their x-y part and their -z coupling and take the next plane's A times
